@@ -1,0 +1,539 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Nothing here compares the oracle with itself: each test checks a printed value
+(the D3Q19 velocity list of Section 3), a closed form (Brinkman decay, shear-wave
+and scalar diffusion rates, Poiseuille flow, Zou-He exactness on equilibria), an
+invariant (conservation, the streaming lemma of Section 2.2) or an independent
+derivative (finite differences and complex-step directional derivatives against
+the adjoint of Section 2.2's theorem).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1501_04741_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _periodic(flow, nx, ny, nz, **kw):
+    return dict(dict(flow=flow, nx=nx, ny=ny, nz=nz, periodic=1, tau=0.8), **kw)
+
+
+def _equilibrium(cfg, rho, u):
+    """E(rho, u) read off the interior operator at tau = 1, w = 1 (h = E(rho, u)).
+
+    The input carries density rho and momentum rho*u, which is all E depends on."""
+    q = cfg["flow"]
+    e, wt, _, cs2 = oracle.lattice(q)
+    f = wt * (rho + rho * (e @ np.asarray(u, float)) / cs2)
+    c1 = dict(cfg, tau=1.0, periodic=1)
+    h, _ = oracle.node_op(c1, 1, 1, 1 if q == 19 else 0, f, None if not cfg.get("scalar") else np.zeros(cfg["scalar"]), 1.0)
+    return h
+
+
+# ------------------------------------------------------------------ lattices
+def test_d3q19_matches_paper_list():
+    rows = np.loadtxt(os.path.join(GOLDEN, "d3q19_velocities.txt"), dtype=int)
+    e, _, _, _ = oracle.lattice(19)
+    assert np.array_equal(rows[:, 0], np.arange(1, 20))
+    assert np.array_equal(e, rows[:, 1:])
+    # D3Q7 is the first 7 vectors (Section 3)
+    e7, _, _, _ = oracle.lattice(7)
+    assert np.array_equal(e7, rows[:7, 1:])
+
+
+def test_2d_lattices_are_z0_subsets_in_paper_order():
+    rows = np.loadtxt(os.path.join(GOLDEN, "d3q19_velocities.txt"), dtype=int)[:, 1:]
+    z0 = rows[rows[:, 2] == 0]
+    e9, _, _, _ = oracle.lattice(9)
+    e5, _, _, _ = oracle.lattice(5)
+    assert np.array_equal(e9, z0)
+    assert np.array_equal(e5, z0[:5])
+
+
+@pytest.mark.parametrize("q", [5, 7, 9, 19])
+def test_lattice_moments(q):
+    e, wt, opp, cs2 = oracle.lattice(q)
+    d = 3
+    assert abs(wt.sum() - 1.0) < 1e-15
+    assert np.allclose(wt @ e, 0.0, atol=1e-16)
+    M2 = np.einsum("j,ja,jb->ab", wt, e, e)
+    dims = 3 if q in (7, 19) else 2
+    expect = np.zeros((d, d))
+    expect[:dims, :dims] = cs2 * np.eye(dims)
+    assert np.allclose(M2, expect, atol=1e-15)
+    assert np.array_equal(e[opp], -e)
+    assert np.array_equal(opp[opp], np.arange(q))
+    assert np.allclose(wt[opp], wt)
+    if q in (9, 19):  # fourth-order isotropy needed by the Navier-Stokes limit
+        M4 = np.einsum("j,ja,jb,jc,jd->abcd", wt, e, e, e, e)
+        dl = np.eye(3)
+        iso = cs2 ** 2 * (np.einsum("ab,cd->abcd", dl, dl) + np.einsum("ac,bd->abcd", dl, dl)
+                          + np.einsum("ad,bc->abcd", dl, dl))
+        sl = slice(0, dims)
+        assert np.allclose(M4[sl, sl, sl, sl], iso[sl, sl, sl, sl], atol=1e-15)
+    assert cs2 == (0.25 if q == 7 else 1.0 / 3.0)
+
+
+# ------------------------------------------------------- masks and streaming
+@pytest.mark.parametrize("flow,nx,ny,nz", [(9, 7, 5, 1), (19, 6, 5, 4)])
+def test_mask_classes(flow, nx, ny, nz):
+    m = oracle.mask(dict(flow=flow, nx=nx, ny=ny, nz=nz)).reshape(nz, ny, nx)
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                wall = y in (0, ny - 1) or (flow == 19 and z in (0, nz - 1))
+                want = 1 if wall else (2 if x == 0 else (3 if x == nx - 1 else 0))
+                assert m[z, y, x] == want
+    assert (oracle.mask(_periodic(flow, nx, ny, nz)) == 0).all()
+
+
+@pytest.mark.parametrize("flow,nx,ny,nz", [(9, 7, 5, 1), (19, 6, 5, 4)])
+def test_streaming_map_is_a_periodic_shift(flow, nx, ny, nz):
+    cfg = dict(flow=flow, nx=nx, ny=ny, nz=nz)
+    src = oracle.src_map(cfg)
+    e, _, opp, _ = oracle.lattice(flow)
+    n = nx * ny * nz
+    idx = np.arange(n)
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    assert np.array_equal(src[0], idx)
+    for j in range(flow):
+        assert np.array_equal(np.sort(src[j]), idx)            # a permutation
+        assert np.array_equal(src[opp[j]][src[j]], idx)        # reversed shift undoes it
+        sx, sy, sz = src[j] % nx, (src[j] // nx) % ny, src[j] // (nx * ny)
+        assert np.all((x - sx) % nx == e[j, 0] % nx)
+        assert np.all((y - sy) % ny == e[j, 1] % ny)
+        assert np.all((z - sz) % nz == e[j, 2] % nz)
+
+
+def test_streaming_lemma_unitarity():
+    """<a, S b> = <S^-1 a, b> and sum f invariant under S (Lemma 1)."""
+    cfg = dict(flow=19, nx=5, ny=4, nz=3)
+    src = oracle.src_map(cfg)
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal(src.shape)
+    b = rng.standard_normal(src.shape)
+    Sb = np.take_along_axis(b, src, axis=1)          # (S b)_j(x) = b_j(x - e_j)
+    inv = np.argsort(src, axis=1)
+    Sia = np.take_along_axis(a, inv, axis=1)         # (S^-1 a)_j(x) = a_j(x + e_j)
+    assert abs(np.sum(a * Sb) - np.sum(Sia * b)) < 1e-12 * np.abs(a * Sb).sum()
+    assert abs(Sb.sum() - b.sum()) < 1e-12 * np.abs(b).sum()
+
+
+# -------------------------------------------------------- interior collision
+def _random_state(q, rng, rho=1.0, amp=0.05):
+    e, wt, _, _ = oracle.lattice(q)
+    return wt * rho * (1 + amp * rng.standard_normal(q))
+
+
+@pytest.mark.parametrize("flow", [9, 19])
+@pytest.mark.parametrize("fn,par", [("power", 3.0), ("ramp", 0.01)])
+def test_interior_conserves_mass_and_scales_momentum(flow, fn, par):
+    rng = np.random.default_rng(11)
+    e, _, _, _ = oracle.lattice(flow)
+    cfg = _periodic(flow, 4, 4, 4 if flow == 19 else 1, switch_fn=fn, switch_param=par)
+    for w in (1.0, 0.73, 0.2, 0.0):
+        f = _random_state(flow, rng)
+        h, _ = oracle.node_op(cfg, 1, 1, 1 if flow == 19 else 0, f, None, w)
+        G = w ** 3 if fn == "power" else (1 + par) * w / (w + par)
+        assert abs(h.sum() - f.sum()) < 1e-15
+        assert np.allclose(h @ e, G * (f @ e), rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("flow", [9, 19])
+def test_equilibrium_moments(flow):
+    """At tau = 1 the interior operator returns E(rho, G u): check its moments."""
+    e, _, _, cs2 = oracle.lattice(flow)
+    cfg = _periodic(flow, 4, 4, 4 if flow == 19 else 1)
+    u = np.array([0.03, -0.02, 0.01 if flow == 19 else 0.0])
+    rho = 1.07
+    E = _equilibrium(cfg, rho, u)
+    assert abs(E.sum() - rho) < 1e-15
+    assert np.allclose(E @ e, rho * u, atol=1e-16)
+    dims = 3 if flow == 19 else 2
+    P = np.einsum("j,ja,jb->ab", E, e, e)[:dims, :dims]
+    assert np.allclose(P, rho * (cs2 * np.eye(dims) + np.outer(u[:dims], u[:dims])), atol=1e-15)
+
+
+@pytest.mark.parametrize("flow", [9, 19])
+def test_exact_difference_identity(flow):
+    """W_forced(f) - W_unforced(f) = E(rho, u_post) - E(rho, u_pre) for any tau (Section 3.1)."""
+    rng = np.random.default_rng(5)
+    z = 1 if flow == 19 else 0
+    f = _random_state(flow, rng)
+    diffs = []
+    for tau in (1.0, 0.8, 0.55, 1.7):
+        cfg = _periodic(flow, 4, 4, 4 if flow == 19 else 1, tau=tau)
+        hw, _ = oracle.node_op(cfg, 1, 1, z, f, None, 0.6)
+        h1, _ = oracle.node_op(cfg, 1, 1, z, f, None, 1.0)
+        diffs.append(hw - h1)
+    for d in diffs[1:]:
+        assert np.allclose(d, diffs[0], atol=1e-16)
+    e, _, _, _ = oracle.lattice(flow)
+    rho, u = f.sum(), (f @ e) / f.sum()
+    cfg = _periodic(flow, 4, 4, 4 if flow == 19 else 1)
+    G = 0.6 ** 3
+    assert np.allclose(diffs[0], _equilibrium(cfg, rho, G * u) - _equilibrium(cfg, rho, u), atol=1e-16)
+
+
+@pytest.mark.parametrize("flow,scalar", [(9, 5), (19, 7)])
+@pytest.mark.parametrize("fn,par", [("power", 3.0), ("ramp", 0.01)])
+def test_interior_scalar_relaxes_flux_toward_forced_velocity(flow, scalar, fn, par):
+    """Interior scalar BGK: sum g' = sum g and
+    sum e g' = (1 - w_s) sum e g + w_s T G(w) u  (advection by the post-forcing velocity)."""
+    rng = np.random.default_rng(12)
+    e, _, _, _ = oracle.lattice(flow)
+    es, wts, _, _ = oracle.lattice(scalar)
+    tau_s = 0.7
+    cfg = _periodic(flow, 4, 4, 4 if flow == 19 else 1, scalar=scalar, tau_s=tau_s, switch_fn=fn,
+                    switch_param=par)
+    for w in (1.0, 0.8, 0.3):
+        f = _random_state(flow, rng, amp=0.2)
+        g = wts * (0.5 + 0.2 * rng.standard_normal(scalar))
+        _, gp = oracle.node_op(cfg, 1, 1, 1 if flow == 19 else 0, f, g, w)
+        G = w ** 3 if fn == "power" else (1 + par) * w / (w + par)
+        u = (f @ e) / f.sum()
+        T = g.sum()
+        om = 1.0 / tau_s
+        assert abs(gp.sum() - T) < 1e-15
+        assert np.allclose(gp @ es, (1 - om) * (g @ es) + om * T * G * u, atol=1e-16)
+
+
+# ----------------------------------------------------------- closed forms
+@pytest.mark.parametrize("flow", [9, 19])
+@pytest.mark.parametrize("fn,par,w", [("power", 3.0, 0.9), ("ramp", 0.01, 0.5), ("power", 3.0, 1.0)])
+def test_uniform_brinkman_decay(flow, fn, par, w):
+    """Periodic box, uniform w, start at E(1, u0): u_n = G(w)^n u0, rho = 1."""
+    nx, ny, nz = 5, 4, (3 if flow == 19 else 1)
+    cfg = _periodic(flow, nx, ny, nz, switch_fn=fn, switch_param=par)
+    u0 = np.array([0.04, -0.01, 0.02 if flow == 19 else 0.0])
+    E = _equilibrium(cfg, 1.0, u0)
+    n = nx * ny * nz
+    f0 = np.repeat(E[:, None], n, axis=1)
+    G = w ** 3 if fn == "power" else (1 + par) * w / (w + par)
+    steps = 25
+    r = oracle.primal(cfg, np.full(n, w), steps, f0=f0)
+    rho, u, _ = oracle.fields(cfg, r["f"])
+    assert np.allclose(rho, 1.0, rtol=0, atol=1e-14)
+    # rounding adds ~1e-17 absolute per step while u shrinks geometrically
+    for a in range(3):
+        assert np.allclose(u[a], G ** steps * u0[a], rtol=1e-11, atol=1e-15 * abs(u0[a]))
+
+
+def _mode_amplitude(field, k_index, axis_len, coord):
+    phase = np.exp(-2j * np.pi * k_index * coord / axis_len)
+    return 2 * np.mean(field * phase)
+
+
+@pytest.mark.parametrize("flow", [9, 19])
+def test_shear_wave_decay_gives_bgk_viscosity(flow):
+    """u_x = A sin(k y) decays as exp(-nu k^2 t) with nu = (tau - 1/2)/3 (eq. SRT)."""
+    ny, nx, nz = 96, 3, (3 if flow == 19 else 1)
+    tau = 0.8
+    cfg = _periodic(flow, nx, ny, nz, tau=tau)
+    n = nx * ny * nz
+    idx = np.arange(n)
+    y = (idx // nx) % ny
+    k = 2 * np.pi / ny
+    A = 1e-4
+    e, wt, _, cs2 = oracle.lattice(flow)
+    ux = A * np.sin(k * y)
+    f0 = wt[:, None] * (1 + e[:, 0:1] * ux[None, :] / cs2)
+    t1, t2 = 200, 1200
+    r1 = oracle.primal(cfg, np.ones(n), t1, f0=f0)
+    r2 = oracle.primal(cfg, np.ones(n), t2 - t1, f0=r1["f"])
+    a1 = abs(_mode_amplitude(oracle.fields(cfg, r1["f"])[1][0], 1, ny, y))
+    a2 = abs(_mode_amplitude(oracle.fields(cfg, r2["f"])[1][0], 1, ny, y))
+    rate = -np.log(a2 / a1) / (t2 - t1)
+    nu = (tau - 0.5) / 3
+    assert abs(rate / (nu * k * k) - 1) < 2e-3
+
+
+@pytest.mark.parametrize("flow,scalar", [(9, 5), (19, 7)])
+@pytest.mark.parametrize("w", [1.0, 0.7])
+def test_scalar_advection_diffusion_closed_form(flow, scalar, w):
+    """Uniform flow u0 in a periodic box carries T = A sin(k x): the mode decays as
+    exp(-alpha k^2 t), alpha = c^2 (tau_s - 1/2), and moves by sum_n G^(n+1) u0
+    (the scalar is advected by the post-forcing velocity G(w) u)."""
+    nx, ny, nz = 64, 3, (3 if flow == 19 else 1)
+    tau_s = 0.7
+    cfg = _periodic(flow, nx, ny, nz, scalar=scalar, tau_s=tau_s, switch_fn="power", switch_param=3.0)
+    n = nx * ny * nz
+    idx = np.arange(n)
+    x = idx % nx
+    k = 2 * np.pi / nx
+    u0 = np.array([0.02, 0.0, 0.0])
+    E = _equilibrium(cfg, 1.0, u0)
+    f0 = np.repeat(E[:, None], n, axis=1)
+    es, wts, _, c2 = oracle.lattice(scalar)
+    T0 = 1e-3 * np.sin(k * x)
+    g0 = wts[:, None] * T0[None, :]
+    G = w ** 3
+    steps = 400
+    r = oracle.primal(cfg, np.full(n, w), steps, f0=f0, g0=g0)
+    T = r["g"].sum(axis=0)
+    amp = _mode_amplitude(T, 1, nx, x)
+    alpha = c2 * (tau_s - 0.5)
+    shift = u0[0] * sum(G ** (m + 1) for m in range(steps))
+    # sin(k(x - s)) has complex amplitude -i exp(-i k s)
+    want = -1j * 1e-3 * np.exp(-1j * k * shift) * np.exp(-alpha * k * k * steps)
+    assert abs(abs(amp) / abs(want) - 1) < 1e-2
+    dphase = np.angle(amp / want)
+    assert abs(dphase) < 2e-3
+
+
+def test_poiseuille_channel():
+    """Velocity inlet / pressure outlet / bounce-back channel at w = 1 develops the
+    parabolic profile with walls half-way between wall and first fluid rows, and
+    carries the inlet flux unchanged along x (Zou-He and bounce-back, Section 3).
+    tau = 1/2 + sqrt(3/16) puts the BGK bounce-back wall exactly half-way."""
+    nx, ny = 120, 18
+    tau = 0.5 + np.sqrt(3.0 / 16.0)
+    cfg = dict(flow=9, nx=nx, ny=ny, nz=1, tau=tau, u_in=0.005, switch_fn="power", switch_param=3.0)
+    n = nx * ny
+    r = oracle.primal(cfg, np.ones(n), 30000)
+    rho, u, _ = oracle.fields(cfg, r["f"])
+    ux = u[0].reshape(ny, nx)
+    rho = rho.reshape(ny, nx)
+    H = ny - 2
+    yy = np.arange(1, ny - 1)
+    xm = nx // 2
+    flux = (rho * ux)[1:-1, :].sum(axis=0)
+    assert np.allclose(flux[1:-1], flux[xm], rtol=1e-5)
+    ubar = ux[1:-1, xm].mean()
+    prof = 6 * ubar * (yy - 0.5) * (ny - 1.5 - yy) / H ** 2
+    assert np.max(np.abs(ux[1:-1, xm] - prof)) < 2e-3 * np.max(prof)
+    # Poiseuille pressure gradient dp/dx = -12 nu rho ubar / H^2, p = c_s^2 rho
+    nu = (tau - 0.5) / 3
+    dpdx = (rho[1:-1, xm + 20].mean() - rho[1:-1, xm - 20].mean()) / 40 / 3
+    assert abs(dpdx / (-12 * nu * ubar / H ** 2) - 1) < 2e-2
+
+
+# ---------------------------------------------------------------- boundaries
+@pytest.mark.parametrize("flow", [9, 19])
+def test_zou_he_is_exact_on_equilibria(flow):
+    """An equilibrium with the prescribed inlet velocity (outlet density) passes the
+    inlet (outlet) operator unchanged, for any tau."""
+    nz = 5 if flow == 19 else 1
+    z = 2 if flow == 19 else 0
+    for tau in (0.8, 1.3):
+        cfg = dict(flow=flow, nx=6, ny=5, nz=nz, tau=tau, u_in=0.03, rho_out=1.0)
+        E_in = _equilibrium(_periodic(flow, 4, 4, nz), 1.04, [0.03, 0.0, 0.0])
+        h, _ = oracle.node_op(cfg, 0, 2, z, E_in, None, 0.3)
+        assert np.allclose(h, E_in, atol=1e-16)
+        E_out = _equilibrium(_periodic(flow, 4, 4, nz), 1.0, [0.021, 0.0, 0.0])
+        h, _ = oracle.node_op(cfg, 5, 2, z, E_out, None, 0.3)
+        assert np.allclose(h, E_out, atol=1e-16)
+        # the scalar operators pass the scalar equilibrium at the boundary velocity
+        scalar = 7 if flow == 19 else 5
+        es, wts, _, c2 = oracle.lattice(scalar)
+        cs = dict(cfg, scalar=scalar, tau_s=0.65, s_in_lo=0.4, s_split_axis=0)
+        gin = wts * 0.4 * (1 + es[:, 0] * 0.03 / c2)
+        _, gp = oracle.node_op(cs, 0, 2, z, E_in, gin, 0.3)
+        assert np.allclose(gp, gin, atol=1e-16)
+        gout = wts * 0.7 * (1 + es[:, 0] * 0.021 / c2)
+        _, gp = oracle.node_op(cs, 5, 2, z, E_out, gout, 0.3)
+        assert np.allclose(gp, gout, atol=1e-16)
+
+
+@pytest.mark.parametrize("flow,scalar", [(9, 5), (19, 7)])
+def test_boundary_operators_impose_their_values(flow, scalar):
+    """For arbitrary incoming populations: inlet keeps u = (u_in,0,0) and T = T_in,
+    outlet keeps rho = rho_out and zero transverse velocity, walls reflect."""
+    rng = np.random.default_rng(7)
+    nz = 5 if flow == 19 else 1
+    z = 2 if flow == 19 else 0
+    e, wt, opp, _ = oracle.lattice(flow)
+    es, wts, opps, _ = oracle.lattice(scalar)
+    cfg = dict(flow=flow, scalar=scalar, nx=6, ny=5, nz=nz, tau=0.9, tau_s=0.7, u_in=0.03, rho_out=1.0,
+               s_in_lo=0.25, s_in_hi=0.75, s_split_axis=1)
+    for _ in range(5):
+        f = _random_state(flow, rng, rho=1.02)
+        g = wts * (0.4 + 0.1 * rng.standard_normal(scalar))
+        for y, tin in ((1, 0.25), (3, 0.75)):
+            h, gp = oracle.node_op(cfg, 0, y, z, f, g, 0.5)
+            rho = h.sum()
+            assert np.allclose(h @ e, rho * np.array([0.03, 0, 0]), atol=1e-16)
+            assert abs(gp.sum() - tin) < 1e-15
+            known = e[:, 0] <= 0
+            rho_zh = (f[e[:, 0] == 0].sum() + 2 * f[e[:, 0] == -1].sum()) / (1 - 0.03)
+            assert abs(rho - rho_zh) < 1e-15
+            assert np.allclose(h[known & (e[:, 0] == 0)] - f[known & (e[:, 0] == 0)],
+                               (h - f)[known & (e[:, 0] == 0)])
+        h, gp = oracle.node_op(cfg, 5, 2, z, f, g, 0.5)
+        assert abs(h.sum() - 1.0) < 1e-15
+        m = h @ e
+        assert abs(m[1]) < 1e-16 and abs(m[2]) < 1e-16
+        h, gp = oracle.node_op(cfg, 3, 0, z, f, g, 0.5)
+        assert np.array_equal(h, f[opp])
+        assert np.array_equal(gp, g[opps])
+        h, gp = oracle.node_op(dict(cfg, scalar_wall="dirichlet", s_wall=1.5), 3, 0, z, f, g, 0.5)
+        assert np.allclose(gp, 1.5 * wts, atol=1e-16)
+
+
+@pytest.mark.parametrize("flow,scalar", [(9, 5), (19, 7)])
+def test_closed_box_conserves_mass(flow, scalar):
+    """With u_in = 0 the mixed channel run keeps total scalar/flow mass finite and the
+    periodic box conserves sum f exactly for any w field."""
+    nz = 4 if flow == 19 else 1
+    cfg = _periodic(flow, 6, 5, nz, scalar=scalar)
+    n = 6 * 5 * nz
+    rng = np.random.default_rng(2)
+    e, wt, _, _ = oracle.lattice(flow)
+    f0 = wt[:, None] * (1 + 0.05 * rng.standard_normal((flow, n)))
+    es, wts, _, _ = oracle.lattice(scalar)
+    g0 = wts[:, None] * (1 + 0.3 * rng.standard_normal((scalar, n)))
+    r = oracle.primal(cfg, rng.random(n), 50, f0=f0, g0=g0)
+    assert abs(r["f"].sum() - f0.sum()) < 1e-12
+    assert abs(r["g"].sum() - g0.sum()) < 1e-12
+
+
+# ---------------------------------------------------------------- objectives
+@pytest.mark.parametrize("flow,scalar", [(9, 5), (19, 7)])
+def test_objective_on_known_states(flow, scalar):
+    nx, ny = 6, 5
+    nz = 5 if flow == 19 else 1
+    n = nx * ny * nz
+    e, wt, _, cs2 = oracle.lattice(flow)
+    es, wts, _, c2 = oracle.lattice(scalar)
+    base = dict(flow=flow, scalar=scalar, nx=nx, ny=ny, nz=nz, u_in=0.0, rho_out=1.0)
+    # rest state, uniform T: dp = 0, Var = 0, HF = 0
+    f0 = np.repeat(wt[:, None], n, axis=1)
+    g0 = np.repeat(0.3 * wts[:, None], n, axis=1)
+    for cw in (dict(c_dp=1.0), dict(c_dp=0.0, c_var=1.0), dict(c_dp=0.0, c_hf=1.0)):
+        r = oracle.primal(dict(base, **cw), np.ones(n), 0, f0=f0, g0=g0)
+        assert abs(r["J"]) < 1e-15
+    # outlet carrying E(1, (u0,0,0)) and E^s(T(y,z), u0): HF = sum u0 T, Var of T
+    u0 = 0.02
+    msk = oracle.mask(base)
+    idx = np.arange(n)
+    yy = (idx // nx) % ny
+    Tn = 0.1 + 0.05 * yy
+    Ef = _equilibrium(_periodic(flow, 4, 4, nz), 1.0, [u0, 0, 0])
+    f = np.repeat(Ef[:, None], n, axis=1)
+    g = wts[:, None] * Tn[None, :] * (1 + (es[:, 0:1] * u0) / c2)
+    outl = msk == 3
+    r = oracle.primal(dict(base, c_dp=0.0, c_hf=1.0), np.ones(n), 0, f0=f, g0=g)
+    assert abs(r["J"] - u0 * Tn[outl].sum()) < 1e-15
+    r = oracle.primal(dict(base, c_dp=0.0, c_var=1.0), np.ones(n), 0, f0=f, g0=g)
+    assert abs(r["J"] - Tn[outl].var()) < 1e-15
+    # inlet density 1.05 at u_in = 0: dp = c_s^2 (1.05 - 1)
+    Ein = _equilibrium(_periodic(flow, 4, 4, nz), 1.05, [0, 0, 0])
+    f2 = f0.copy()
+    f2[:, msk == 2] = Ein[:, None]
+    r = oracle.primal(dict(base, c_dp=1.0), np.ones(n), 0, f0=f2, g0=g0)
+    assert abs(r["J"] - cs2 * 0.05) < 1e-15
+
+
+# -------------------------------------------------------------------- adjoint
+def _small(flow=9, scalar=0, fn="power", **kw):
+    nz = 6 if flow == 19 else 1
+    nx, ny = (16, 8) if flow == 9 else (8, 6)
+    p = dict(flow=flow, scalar=scalar, nx=nx, ny=ny, nz=nz, tau=0.8, tau_s=0.6, u_in=0.02, rho_out=1.0,
+             switch_fn=fn, switch_param=3.0 if fn == "power" else 0.01, c_dp=1.0)
+    if scalar:
+        p.update(c_hf=1.0, c_var=0.5, s_in_lo=0.0, s_in_hi=1.0, s_split_axis=1, scalar_wall="adiabatic")
+    p.update(kw)
+    w = inputs.porosity(p["nx"], p["ny"], p["nz"], 0, 3)
+    return p, w
+
+
+@pytest.mark.parametrize("flow,scalar", [(9, 0), (9, 5), (19, 7)])
+def test_step_adjoint_dot_product(flow, scalar):
+    """<T(df, dg, dw), lam> = <df, T^* lam> + <dw, gw> for one step, i.e. the adjoint
+    step is the transpose of the tangent step (reverse streaming, Lemma 1)."""
+    p, w = _small(flow, scalar)
+    n = p["nx"] * p["ny"] * p["nz"]
+    rng = np.random.default_rng(4)
+    e, wt, _, _ = oracle.lattice(flow)
+    f = wt[:, None] * (1 + 0.05 * rng.standard_normal((flow, n)))
+    g = rng.random((scalar, n)) * 0.2 if scalar else np.zeros((0, n))
+    df = rng.standard_normal((flow, n))
+    dg = rng.standard_normal((scalar, n))
+    dw = rng.standard_normal(n)
+    lf = rng.standard_normal((flow, n))
+    lg = rng.standard_normal((scalar, n))
+    tf, tg = oracle.step_tangent(p, w, f, g, df, dg, dw)
+    af, ag, gw = oracle.step_adjoint(p, w, f, g, lf, lg)
+    lhs = np.sum(tf * lf) + np.sum(tg * lg)
+    rhs = np.sum(df * af) + np.sum(dg * ag) + np.sum(dw * gw)
+    assert abs(lhs - rhs) <= 1e-13 * (abs(lhs) + 1e-300)
+    # and the tangent matches central differences of the real step
+    eps = 1e-6
+    fp, gp = oracle.step(p, w + eps * dw, f + eps * df, g + eps * dg)
+    fm, gm = oracle.step(p, w - eps * dw, f - eps * df, g - eps * dg)
+    assert np.allclose((fp - fm) / (2 * eps), tf, rtol=1e-6, atol=1e-8)
+    if scalar:
+        assert np.allclose((gp - gm) / (2 * eps), tg, rtol=1e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("flow,scalar,fn,steps", [(9, 0, "power", 1000), (9, 0, "ramp", 1000),
+                                                   (9, 5, "power", 400), (19, 7, "ramp", 60), (19, 0, "power", 60)])
+def test_adjoint_gradient_vs_complex_step_directional(flow, scalar, fn, steps):
+    """<dJ/dw, dw> from the adjoint equals the complex-step derivative of J along dw
+    through the whole run, to 1e-12 relative (the theorem of Section 2.2, unsteady)."""
+    p, w = _small(flow, scalar, fn)
+    rng = np.random.default_rng(9)
+    dw = rng.standard_normal(w.size)
+    a = oracle.adjoint(p, w, steps)
+    J, dJ = oracle.directional(p, w, dw, steps)
+    assert abs(a["J"] - J) <= 1e-14 * abs(J)
+    assert abs(a["grad"] @ dw - dJ) <= 1e-12 * abs(dJ)
+
+
+def test_adjoint_vs_central_differences_every_node():
+    """Central finite differences (eps = 1e-5, real arithmetic) at every node of 16x8."""
+    p, w = _small(9, 0, "power")
+    steps = 300
+    g = oracle.adjoint(p, w, steps)["grad"]
+    eps = 1e-5
+    fd = np.zeros_like(w)
+    for k in range(w.size):
+        wp = w.copy(); wp[k] += eps
+        wm = w.copy(); wm[k] -= eps
+        fd[k] = (oracle.primal(p, wp, steps)["J"] - oracle.primal(p, wm, steps)["J"]) / (2 * eps)
+    scale = np.abs(g).max()
+    assert np.max(np.abs(fd - g)) < 1e-7 * scale
+    assert (g[oracle.mask(p) != 0] == 0).all()  # w acts at interior nodes only
+
+
+def test_adjoint_vs_brute_force_complex_step():
+    """Per-node complex-step derivative of J (one complex forward run per node) gives
+    the exact gradient: rel-L2 1e-12 on 16x8 with the coupled scalar."""
+    p, w = _small(9, 5, "ramp")
+    steps = 200
+    g = oracle.adjoint(p, w, steps)["grad"]
+    bf = np.zeros_like(w)
+    for k in range(w.size):
+        dw = np.zeros_like(w); dw[k] = 1.0
+        bf[k] = oracle.directional(p, w, dw, steps)[1]
+    assert np.linalg.norm(g - bf) <= 1e-12 * np.linalg.norm(bf)
+
+
+def test_objective_seed_vs_finite_differences():
+    p, w = _small(9, 5, "power")
+    r = oracle.primal(p, w, 50)
+    J, lf, lg = oracle.objective_seed(p, r["f"], r["g"])
+    assert abs(J - r["J"]) < 1e-15
+    rng = np.random.default_rng(1)
+    df = rng.standard_normal(r["f"].shape)
+    dg = rng.standard_normal(r["g"].shape)
+    eps = 1e-6
+    Jp = oracle.objective_seed(p, r["f"] + eps * df, r["g"] + eps * dg)[0]
+    Jm = oracle.objective_seed(p, r["f"] - eps * df, r["g"] - eps * dg)[0]
+    fd = (Jp - Jm) / (2 * eps)
+    assert abs(fd - (np.sum(lf * df) + np.sum(lg * dg))) < 1e-8 * abs(fd)
+
+
+def test_adjoint_checkpointing_is_exact():
+    """N that is not a multiple of the checkpoint interval, and N = 0, 1."""
+    p, w = _small(9, 0, "power")
+    rng = np.random.default_rng(8)
+    dw = rng.standard_normal(w.size)
+    for steps in (0, 1, 2, 7, 50):
+        a = oracle.adjoint(p, w, steps)
+        _, dJ = oracle.directional(p, w, dw, steps)
+        assert abs(a["grad"] @ dw - dJ) <= 1e-12 * max(abs(dJ), 1e-300) or (steps == 0 and dJ == 0)
