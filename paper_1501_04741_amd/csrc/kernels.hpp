@@ -1,0 +1,836 @@
+// gfx950 kernels of the adjoint lattice-Boltzmann hot path.
+//
+// Data layout (HBM): a state is Qt = Q + QS planes of N values, population j
+// of node n = x + nx*(y + ny*z) at j*N + n.  Stored flow populations are
+// shifted by their lattice weight (f~_j = f_j - w_j) so that FP32 keeps the
+// small deviations from rest at full relative precision; the scalar is stored
+// as is.  The primal buffers hold POST-collision states h^k; the pre-collision
+// state of step k+1 is pulled, f^{k+1}_j(x) = h^k_j(x - e_j) (Section 2.1).
+//
+// Launch geometry (all node kernels): block = BX threads along x, grid =
+// (ceil(nx/BX), ny, nz).  y and z are block-uniform, so wall rows are decided
+// per block and every x-shift in the pull stays inside the row the block
+// owns: each fetched cache line of a source row is consumed by one block.
+//
+// Each node is owned by exactly one thread; there are no atomics, and every
+// reduction runs in a fixed order, so results are bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lattice.hpp"
+
+namespace lbmk {
+
+enum : int { INTERIOR = 0, WALL = 1, INLET = 2, OUTLET = 3 };
+enum : int { G_POWER = 0, G_RAMP = 1 };
+enum : int { S_ADIABATIC = 0, S_DIRICHLET = 1 };
+
+// Per-context parameters, passed by value to every kernel.
+template <typename Real>
+struct Params {
+  int nx, ny, nz, periodic;
+  int N;                    // nodes (Qt*N < 2^31 is enforced on the host)
+  int scalar_wall, split_axis, switch_fn;
+  int theta_int;            // POWER with integer theta: theta, else -1
+  Real om, oms;             // 1/tau, 1/tau_s
+  Real u_in, rho_out;
+  Real s_wall, s_in_lo, s_in_hi;
+  Real sw_param;            // theta (POWER) or q (RAMP)
+  double c_dp, c_hf, c_var; // objective weights
+};
+
+template <typename P>
+__device__ __forceinline__ int node_class(const P& p, int x, int y, int z, bool is3d) {
+  if (p.periodic) return INTERIOR;
+  if (y == 0 || y == p.ny - 1) return WALL;
+  if (is3d && (z == 0 || z == p.nz - 1)) return WALL;
+  if (x == 0) return INLET;
+  if (x == p.nx - 1) return OUTLET;
+  return INTERIOR;
+}
+
+// Wrapped neighbour coordinates: X[s+1] = (x+s) mod nx, Y[s+1] = nx*((y+s) mod ny),
+// Z[s+1] = nx*ny*((z+s) mod nz) for s in {-1, 0, +1}.
+struct Nbr {
+  int X[3], Y[3], Z[3];
+};
+
+template <typename P>
+__device__ __forceinline__ Nbr make_nbr(const P& p, int x, int y, int z) {
+  Nbr b;
+  b.X[0] = (x == 0) ? p.nx - 1 : x - 1;
+  b.X[1] = x;
+  b.X[2] = (x == p.nx - 1) ? 0 : x + 1;
+  const int ym = (y == 0) ? p.ny - 1 : y - 1, yp = (y == p.ny - 1) ? 0 : y + 1;
+  b.Y[0] = ym * p.nx;
+  b.Y[1] = y * p.nx;
+  b.Y[2] = yp * p.nx;
+  const int plane = p.nx * p.ny;
+  const int zm = (z == 0) ? p.nz - 1 : z - 1, zp = (z == p.nz - 1) ? 0 : z + 1;
+  b.Z[0] = zm * plane;
+  b.Z[1] = z * plane;
+  b.Z[2] = zp * plane;
+  return b;
+}
+
+// Pull source of a population with velocity (ex,ey,ez): node x - e.
+__device__ __forceinline__ int pull_idx(const Nbr& b, int ex, int ey, int ez) {
+  return b.X[1 - ex] + b.Y[1 - ey] + b.Z[1 - ez];
+}
+// Reverse pull (adjoint streaming S^{-1}): node x + e.
+__device__ __forceinline__ int push_idx(const Nbr& b, int ex, int ey, int ez) {
+  return b.X[1 + ex] + b.Y[1 + ey] + b.Z[1 + ez];
+}
+
+template <typename Real, typename P>
+__device__ __forceinline__ Real inlet_value(const P& p, int y, int z) {
+  if (p.split_axis == 1) return (y < p.ny / 2) ? p.s_in_lo : p.s_in_hi;
+  if (p.split_axis == 2) return (z < p.nz / 2) ? p.s_in_lo : p.s_in_hi;
+  return p.s_in_lo;
+}
+
+// Switching function G(w) and its derivative (Darcy/Brinkman, Section 3.2).
+template <typename Real>
+__device__ __forceinline__ void switch_fn(const Params<Real>& p, Real w, Real& G, Real& dG) {
+  if (p.switch_fn == G_RAMP) {
+    const Real q = p.sw_param;
+    const Real d = w + q;
+    G = (Real(1) + q) * w / d;
+    dG = (Real(1) + q) * q / (d * d);
+  } else if (p.theta_int >= 0) {
+    Real r = Real(1), r1 = Real(1);
+    for (int k = 0; k < p.theta_int; ++k) {
+      r1 = r;
+      r = r * w;
+    }
+    G = r;
+    dG = p.theta_int > 0 ? Real(p.theta_int) * r1 : Real(0);
+  } else {
+    G = pow(w, p.sw_param);
+    dG = p.sw_param * pow(w, p.sw_param - Real(1));
+  }
+}
+
+// ------------------------------------------------------------------ loads
+template <int Q, int QS, typename Real>
+__device__ __forceinline__ void pull_state(const Real* __restrict__ src, int N, const Nbr& b, Real (&f)[Q],
+                                           Real (&g)[QS > 0 ? QS : 1]) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) f[j] = src[(size_t)j * N + pull_idx(b, L::ex(j), L::ey(j), L::ez(j))];
+#pragma unroll
+  for (int i = 0; i < QS; ++i) g[i] = src[(size_t)(Q + i) * N + pull_idx(b, S::ex(i), S::ey(i), S::ez(i))];
+}
+
+// ------------------------------------------------------- node operators
+// All operators map the shifted pre-collision populations f~ (and scalar g)
+// of one node to its shifted post-collision values in place.
+
+// Interior: h = E(rho, G u) + (1 - omega)(f - E(rho, u))   (Section 3.1 with
+// T = omega I, Section 3.2 for u_post = G(w) u_pre); scalar BGK toward the
+// linear equilibrium at u_post.
+template <int Q, int QS, typename Real>
+__device__ __forceinline__ void collide_interior(const Params<Real>& p, Real wn, Real (&f)[Q],
+                                                 Real (&g)[QS > 0 ? QS : 1]) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  Real drho = 0, mx = 0, my = 0, mz = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    drho += f[j];
+    if (L::ex(j)) mx += Real(L::ex(j)) * f[j];
+    if (L::ey(j)) my += Real(L::ey(j)) * f[j];
+    if (L::ez(j)) mz += Real(L::ez(j)) * f[j];
+  }
+  const Real rho = Real(1) + drho;
+  const Real inv = Real(1) / rho;
+  const Real ux = mx * inv, uy = my * inv, uz = mz * inv;
+  Real G, dG;
+  switch_fn(p, wn, G, dG);
+  const Real usq = ux * ux + uy * uy + uz * uz;
+  const Real om1 = Real(1) - p.om;
+  const Real G2 = G * G;
+  const Real a0 = p.om * drho;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const Real eu = Real(L::ex(j)) * ux + Real(L::ey(j)) * uy + Real(L::ez(j)) * uz;
+    // P(u) = 3 e.u + 4.5 (e.u)^2 - 1.5 u^2 (c_s^2 = 1/3), P(Gu) = G P1 + G^2 P2
+    const Real P1 = Real(3) * eu;
+    const Real P2 = Real(4.5) * eu * eu - Real(1.5) * usq;
+    const Real Pu = P1 + P2;
+    const Real Pv = G * P1 + G2 * P2;
+    f[j] = om1 * f[j] + Real(L::w(j)) * (a0 + rho * (Pv - om1 * Pu));
+  }
+  if constexpr (QS > 0) {
+    Real T = 0;
+#pragma unroll
+    for (int i = 0; i < QS; ++i) T += g[i];
+    const Real vx = G * ux, vy = G * uy, vz = G * uz;
+    const Real oms1 = Real(1) - p.oms;
+    const Real ic2 = Real(1.0 / S::c2());
+#pragma unroll
+    for (int i = 0; i < QS; ++i) {
+      const Real ev = Real(S::ex(i)) * vx + Real(S::ey(i)) * vy + Real(S::ez(i)) * vz;
+      g[i] = oms1 * g[i] + p.oms * Real(S::w(i)) * T * (Real(1) + ev * ic2);
+    }
+  }
+}
+
+// Wall: full-way bounce-back h_j = f_opp(j); scalar bounce-back (adiabatic)
+// or equilibrium at the wall value with u = 0 (Dirichlet).
+template <int Q, int QS, typename Real>
+__device__ __forceinline__ void collide_wall(const Params<Real>& p, Real (&f)[Q], Real (&g)[QS > 0 ? QS : 1]) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  Real t[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) t[j] = f[L::opp(j)];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) f[j] = t[j];
+  if constexpr (QS > 0) {
+    if (p.scalar_wall == S_DIRICHLET) {
+#pragma unroll
+      for (int i = 0; i < QS; ++i) g[i] = Real(S::w(i)) * p.s_wall;
+    } else {
+      Real s[QS];
+#pragma unroll
+      for (int i = 0; i < QS; ++i) s[i] = g[S::opp(i)];
+#pragma unroll
+      for (int i = 0; i < QS; ++i) g[i] = s[i];
+    }
+  }
+}
+
+// Inlet (x = 0): Zou-He velocity u = (u_in, 0, 0); the e_x = +1 populations
+// are rebuilt from their opposites with the transverse correction
+// N_t = 1/2 sum_{e_x=0} f_k e_kt, then BGK at E(rho, u_in).  The scalar's
+// single unknown (+x) population is set so that sum g = T_in.
+template <int Q, int QS, typename Real>
+__device__ __forceinline__ void collide_inlet(const Params<Real>& p, int y, int z, Real (&f)[Q],
+                                              Real (&g)[QS > 0 ? QS : 1]) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  Real s0 = 0, sm = 0, Ny = 0, Nz = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    if (L::ex(j) == 0) {
+      s0 += f[j];
+      if (L::ey(j)) Ny += Real(0.5 * L::ey(j)) * f[j];
+      if (L::ez(j)) Nz += Real(0.5 * L::ez(j)) * f[j];
+    } else if (L::ex(j) == -1) {
+      sm += f[j];
+    }
+  }
+  const Real u = p.u_in;
+  const Real drho = (s0 + Real(2) * sm + u) / (Real(1) - u);
+  const Real rho = Real(1) + drho;
+  const Real usq = u * u;
+  Real fs[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    if (L::ex(j) == 1) {
+      fs[j] = f[L::opp(j)] + Real(6.0 * L::w(j)) * rho * u - Real(L::ey(j)) * Ny - Real(L::ez(j)) * Nz;
+    } else {
+      fs[j] = f[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const Real eu = Real(L::ex(j)) * u;
+    const Real E = Real(L::w(j)) * (drho + rho * (Real(3) * eu + Real(4.5) * eu * eu - Real(1.5) * usq));
+    f[j] = fs[j] + p.om * (E - fs[j]);
+  }
+  if constexpr (QS > 0) {
+    const Real T = inlet_value<Real>(p, y, z);
+    Real rest = 0;
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (i != kPX) rest += g[i];
+    g[kPX] = T - rest;
+    const Real ic2 = Real(1.0 / S::c2());
+#pragma unroll
+    for (int i = 0; i < QS; ++i) {
+      const Real E = Real(S::w(i)) * T * (Real(1) + Real(S::ex(i)) * u * ic2);
+      g[i] = g[i] + p.oms * (E - g[i]);
+    }
+  }
+}
+
+// Outlet (x = nx-1): Zou-He density rho_out, u = (u_x, 0, 0); the e_x = -1
+// populations are rebuilt, then BGK.  Scalar outflow: the unknown (-x)
+// population takes its equilibrium value at the reconstructed T*.
+template <int Q, int QS, typename Real>
+__device__ __forceinline__ void collide_outlet(const Params<Real>& p, Real (&f)[Q], Real (&g)[QS > 0 ? QS : 1]) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  Real s0 = 0, sp = 0, Ny = 0, Nz = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    if (L::ex(j) == 0) {
+      s0 += f[j];
+      if (L::ey(j)) Ny += Real(0.5 * L::ey(j)) * f[j];
+      if (L::ez(j)) Nz += Real(0.5 * L::ez(j)) * f[j];
+    } else if (L::ex(j) == 1) {
+      sp += f[j];
+    }
+  }
+  const Real rho = p.rho_out;
+  const Real drho = rho - Real(1);
+  const Real ux = (s0 + Real(2) * sp - drho) / rho;
+  const Real usq = ux * ux;
+  Real fs[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    if (L::ex(j) == -1) {
+      fs[j] = f[L::opp(j)] - Real(6.0 * L::w(j)) * rho * ux - Real(L::ey(j)) * Ny - Real(L::ez(j)) * Nz;
+    } else {
+      fs[j] = f[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const Real eu = Real(L::ex(j)) * ux;
+    const Real E = Real(L::w(j)) * (drho + rho * (Real(3) * eu + Real(4.5) * eu * eu - Real(1.5) * usq));
+    f[j] = fs[j] + p.om * (E - fs[j]);
+  }
+  if constexpr (QS > 0) {
+    const Real ic2 = Real(1.0 / S::c2());
+    Real rest = 0;
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (i != kMX) rest += g[i];
+    const Real a = Real(S::w(kMX)) * (Real(1) - ux * ic2);
+    const Real T = rest / (Real(1) - a);
+    g[kMX] = a * T;
+#pragma unroll
+    for (int i = 0; i < QS; ++i) {
+      const Real E = Real(S::w(i)) * T * (Real(1) + Real(S::ex(i)) * ux * ic2);
+      g[i] = g[i] + p.oms * (E - g[i]);
+    }
+  }
+}
+
+// One primal node update: pull, collide by node class, store (coalesced).
+template <int Q, int QS, typename Real>
+__device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* __restrict__ src,
+                                            Real* __restrict__ dst, const Real* __restrict__ w, int x, int y,
+                                            int z) {
+  constexpr bool is3d = (Q == 19);
+  const Nbr b = make_nbr(p, x, y, z);
+  const int n = x + b.Y[1] + b.Z[1];
+  Real f[Q], g[QS > 0 ? QS : 1];
+  pull_state<Q, QS, Real>(src, p.N, b, f, g);
+  const int cls = node_class(p, x, y, z, is3d);
+  if (cls == INTERIOR) {
+    collide_interior<Q, QS, Real>(p, w[n], f, g);
+  } else if (cls == WALL) {
+    collide_wall<Q, QS, Real>(p, f, g);
+  } else if (cls == INLET) {
+    collide_inlet<Q, QS, Real>(p, y, z, f, g);
+  } else {
+    collide_outlet<Q, QS, Real>(p, f, g);
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) dst[(size_t)j * p.N + n] = f[j];
+#pragma unroll
+  for (int i = 0; i < QS; ++i) dst[(size_t)(Q + i) * p.N + n] = g[i];
+}
+
+template <int Q, int QS, typename Real>
+__global__ __launch_bounds__(256) void k_primal(Params<Real> p, const Real* __restrict__ src,
+                                                Real* __restrict__ dst, const Real* __restrict__ w) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  primal_node<Q, QS, Real>(p, src, dst, w, x, blockIdx.y, blockIdx.z);
+}
+
+// ------------------------------------------------------------ objective
+// Boundary sums ("Globals") of the pre-collision state pulled from src, and
+// J = c_dp*dp + c_hf*HF + c_var*Var.  One block per context, fixed-order
+// reduction in LDS.  out[0..7] = sums (see lbm_objective), out[8] = J.
+constexpr int kNG = 8;
+constexpr int kObjThreads = 256;
+
+template <int Q, int QS, typename Real>
+__device__ void objective_block(const Params<Real>& p, const Real* __restrict__ src, double* __restrict__ out) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  constexpr bool is3d = (Q == 19);
+  __shared__ double red[kNG][kObjThreads];
+  double acc[kNG];
+#pragma unroll
+  for (int k = 0; k < kNG; ++k) acc[k] = 0.0;
+  const int plane = p.ny * p.nz;
+  if (!p.periodic) {
+    for (int k = threadIdx.x; k < 2 * plane; k += kObjThreads) {
+      const int side = k / plane;
+      const int r = k - side * plane;
+      const int y = r % p.ny, z = r / p.ny;
+      const int x = side ? p.nx - 1 : 0;
+      if (node_class(p, x, y, z, is3d) == WALL) continue;
+      const Nbr b = make_nbr(p, x, y, z);
+      Real f[Q], g[QS > 0 ? QS : 1];
+      pull_state<Q, QS, Real>(src, p.N, b, f, g);
+      double s0 = 0, sk = 0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        if (L::ex(j) == 0) s0 += (double)f[j];
+        else if (L::ex(j) == (side ? 1 : -1)) sk += (double)f[j];
+      }
+      if (side == 0) {
+        acc[0] += (1.0 + s0 + 2.0 * sk) / (1.0 - (double)p.u_in);
+        acc[1] += 1.0;
+      } else {
+        const double ro = (double)p.rho_out;
+        const double ux = (1.0 + s0 + 2.0 * sk) / ro - 1.0;
+        acc[2] += ro;
+        acc[3] += 1.0;
+        acc[7] += ux;
+        if constexpr (QS > 0) {
+          double rest = 0;
+#pragma unroll
+          for (int i = 0; i < QS; ++i)
+            if (i != kMX) rest += (double)g[i];
+          const double a = S::w(kMX) * (1.0 - ux / S::c2());
+          const double T = rest / (1.0 - a);
+          acc[4] += ux * T;
+          acc[5] += T;
+          acc[6] += T * T;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kNG; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = kObjThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < kNG; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double G[kNG];
+#pragma unroll
+    for (int k = 0; k < kNG; ++k) G[k] = red[k][0];
+    double J = 0;
+    if (!p.periodic && G[1] > 0 && G[3] > 0) {
+      const double dp = L::cs2() * (G[0] / G[1] - G[2] / G[3]);
+      const double mean = G[5] / G[3];
+      J = p.c_dp * dp + p.c_hf * G[4] + p.c_var * (G[6] / G[3] - mean * mean);
+    }
+#pragma unroll
+    for (int k = 0; k < kNG; ++k) out[k] = G[k];
+    out[kNG] = J;
+  }
+}
+
+template <int Q, int QS, typename Real>
+__global__ __launch_bounds__(kObjThreads) void k_objective(Params<Real> p, const Real* __restrict__ src,
+                                                           double* __restrict__ out) {
+  objective_block<Q, QS, Real>(p, src, out);
+}
+
+// ------------------------------------------------------------ adjoint seed
+// lambda^N = dJ/df^N: non-zero only at inlet/outlet nodes.  Uses the sums
+// written by the objective kernel (glob[0..7]).
+template <int Q, int QS, typename Real>
+__device__ __forceinline__ void seed_node(const Params<Real>& p, const Real* __restrict__ src,
+                                          const double* __restrict__ glob, Real* __restrict__ lam, int x, int y,
+                                          int z) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  constexpr bool is3d = (Q == 19);
+  const Nbr b = make_nbr(p, x, y, z);
+  const int n = x + b.Y[1] + b.Z[1];
+  const int cls = node_class(p, x, y, z, is3d);
+  double lf[Q], lg[QS > 0 ? QS : 1];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) lf[j] = 0.0;
+#pragma unroll
+  for (int i = 0; i < (QS > 0 ? QS : 1); ++i) lg[i] = 0.0;
+  if (cls == INLET && glob[1] > 0) {
+    const double dG0 = p.c_dp * L::cs2() / glob[1];
+    const double c = dG0 / (1.0 - (double)p.u_in);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) lf[j] = (L::ex(j) == 0) ? c : (L::ex(j) == -1 ? 2.0 * c : 0.0);
+  }
+  if constexpr (QS > 0) {
+    if (cls == OUTLET && glob[3] > 0) {
+      const double G3 = glob[3];
+      const double A4 = p.c_hf, A5 = -2.0 * p.c_var * glob[5] / (G3 * G3), A6 = p.c_var / G3;
+      Real f[Q], g[QS];
+      pull_state<Q, QS, Real>(src, p.N, b, f, g);
+      double s0 = 0, sp = 0, rest = 0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        if (L::ex(j) == 0) s0 += (double)f[j];
+        else if (L::ex(j) == 1) sp += (double)f[j];
+      }
+#pragma unroll
+      for (int i = 0; i < QS; ++i)
+        if (i != kMX) rest += (double)g[i];
+      const double ro = (double)p.rho_out;
+      const double ux = (1.0 + s0 + 2.0 * sp) / ro - 1.0;
+      const double a = S::w(kMX) * (1.0 - ux / S::c2());
+      const double T = rest / (1.0 - a);
+      const double dT = A4 * ux + A5 + 2.0 * A6 * T;        // dJ/dT*
+      const double dux = A4 * T + dT * (-T * S::w(kMX) / (S::c2() * (1.0 - a)));
+#pragma unroll
+      for (int j = 0; j < Q; ++j) lf[j] = (L::ex(j) == 0) ? dux / ro : (L::ex(j) == 1 ? 2.0 * dux / ro : 0.0);
+#pragma unroll
+      for (int i = 0; i < QS; ++i) lg[i] = (i == kMX) ? 0.0 : dT / (1.0 - a);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) lam[(size_t)j * p.N + n] = (Real)lf[j];
+#pragma unroll
+  for (int i = 0; i < QS; ++i) lam[(size_t)(Q + i) * p.N + n] = (Real)lg[i];
+}
+
+template <int Q, int QS, typename Real>
+__global__ __launch_bounds__(256) void k_seed(Params<Real> p, const Real* __restrict__ src,
+                                              const double* __restrict__ glob, Real* __restrict__ lam) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  seed_node<Q, QS, Real>(p, src, glob, lam, x, blockIdx.y, blockIdx.z);
+}
+
+// ------------------------------------------------------------ adjoint step
+// lambda^n(x) = (dW^x/df)^T(f^n(x)) mu(x),  mu_j(x) = lambda^{n+1}_j(x + e_j)
+// grad(x)    += (dW^x/dw)^T mu(x)            (interior nodes only)
+// The vector-Jacobian products below are hand-derived from the operators above.
+template <int Q, int QS, typename Real>
+__device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* __restrict__ prim,
+                                             const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
+                                             const Real* __restrict__ w, Real* __restrict__ grad, int x, int y,
+                                             int z) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  constexpr bool is3d = (Q == 19);
+  constexpr int QSA = QS > 0 ? QS : 1;
+  const Nbr b = make_nbr(p, x, y, z);
+  const int n = x + b.Y[1] + b.Z[1];
+  const int N = p.N;
+  Real mu[Q], nu[QSA];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) mu[j] = lam_in[(size_t)j * N + push_idx(b, L::ex(j), L::ey(j), L::ez(j))];
+#pragma unroll
+  for (int i = 0; i < QS; ++i) nu[i] = lam_in[(size_t)(Q + i) * N + push_idx(b, S::ex(i), S::ey(i), S::ez(i))];
+  const int cls = node_class(p, x, y, z, is3d);
+  Real lf[Q], lg[QSA];
+  const Real om1 = Real(1) - p.om;
+  const Real oms1 = Real(1) - p.oms;
+  if (cls == WALL) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) lf[j] = mu[L::opp(j)];
+#pragma unroll
+    for (int i = 0; i < QS; ++i) lg[i] = (p.scalar_wall == S_DIRICHLET) ? Real(0) : nu[S::opp(i)];
+  } else if (cls == INLET) {
+    // h = (1-omega) f* + omega E(rho, u_in): affine in f, no primal needed.
+    const Real u = p.u_in, usq = u * u;
+    Real B = 0, drho = 0, dNy = 0, dNz = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const Real eu = Real(L::ex(j)) * u;
+      B += mu[j] * Real(L::w(j)) * (Real(1) + Real(3) * eu + Real(4.5) * eu * eu - Real(1.5) * usq);
+      if (L::ex(j) == 1) {
+        drho += om1 * mu[j] * Real(6.0 * L::w(j)) * u;
+        if (L::ey(j)) dNy -= om1 * mu[j] * Real(L::ey(j));
+        if (L::ez(j)) dNz -= om1 * mu[j] * Real(L::ez(j));
+      }
+    }
+    drho += p.om * B;
+    const Real c = drho / (Real(1) - u);
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      Real v = 0;
+      if (L::ex(k) == 0) v = om1 * mu[k] + c + Real(0.5) * (Real(L::ey(k)) * dNy + Real(L::ez(k)) * dNz);
+      if (L::ex(k) == -1) v = om1 * (mu[k] + mu[L::opp(k)]) + Real(2) * c;
+      lf[k] = v;
+    }
+    if constexpr (QS > 0) {
+#pragma unroll
+      for (int i = 0; i < QS; ++i) lg[i] = (i == kPX) ? Real(0) : oms1 * (nu[i] - nu[kPX]);
+    }
+  } else {
+    Real f[Q], g[QSA];
+    pull_state<Q, QS, Real>(prim, N, b, f, g);
+    if (cls == INTERIOR) {
+      Real drho = 0, mx = 0, my = 0, mz = 0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        drho += f[j];
+        if (L::ex(j)) mx += Real(L::ex(j)) * f[j];
+        if (L::ey(j)) my += Real(L::ey(j)) * f[j];
+        if (L::ez(j)) mz += Real(L::ez(j)) * f[j];
+      }
+      const Real rho = Real(1) + drho;
+      const Real inv = Real(1) / rho;
+      const Real ux = mx * inv, uy = my * inv, uz = mz * inv;
+      const Real usq = ux * ux + uy * uy + uz * uz;
+      Real G, dG;
+      switch_fn(p, w[n], G, dG);
+      const Real G2 = G * G;
+      // cotangent moments M0 = sum mu w, M1 = sum mu w e, P = sum mu w (e.u) e
+      Real M0 = 0, M1x = 0, M1y = 0, M1z = 0, Px = 0, Py = 0, Pz = 0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const Real a = mu[j] * Real(L::w(j));
+        const Real eu = Real(L::ex(j)) * ux + Real(L::ey(j)) * uy + Real(L::ez(j)) * uz;
+        const Real be = a * eu;
+        M0 += a;
+        if (L::ex(j)) { M1x += Real(L::ex(j)) * a; Px += Real(L::ex(j)) * be; }
+        if (L::ey(j)) { M1y += Real(L::ey(j)) * a; Py += Real(L::ey(j)) * be; }
+        if (L::ez(j)) { M1z += Real(L::ez(j)) * a; Pz += Real(L::ez(j)) * be; }
+      }
+      const Real Mu = M1x * ux + M1y * uy + M1z * uz;
+      const Real Pu = Px * ux + Py * uy + Pz * uz;
+      // d/drho at fixed u of A(rho, G u) - (1-omega) A(rho, u), A = sum mu_j E_j
+      const Real dL_drho = M0 * (Real(1) - om1) + Real(3) * (G - om1) * Mu + Real(4.5) * (G2 - om1) * Pu -
+                           Real(1.5) * (G2 - om1) * M0 * usq;
+      const Real c1 = Real(3) * (G - om1), c2 = Real(9) * (G2 - om1), c3 = Real(3) * (G2 - om1) * M0;
+      Real dux = rho * (c1 * M1x + c2 * Px - c3 * ux);
+      Real duy = rho * (c1 * M1y + c2 * Py - c3 * uy);
+      Real duz = rho * (c1 * M1z + c2 * Pz - c3 * uz);
+      Real dLdG = rho * (Real(3) * Mu + Real(9) * G * Pu - Real(3) * G * M0 * usq);
+      if constexpr (QS > 0) {
+        Real T = 0, N0 = 0, N1x = 0, N1y = 0, N1z = 0;
+#pragma unroll
+        for (int i = 0; i < QS; ++i) {
+          T += g[i];
+          const Real a = nu[i] * Real(S::w(i));
+          N0 += a;
+          if (S::ex(i)) N1x += Real(S::ex(i)) * a;
+          if (S::ey(i)) N1y += Real(S::ey(i)) * a;
+          if (S::ez(i)) N1z += Real(S::ez(i)) * a;
+        }
+        const Real ic2 = Real(1.0 / S::c2());
+        const Real N1u = N1x * ux + N1y * uy + N1z * uz;
+        const Real k = p.oms * T * G * ic2;
+        dux += k * N1x;
+        duy += k * N1y;
+        duz += k * N1z;
+        dLdG += p.oms * T * N1u * ic2;
+        const Real dT = p.oms * (N0 + G * N1u * ic2);
+#pragma unroll
+        for (int i = 0; i < QS; ++i) lg[i] = oms1 * nu[i] + dT;
+      }
+      const Real dmx = dux * inv, dmy = duy * inv, dmz = duz * inv;
+      const Real drt = dL_drho - (dux * ux + duy * uy + duz * uz) * inv;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        Real v = om1 * mu[k] + drt;
+        if (L::ex(k)) v += Real(L::ex(k)) * dmx;
+        if (L::ey(k)) v += Real(L::ey(k)) * dmy;
+        if (L::ez(k)) v += Real(L::ez(k)) * dmz;
+        lf[k] = v;
+      }
+      grad[n] += dG * dLdG;
+    } else {  // OUTLET
+      Real s0 = 0, sp = 0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        if (L::ex(j) == 0) s0 += f[j];
+        else if (L::ex(j) == 1) sp += f[j];
+      }
+      const Real ro = p.rho_out;
+      const Real ux = (s0 + Real(2) * sp - (ro - Real(1))) / ro;
+      Real dux = 0, dNy = 0, dNz = 0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const Real ex = Real(L::ex(j));
+        dux += p.om * ro * mu[j] * Real(L::w(j)) * (Real(3) * ex + Real(9) * ex * ex * ux - Real(3) * ux);
+        if (L::ex(j) == -1) {
+          dux -= om1 * mu[j] * Real(6.0 * L::w(j)) * ro;
+          if (L::ey(j)) dNy -= om1 * mu[j] * Real(L::ey(j));
+          if (L::ez(j)) dNz -= om1 * mu[j] * Real(L::ez(j));
+        }
+      }
+      if constexpr (QS > 0) {
+        const Real ic2 = Real(1.0 / S::c2());
+        Real rest = 0, N0 = 0, N1x = 0;
+#pragma unroll
+        for (int i = 0; i < QS; ++i) {
+          if (i != kMX) rest += g[i];
+          const Real a = nu[i] * Real(S::w(i));
+          N0 += a;
+          if (S::ex(i)) N1x += Real(S::ex(i)) * a;
+        }
+        const Real a = Real(S::w(kMX)) * (Real(1) - ux * ic2);
+        const Real inv1a = Real(1) / (Real(1) - a);
+        const Real T = rest * inv1a;
+        const Real dT = oms1 * nu[kMX] * a + p.oms * (N0 + N1x * ux * ic2);
+        const Real da = oms1 * nu[kMX] * T + dT * T * inv1a;
+        const Real dS = dT * inv1a;
+        dux += p.oms * T * N1x * ic2 - da * Real(S::w(kMX)) * ic2;
+#pragma unroll
+        for (int i = 0; i < QS; ++i) lg[i] = (i == kMX) ? Real(0) : oms1 * nu[i] + dS;
+      }
+      const Real c = dux / ro;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        Real v = 0;
+        if (L::ex(k) == 0) v = om1 * mu[k] + c + Real(0.5) * (Real(L::ey(k)) * dNy + Real(L::ez(k)) * dNz);
+        if (L::ex(k) == 1) v = om1 * (mu[k] + mu[L::opp(k)]) + Real(2) * c;
+        lf[k] = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) lam_out[(size_t)j * N + n] = lf[j];
+#pragma unroll
+  for (int i = 0; i < QS; ++i) lam_out[(size_t)(Q + i) * N + n] = lg[i];
+}
+
+template <int Q, int QS, typename Real>
+__global__ __launch_bounds__(256) void k_adjoint(Params<Real> p, const Real* __restrict__ prim,
+                                                 const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
+                                                 const Real* __restrict__ w, Real* __restrict__ grad) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  adjoint_node<Q, QS, Real>(p, prim, lam_in, lam_out, w, grad, x, blockIdx.y, blockIdx.z);
+}
+
+// ------------------------------------------------------ inspection kernels
+// Macroscopic fields of the pulled pre-collision state (double outputs).
+template <int Q, int QS, typename Real>
+__global__ __launch_bounds__(256) void k_fields(Params<Real> p, const Real* __restrict__ src,
+                                                double* __restrict__ rho, double* __restrict__ u,
+                                                double* __restrict__ s) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  constexpr bool is3d = (Q == 19);
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  const int y = blockIdx.y, z = blockIdx.z;
+  const Nbr b = make_nbr(p, x, y, z);
+  const int n = x + b.Y[1] + b.Z[1];
+  Real f[Q], g[QS > 0 ? QS : 1];
+  pull_state<Q, QS, Real>(src, p.N, b, f, g);
+  const int cls = node_class(p, x, y, z, is3d);
+  double dr = 0, mx = 0, my = 0, mz = 0, T = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    dr += (double)f[j];
+    mx += L::ex(j) * (double)f[j];
+    my += L::ey(j) * (double)f[j];
+    mz += L::ez(j) * (double)f[j];
+  }
+#pragma unroll
+  for (int i = 0; i < QS; ++i) T += (double)g[i];
+  double r = 1.0 + dr, ox = 0, oy = 0, oz = 0;
+  if (cls == INTERIOR) {
+    ox = mx / r;
+    oy = my / r;
+    oz = mz / r;
+  } else if (cls == WALL) {
+    if (QS > 0 && p.scalar_wall == S_DIRICHLET) T = (double)p.s_wall;
+  } else {
+    double s0 = 0, sk = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      if (L::ex(j) == 0) s0 += (double)f[j];
+      else if (L::ex(j) == (cls == INLET ? -1 : 1)) sk += (double)f[j];
+    }
+    if (cls == INLET) {
+      r = (1.0 + s0 + 2.0 * sk) / (1.0 - (double)p.u_in);
+      ox = (double)p.u_in;
+      if (QS > 0) T = (double)inlet_value<Real>(p, y, z);
+    } else {
+      r = (double)p.rho_out;
+      ox = (1.0 + s0 + 2.0 * sk) / r - 1.0;
+      if constexpr (QS > 0) {
+        double rest = 0;
+#pragma unroll
+        for (int i = 0; i < QS; ++i)
+          if (i != kMX) rest += (double)g[i];
+        const double a = S::w(kMX) * (1.0 - ox / S::c2());
+        T = rest / (1.0 - a);
+      }
+    }
+  }
+  rho[n] = r;
+  u[n] = ox;
+  u[(size_t)p.N + n] = oy;
+  u[(size_t)2 * p.N + n] = oz;
+  if (s) s[n] = T;
+}
+
+// Pre-collision state f^t (un-shifted, double) pulled from src.
+template <int Q, int QS, typename Real>
+__global__ __launch_bounds__(256) void k_get_state(Params<Real> p, const Real* __restrict__ src,
+                                                   double* __restrict__ fo, double* __restrict__ go) {
+  using L = Lat<Q>;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  const Nbr b = make_nbr(p, x, blockIdx.y, blockIdx.z);
+  const int n = x + b.Y[1] + b.Z[1];
+  Real f[Q], g[QS > 0 ? QS : 1];
+  pull_state<Q, QS, Real>(src, p.N, b, f, g);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) fo[(size_t)j * p.N + n] = (double)f[j] + L::w(j);
+  if (go) {
+#pragma unroll
+    for (int i = 0; i < QS; ++i) go[(size_t)i * p.N + n] = (double)g[i];
+  }
+}
+
+// Stored post-collision buffer h^{-1} with S h^{-1} = f0: h_j(x) = f0_j(x + e_j).
+template <int Q, int QS, typename Real>
+__global__ __launch_bounds__(256) void k_set_state(Params<Real> p, const double* __restrict__ f0,
+                                                   const double* __restrict__ g0, Real* __restrict__ dst) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  const Nbr b = make_nbr(p, x, blockIdx.y, blockIdx.z);
+  const int n = x + b.Y[1] + b.Z[1];
+#pragma unroll
+  for (int j = 0; j < Q; ++j)
+    dst[(size_t)j * p.N + n] = (Real)(f0[(size_t)j * p.N + push_idx(b, L::ex(j), L::ey(j), L::ez(j))] - L::w(j));
+#pragma unroll
+  for (int i = 0; i < QS; ++i)
+    dst[(size_t)(Q + i) * p.N + n] =
+        g0 ? (Real)g0[(size_t)i * p.N + push_idx(b, S::ex(i), S::ey(i), S::ez(i))] : Real(0);
+}
+
+// Node classes and pull-source map.
+template <int Q, int QS, typename Real>
+__global__ __launch_bounds__(256) void k_maps(Params<Real> p, uint8_t* __restrict__ mask, int64_t* __restrict__ src) {
+  using L = Lat<Q>;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  const Nbr b = make_nbr(p, x, blockIdx.y, blockIdx.z);
+  const int n = x + b.Y[1] + b.Z[1];
+  if (mask) mask[n] = (uint8_t)node_class(p, x, (int)blockIdx.y, (int)blockIdx.z, Q == 19);
+  if (src) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) src[(size_t)j * p.N + n] = pull_idx(b, L::ex(j), L::ey(j), L::ez(j));
+  }
+}
+
+// ------------------------------------------------------- small helpers
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* __restrict__ a, size_t n, T v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_copy(const T* __restrict__ a, T* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = a[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_to_double(const T* __restrict__ a, double* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (double)a[i];
+}
+
+}  // namespace lbmk

@@ -1,0 +1,693 @@
+// Host side of the adjoint lattice-Boltzmann library: context, workspace
+// carving, checkpoint plan, launch dispatch and the C ABI of lbm_adj.h.
+//
+// The library never allocates device memory: every buffer below is a slice of
+// the caller's workspace.  Workspace layout (each slice 256-byte aligned):
+//   w        N x Real      design field (copied in by lbm_set_design)
+//   grad     N x Real      dJ/dw accumulator
+//   glob     16 doubles    boundary sums + J of the last objective evaluation
+//   desc     batch descriptor table (kMaxBatch entries)
+//   lam[2]   2 states      adjoint ping-pong
+//   pp[2]    2 states      primal ping-pong (unrecorded steps, final state)
+//   ckpt[S]  S states      checkpoints h^{sC-1}, s = 0..S-1 (ckpt[0] = h^{-1})
+//   ring[C-1] states       h^{sC}..h^{sC+C-2} of the segment being reversed
+// A "state" is Qt x N values of the context precision.
+//
+// Trajectory bookkeeping (step k computes h^k from h^{k-1}, k = 0..N-1):
+// while recording, h^k goes to ckpt[(k+1)/C] when (k+1) % C == 0 (and a slot
+// is left), else to ring[(k+1) % C] when that is non-zero, else to a primal
+// ping-pong buffer.  The adjoint step n needs h^{n-1}: ckpt[s] when n = sC,
+// ring[n - sC] otherwise; a segment missing from the ring is recomputed from
+// its checkpoint (C - 1 primal steps).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm_adj.h"
+#include "kernels.hpp"
+
+using namespace lbmk;
+
+namespace {
+
+constexpr uint64_t kAlign = 256;
+constexpr int kMaxBatch = 64;
+
+uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Plan {
+  int Q = 0, QS = 0, QT = 0;
+  int64_t N = 0;             // nodes
+  uint64_t rs = 0;           // bytes per value
+  uint64_t state_bytes = 0;  // aligned
+  uint64_t node_bytes = 0;   // aligned N x Real
+  int64_t C = 1, S = 1;      // checkpoint interval and slots
+  uint64_t total = 0;
+};
+
+}  // namespace
+
+// Descriptor of one context in a batched launch (see kernels below).
+struct BatchDesc;
+
+struct lbm_ctx {
+  lbm_config cfg;
+  Plan plan;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  uint64_t ws_bytes = 0;
+  // carved buffers
+  void* w = nullptr;
+  void* grad = nullptr;
+  double* glob = nullptr;
+  void* desc = nullptr;
+  void* lam[2] = {nullptr, nullptr};
+  void* pp[2] = {nullptr, nullptr};
+  char* ckpt = nullptr;
+  char* ring = nullptr;
+  // time bookkeeping
+  int64_t t = 0;          // primal time: current state is h^{t-1}
+  int64_t rec_len = 0;    // recorded steps (trajectory h^{-1}..h^{rec_len-1})
+  bool rec_open = true;   // recording can be continued
+  void* cur = nullptr;    // buffer holding h^{t-1}
+  bool design_set = false;
+  bool adj_started = false;
+  int64_t t_adj = -1;     // adjoint time (lambda^{t_adj} in lam[lam_cur])
+  int lam_cur = 0;
+  int64_t ring_seg = -1;  // trajectory segment currently held by the ring
+  std::string err;
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return s;
+}
+
+lbm_status check_config(const lbm_config* c, std::string* why) {
+  auto bad = [&](const char* m) {
+    if (why) *why = m;
+    return LBM_EINVAL;
+  };
+  if (!c) return bad("config is NULL");
+  if (c->struct_size != sizeof(lbm_config)) return bad("struct_size does not match sizeof(lbm_config)");
+  if (c->flow != LBM_D2Q9 && c->flow != LBM_D3Q19) return bad("flow must be LBM_D2Q9 or LBM_D3Q19");
+  if (c->scalar != LBM_SCALAR_NONE && !((c->flow == LBM_D2Q9 && c->scalar == LBM_D2Q5) ||
+                                        (c->flow == LBM_D3Q19 && c->scalar == LBM_D3Q7)))
+    return bad("scalar lattice must be none, D2Q5 with D2Q9, or D3Q7 with D3Q19");
+  if (c->precision != LBM_FP32 && c->precision != LBM_FP64) return bad("precision must be LBM_FP32 or LBM_FP64");
+  if (c->nx < 3 || c->ny < 3 || c->nz < 1) return bad("nx, ny must be >= 3 and nz >= 1");
+  if (c->flow == LBM_D2Q9 && c->nz != 1) return bad("D2Q9 needs nz = 1");
+  if (c->flow == LBM_D3Q19 && c->nz < 3) return bad("D3Q19 needs nz >= 3");
+  if (c->ny > 65535 || c->nz > 65535) return bad("ny and nz must be <= 65535");
+  if (!(c->tau > 0.5) || (c->scalar && !(c->tau_s > 0.5))) return bad("relaxation times must exceed 1/2");
+  if (!(std::fabs(c->u_in) < 1.0) || !(c->rho_out > 0.0)) return bad("need |u_in| < 1 and rho_out > 0");
+  if (c->scalar_wall != LBM_WALL_ADIABATIC && c->scalar_wall != LBM_WALL_DIRICHLET) return bad("bad scalar_wall");
+  if (c->s_split_axis < 0 || c->s_split_axis > 2) return bad("bad s_split_axis");
+  if (c->switch_fn != LBM_G_POWER && c->switch_fn != LBM_G_RAMP) return bad("bad switch_fn");
+  if (c->switch_fn == LBM_G_RAMP && !(c->switch_param > 0.0)) return bad("RAMP needs q > 0");
+  if (c->switch_fn == LBM_G_POWER && !(c->switch_param >= 0.0)) return bad("POWER needs theta >= 0");
+  if (c->reserved0 != 0) return bad("reserved0 must be 0");
+  if (c->nsteps < 0 || c->checkpoint_interval < 0) return bad("nsteps and checkpoint_interval must be >= 0");
+  const int64_t N = (int64_t)c->nx * c->ny * c->nz;
+  const int QT = c->flow + c->scalar;
+  if ((int64_t)QT * N >= (int64_t(1) << 31)) return bad("lattice too large: Qt*N must be < 2^31");
+  return LBM_OK;
+}
+
+uint64_t plan_total(const Plan& p, int64_t C, int64_t S) {
+  (void)C;
+  uint64_t t = 2 * p.node_bytes + align_up(16 * sizeof(double)) + align_up(kMaxBatch * 256);
+  t += (uint64_t)(2 + 2 + S + std::max<int64_t>(C - 1, 0)) * p.state_bytes;
+  return t;
+}
+
+lbm_status make_plan(const lbm_config* c, Plan* p, std::string* why) {
+  lbm_status s = check_config(c, why);
+  if (s != LBM_OK) return s;
+  p->Q = c->flow;
+  p->QS = c->scalar;
+  p->QT = p->Q + p->QS;
+  p->N = (int64_t)c->nx * c->ny * c->nz;
+  p->rs = (c->precision == LBM_FP32) ? 4 : 8;
+  p->state_bytes = align_up((uint64_t)p->QT * p->N * p->rs);
+  p->node_bytes = align_up((uint64_t)p->N * p->rs);
+  const int64_t Nst = std::max<int64_t>(c->nsteps, 1);
+  int64_t C;
+  if (c->checkpoint_interval > 0) {
+    C = std::min<int64_t>(c->checkpoint_interval, Nst);
+  } else if (c->hbm_budget_bytes == 0) {
+    C = 1;
+    while (C * C < Nst) ++C;
+  } else {
+    // largest C (fewest recomputed steps) whose workspace fits the budget
+    C = 0;
+    for (int64_t cc = Nst; cc >= 1; --cc) {
+      const int64_t S = (Nst + cc - 1) / cc;
+      if (plan_total(*p, cc, S) <= c->hbm_budget_bytes) {
+        C = cc;
+        break;
+      }
+    }
+    if (C == 0) {
+      if (why) *why = "no checkpoint interval fits hbm_budget_bytes";
+      return LBM_ENOMEM;
+    }
+  }
+  p->C = C;
+  p->S = (Nst + C - 1) / C;
+  p->total = plan_total(*p, p->C, p->S);
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------------- launches
+template <typename Real>
+Params<Real> make_params(const lbm_config& c, int64_t N) {
+  Params<Real> p;
+  p.nx = c.nx;
+  p.ny = c.ny;
+  p.nz = c.nz;
+  p.periodic = c.periodic ? 1 : 0;
+  p.N = (int)N;
+  p.scalar_wall = c.scalar_wall;
+  p.split_axis = c.s_split_axis;
+  p.switch_fn = c.switch_fn;
+  const double th = c.switch_param;
+  p.theta_int = (c.switch_fn == LBM_G_POWER && th == std::floor(th) && th <= 16) ? (int)th : -1;
+  p.om = (Real)(1.0 / c.tau);
+  p.oms = (Real)(c.scalar ? 1.0 / c.tau_s : 0.0);
+  p.u_in = (Real)c.u_in;
+  p.rho_out = (Real)c.rho_out;
+  p.s_wall = (Real)c.s_wall;
+  p.s_in_lo = (Real)c.s_in_lo;
+  p.s_in_hi = (Real)c.s_in_hi;
+  p.sw_param = (Real)c.switch_param;
+  p.c_dp = c.c_dp;
+  p.c_hf = c.c_hf;
+  p.c_var = c.c_var;
+  return p;
+}
+
+struct Geo {
+  dim3 grid, block;
+};
+
+Geo node_geometry(const lbm_config& c) {
+  int bx = std::min(256, (c.nx + 63) / 64 * 64);
+  Geo g;
+  g.block = dim3(bx, 1, 1);
+  g.grid = dim3((c.nx + bx - 1) / bx, c.ny, c.nz);
+  return g;
+}
+
+dim3 flat_grid(size_t n) {
+  size_t b = (n + 255) / 256;
+  return dim3((unsigned)std::min<size_t>(std::max<size_t>(b, 1), 65536), 1, 1);
+}
+
+lbm_status launch_check(lbm_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return LBM_OK;
+}
+
+// Typed operations on one context.
+template <int Q, int QS, typename Real>
+struct Ops {
+  static Params<Real> P(lbm_ctx* c) { return make_params<Real>(c->cfg, c->plan.N); }
+
+  static void primal(lbm_ctx* c, const void* src, void* dst) {
+    Geo g = node_geometry(c->cfg);
+    hipLaunchKernelGGL((k_primal<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src, (Real*)dst,
+                       (const Real*)c->w);
+  }
+  static void objective(lbm_ctx* c, const void* src, double* out) {
+    hipLaunchKernelGGL((k_objective<Q, QS, Real>), dim3(1), dim3(kObjThreads), 0, c->stream, P(c),
+                       (const Real*)src, out);
+  }
+  static void seed(lbm_ctx* c, const void* src, void* lam) {
+    Geo g = node_geometry(c->cfg);
+    hipLaunchKernelGGL((k_seed<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
+                       (const double*)c->glob, (Real*)lam);
+  }
+  static void adjoint(lbm_ctx* c, const void* prim, const void* lin, void* lout) {
+    Geo g = node_geometry(c->cfg);
+    hipLaunchKernelGGL((k_adjoint<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)prim,
+                       (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
+  }
+  static void fields(lbm_ctx* c, const void* src, double* rho, double* u, double* s) {
+    Geo g = node_geometry(c->cfg);
+    hipLaunchKernelGGL((k_fields<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src, rho, u, s);
+  }
+  static void get_state(lbm_ctx* c, const void* src, double* f, double* gg) {
+    Geo g = node_geometry(c->cfg);
+    hipLaunchKernelGGL((k_get_state<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src, f, gg);
+  }
+  static void set_state(lbm_ctx* c, const double* f, const double* gg, void* dst) {
+    Geo g = node_geometry(c->cfg);
+    hipLaunchKernelGGL((k_set_state<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), f, gg, (Real*)dst);
+  }
+  static void maps(lbm_ctx* c, uint8_t* mask, int64_t* src) {
+    Geo g = node_geometry(c->cfg);
+    hipLaunchKernelGGL((k_maps<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), mask, src);
+  }
+  static void fill(lbm_ctx* c, void* a, size_t n) {
+    hipLaunchKernelGGL((k_fill<Real>), flat_grid(n), dim3(256), 0, c->stream, (Real*)a, n, Real(0));
+  }
+  static void copy(lbm_ctx* c, const void* a, void* b, size_t n) {
+    hipLaunchKernelGGL((k_copy<Real>), flat_grid(n), dim3(256), 0, c->stream, (const Real*)a, (Real*)b, n);
+  }
+  static void to_double(lbm_ctx* c, const void* a, double* b, size_t n) {
+    hipLaunchKernelGGL((k_to_double<Real>), flat_grid(n), dim3(256), 0, c->stream, (const Real*)a, b, n);
+  }
+};
+
+// Calls F::template run<Ops<...>>(args) for the context's lattice/precision.
+template <template <class> class F, class... A>
+lbm_status dispatch(lbm_ctx* c, A&&... a) {
+  const lbm_config& k = c->cfg;
+  const bool f32 = k.precision == LBM_FP32;
+  if (k.flow == 9 && k.scalar == 0) return f32 ? F<Ops<9, 0, float>>::run(c, a...) : F<Ops<9, 0, double>>::run(c, a...);
+  if (k.flow == 9 && k.scalar == 5) return f32 ? F<Ops<9, 5, float>>::run(c, a...) : F<Ops<9, 5, double>>::run(c, a...);
+  if (k.flow == 19 && k.scalar == 0)
+    return f32 ? F<Ops<19, 0, float>>::run(c, a...) : F<Ops<19, 0, double>>::run(c, a...);
+  return f32 ? F<Ops<19, 7, float>>::run(c, a...) : F<Ops<19, 7, double>>::run(c, a...);
+}
+
+void* ckpt_slot(lbm_ctx* c, int64_t s) { return c->ckpt + (uint64_t)s * c->plan.state_bytes; }
+void* ring_slot(lbm_ctx* c, int64_t i) { return c->ring + (uint64_t)(i - 1) * c->plan.state_bytes; }
+
+// Destination of h^k while recording.
+void* rec_dst(lbm_ctx* c, int64_t k) {
+  const int64_t C = c->plan.C;
+  const int64_t s = (k + 1) / C, i = (k + 1) % C;
+  if (i == 0 && s < c->plan.S) return ckpt_slot(c, s);
+  if (i != 0) return ring_slot(c, i);
+  return (c->cur == c->pp[0]) ? c->pp[1] : c->pp[0];
+}
+
+template <class O>
+struct RunPrimal {
+  static lbm_status run(lbm_ctx* c, int64_t nsteps, int record) {
+    for (int64_t i = 0; i < nsteps; ++i) {
+      void* src = c->cur;
+      void* dst = record ? rec_dst(c, c->t) : ((c->cur == c->pp[0]) ? c->pp[1] : c->pp[0]);
+      O::primal(c, src, dst);
+      c->cur = dst;
+      ++c->t;
+    }
+    return launch_check(c, "primal step");
+  }
+};
+
+template <class O>
+struct RunObjective {
+  static lbm_status run(lbm_ctx* c, double* J_dev) {
+    O::objective(c, c->cur, c->glob);
+    if (J_dev) {
+      hipError_t e = hipMemcpyAsync(J_dev, c->glob + kNG, sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) return fail(c, LBM_EHIP, "objective copy: %s", hipGetErrorString(e));
+    }
+    return launch_check(c, "objective");
+  }
+};
+
+// Recompute the trajectory segment s into the ring from its checkpoint.
+template <class O>
+void recompute_segment(lbm_ctx* c, int64_t s) {
+  const int64_t C = c->plan.C;
+  const int64_t last = std::min<int64_t>(s * C + C - 2, c->rec_len - 2);
+  const void* src = ckpt_slot(c, s);
+  for (int64_t k = s * C; k <= last; ++k) {
+    void* dst = ring_slot(c, k + 1 - s * C);
+    O::primal(c, src, dst);
+    src = dst;
+  }
+  c->ring_seg = s;
+}
+
+template <class O>
+struct RunAdjoint {
+  static lbm_status run(lbm_ctx* c, int64_t nsteps) {
+    const int64_t C = c->plan.C;
+    if (!c->adj_started) {
+      O::objective(c, c->cur, c->glob);
+      O::seed(c, c->cur, c->lam[0]);
+      O::fill(c, c->grad, (size_t)c->plan.N);
+      c->lam_cur = 0;
+      c->t_adj = c->rec_len;
+      c->ring_seg = c->rec_len > 0 ? (c->rec_len - 1) / C : -1;
+      c->adj_started = true;
+    }
+    for (int64_t i = 0; i < nsteps; ++i) {
+      const int64_t n = c->t_adj - 1;
+      const int64_t s = n / C;
+      if (s != c->ring_seg) recompute_segment<O>(c, s);
+      const int64_t r = n - s * C;
+      const void* prim = (r == 0) ? ckpt_slot(c, s) : ring_slot(c, r);
+      O::adjoint(c, prim, c->lam[c->lam_cur], c->lam[1 - c->lam_cur]);
+      c->lam_cur ^= 1;
+      --c->t_adj;
+    }
+    return launch_check(c, "adjoint step");
+  }
+};
+
+template <class O>
+struct RunReset {
+  static lbm_status run(lbm_ctx* c) {
+    O::fill(c, ckpt_slot(c, 0), (size_t)c->plan.QT * c->plan.N);
+    return launch_check(c, "reset");
+  }
+};
+
+template <class O>
+struct RunSetState {
+  static lbm_status run(lbm_ctx* c, const double* f, const double* g) {
+    O::set_state(c, f, g, ckpt_slot(c, 0));
+    return launch_check(c, "set_state");
+  }
+};
+
+template <class O>
+struct RunGradient {
+  static lbm_status run(lbm_ctx* c, void* out) {
+    O::copy(c, c->grad, out, (size_t)c->plan.N);
+    return launch_check(c, "gradient");
+  }
+};
+
+template <class O>
+struct RunFields {
+  static lbm_status run(lbm_ctx* c, double* rho, double* u, double* s) {
+    O::fields(c, c->cur, rho, u, s);
+    return launch_check(c, "fields");
+  }
+};
+
+template <class O>
+struct RunGetState {
+  static lbm_status run(lbm_ctx* c, double* f, double* g) {
+    O::get_state(c, c->cur, f, g);
+    return launch_check(c, "get_state");
+  }
+};
+
+template <class O>
+struct RunGetAdjoint {
+  static lbm_status run(lbm_ctx* c, double* lf, double* lg) {
+    const size_t n = (size_t)c->plan.N;
+    const char* base = (const char*)c->lam[c->lam_cur];
+    O::to_double(c, base, lf, (size_t)c->plan.Q * n);
+    if (lg && c->plan.QS) O::to_double(c, base + (size_t)c->plan.Q * n * c->plan.rs, lg, (size_t)c->plan.QS * n);
+    return launch_check(c, "get_adjoint");
+  }
+};
+
+template <class O>
+struct RunMaps {
+  static lbm_status run(lbm_ctx* c, uint8_t* mask, int64_t* src) {
+    O::maps(c, mask, src);
+    return launch_check(c, "export_maps");
+  }
+};
+
+template <class O>
+struct RunSetDesign {
+  static lbm_status run(lbm_ctx* c, const void* w) {
+    O::copy(c, w, c->w, (size_t)c->plan.N);
+    return launch_check(c, "set_design");
+  }
+};
+
+void reset_times(lbm_ctx* c) {
+  c->t = 0;
+  c->rec_len = 0;
+  c->rec_open = true;
+  c->cur = ckpt_slot(c, 0);
+  c->adj_started = false;
+  c->t_adj = -1;
+  c->lam_cur = 0;
+  c->ring_seg = -1;
+}
+
+lbm_status sync_check(lbm_ctx* c, const char* what) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return fail(c, LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return LBM_OK;
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+extern "C" {
+
+lbm_status lbm_required_bytes(const lbm_config* cfg, uint64_t* bytes_out) {
+  if (!bytes_out) return LBM_EINVAL;
+  Plan p;
+  lbm_status s = make_plan(cfg, &p, nullptr);
+  if (s != LBM_OK) return s;
+  *bytes_out = p.total;
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_config* cfg, void* hip_stream, void* workspace_dev, uint64_t workspace_bytes,
+                      lbm_ctx** ctx_out) {
+  if (!ctx_out) return LBM_EINVAL;
+  *ctx_out = nullptr;
+  Plan p;
+  std::string why;
+  lbm_status s = make_plan(cfg, &p, &why);
+  if (s != LBM_OK) {
+    fprintf(stderr, "lbm_create: %s\n", why.c_str());
+    return s;
+  }
+  if (!workspace_dev || ((uintptr_t)workspace_dev % kAlign) != 0) return LBM_EINVAL;
+  if (workspace_bytes < p.total) return LBM_ENOMEM;
+  lbm_ctx* c = new lbm_ctx();
+  c->cfg = *cfg;
+  c->plan = p;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)workspace_dev;
+  c->ws_bytes = workspace_bytes;
+  char* q = c->ws;
+  c->w = q;
+  q += p.node_bytes;
+  c->grad = q;
+  q += p.node_bytes;
+  c->glob = (double*)q;
+  q += align_up(16 * sizeof(double));
+  c->desc = q;
+  q += align_up(kMaxBatch * 256);
+  for (int i = 0; i < 2; ++i) {
+    c->lam[i] = q;
+    q += p.state_bytes;
+  }
+  for (int i = 0; i < 2; ++i) {
+    c->pp[i] = q;
+    q += p.state_bytes;
+  }
+  c->ckpt = q;
+  q += (uint64_t)p.S * p.state_bytes;
+  c->ring = q;
+  q += (uint64_t)std::max<int64_t>(p.C - 1, 0) * p.state_bytes;
+  reset_times(c);
+  s = dispatch<RunReset>(c);
+  if (s != LBM_OK) {
+    delete c;
+    return s;
+  }
+  *ctx_out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx* ctx) {
+  if (!ctx) return LBM_EINVAL;
+  delete ctx;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_design(lbm_ctx* c, const void* w_dev) {
+  if (!c) return LBM_EINVAL;
+  if (!w_dev) return fail(c, LBM_EINVAL, "set_design: NULL design field");
+  lbm_status s = dispatch<RunSetDesign>(c, w_dev);
+  if (s != LBM_OK) return s;
+  c->design_set = true;
+  // a recorded trajectory or adjoint of another design is no longer valid
+  if (c->rec_len > 0 || c->adj_started) {
+    c->rec_len = 0;
+    c->rec_open = false;
+    c->adj_started = false;
+    c->t_adj = -1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_reset(lbm_ctx* c) {
+  if (!c) return LBM_EINVAL;
+  reset_times(c);
+  return dispatch<RunReset>(c);
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const double* f_dev, const double* g_dev) {
+  if (!c) return LBM_EINVAL;
+  if (!f_dev) return fail(c, LBM_EINVAL, "set_state: NULL f");
+  reset_times(c);
+  return dispatch<RunSetState>(c, f_dev, g_dev);
+}
+
+lbm_status lbm_primal_steps(lbm_ctx* c, int64_t nsteps, int32_t record) {
+  if (!c) return LBM_EINVAL;
+  if (nsteps < 0) return fail(c, LBM_EINVAL, "primal_steps: negative count");
+  if (!c->design_set) return fail(c, LBM_ESTATE, "primal_steps: no design field set");
+  if (c->adj_started) return fail(c, LBM_ESTATE, "primal_steps: adjoint started; call lbm_reset first");
+  if (record) {
+    if (!(c->rec_open && c->t == c->rec_len))
+      return fail(c, LBM_ESTATE, "primal_steps: recording must start at t = 0 or continue a recorded run");
+    if (c->t + nsteps > c->cfg.nsteps)
+      return fail(c, LBM_EINVAL, "primal_steps: recorded run of %lld steps exceeds the horizon %lld",
+                  (long long)(c->t + nsteps), (long long)c->cfg.nsteps);
+  }
+  if (nsteps == 0) return LBM_OK;
+  lbm_status s = dispatch<RunPrimal>(c, nsteps, (int)(record != 0));
+  if (record) {
+    c->rec_len = c->t;
+  } else {
+    c->rec_open = false;
+  }
+  return s;
+}
+
+lbm_status lbm_objective_async(lbm_ctx* c, double* J_dev) {
+  if (!c) return LBM_EINVAL;
+  if (c->adj_started) return fail(c, LBM_ESTATE, "objective: primal state consumed by the adjoint");
+  return dispatch<RunObjective>(c, J_dev);
+}
+
+lbm_status lbm_objective(lbm_ctx* c, double* J_host, double* globals_host) {
+  if (!c) return LBM_EINVAL;
+  if (c->adj_started) return fail(c, LBM_ESTATE, "objective: primal state consumed by the adjoint");
+  lbm_status s = dispatch<RunObjective>(c, (double*)nullptr);
+  if (s != LBM_OK) return s;
+  double h[kNG + 1];
+  hipError_t e = hipMemcpyAsync(h, c->glob, sizeof h, hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return fail(c, LBM_EHIP, "objective: %s", hipGetErrorString(e));
+  s = sync_check(c, "objective");
+  if (s != LBM_OK) return s;
+  if (J_host) *J_host = h[kNG];
+  if (globals_host) std::memcpy(globals_host, h, kNG * sizeof(double));
+  if (!std::isfinite(h[kNG])) return fail(c, LBM_ENONFINITE, "objective is not finite");
+  return LBM_OK;
+}
+
+lbm_status lbm_adjoint_steps(lbm_ctx* c, int64_t nsteps) {
+  if (!c) return LBM_EINVAL;
+  if (nsteps < 0) return fail(c, LBM_EINVAL, "adjoint_steps: negative count");
+  if (!c->adj_started) {
+    if (!c->design_set) return fail(c, LBM_ESTATE, "adjoint_steps: no design field set");
+    if (!(c->rec_open && c->t == c->rec_len))
+      return fail(c, LBM_ESTATE, "adjoint_steps: needs a recorded run ending at the current time");
+    if (nsteps > c->rec_len) return fail(c, LBM_EINVAL, "adjoint_steps: more steps than recorded");
+  } else if (nsteps > c->t_adj) {
+    return fail(c, LBM_EINVAL, "adjoint_steps: only %lld steps remain", (long long)c->t_adj);
+  }
+  return dispatch<RunAdjoint>(c, nsteps);
+}
+
+lbm_status lbm_gradient(lbm_ctx* c, void* grad_dev) {
+  if (!c) return LBM_EINVAL;
+  if (!grad_dev) return fail(c, LBM_EINVAL, "gradient: NULL output");
+  if (!(c->adj_started && c->t_adj == 0)) return fail(c, LBM_ESTATE, "gradient: adjoint has not reached t = 0");
+  return dispatch<RunGradient>(c, grad_dev);
+}
+
+lbm_status lbm_fields(lbm_ctx* c, double* rho_dev, double* u_dev, double* s_dev) {
+  if (!c) return LBM_EINVAL;
+  if (!rho_dev || !u_dev) return fail(c, LBM_EINVAL, "fields: NULL output");
+  if (c->adj_started) return fail(c, LBM_ESTATE, "fields: primal state consumed by the adjoint");
+  return dispatch<RunFields>(c, rho_dev, u_dev, s_dev);
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, double* f_dev, double* g_dev) {
+  if (!c) return LBM_EINVAL;
+  if (!f_dev) return fail(c, LBM_EINVAL, "get_state: NULL output");
+  if (c->adj_started) return fail(c, LBM_ESTATE, "get_state: primal state consumed by the adjoint");
+  return dispatch<RunGetState>(c, f_dev, g_dev);
+}
+
+lbm_status lbm_get_adjoint(lbm_ctx* c, double* lf_dev, double* lg_dev) {
+  if (!c) return LBM_EINVAL;
+  if (!lf_dev) return fail(c, LBM_EINVAL, "get_adjoint: NULL output");
+  if (!c->adj_started) return fail(c, LBM_ESTATE, "get_adjoint: adjoint not seeded");
+  return dispatch<RunGetAdjoint>(c, lf_dev, lg_dev);
+}
+
+lbm_status lbm_export_maps(lbm_ctx* c, uint8_t* mask_dev, int64_t* src_dev) {
+  if (!c) return LBM_EINVAL;
+  return dispatch<RunMaps>(c, mask_dev, src_dev);
+}
+
+lbm_status lbm_times(const lbm_ctx* c, int64_t* t, int64_t* recorded, int64_t* t_adj) {
+  if (!c) return LBM_EINVAL;
+  if (t) *t = c->t;
+  if (recorded) *recorded = c->rec_len;
+  if (t_adj) *t_adj = c->adj_started ? c->t_adj : -1;
+  return LBM_OK;
+}
+
+lbm_status lbm_plan(const lbm_ctx* c, int64_t* interval, int64_t* n_checkpoints, int64_t* n_ring,
+                    uint64_t* state_bytes) {
+  if (!c) return LBM_EINVAL;
+  if (interval) *interval = c->plan.C;
+  if (n_checkpoints) *n_checkpoints = c->plan.S;
+  if (n_ring) *n_ring = std::max<int64_t>(c->plan.C - 1, 0);
+  if (state_bytes) *state_bytes = c->plan.state_bytes;
+  return LBM_OK;
+}
+
+lbm_status lbm_primal_steps_batch(lbm_ctx* const* ctxs, int32_t n, int64_t nsteps, int32_t record) {
+  (void)ctxs;
+  (void)n;
+  (void)nsteps;
+  (void)record;
+  return LBM_EINVAL;
+}
+
+lbm_status lbm_adjoint_steps_batch(lbm_ctx* const* ctxs, int32_t n, int64_t nsteps) {
+  (void)ctxs;
+  (void)n;
+  (void)nsteps;
+  return LBM_EINVAL;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+const char* lbm_status_string(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "workspace too small";
+    case LBM_EHIP: return "HIP error";
+    case LBM_ESTATE: return "invalid state";
+    case LBM_ENONFINITE: return "non-finite objective";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+"""Host-only checks of the C ABI: the library loads, exports every function the
+header declares, and validates configurations (no GPU work is issued)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1501_04741_amd import build as hipbuild
+from paper_1501_04741_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(hipbuild.LIB):
+        hipbuild.build(force=False)
+    return lbm.library()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lbm_adj.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "lbm_primal_steps" in names and "lbm_adjoint_steps" in names and "lbm_gradient" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_config_struct_size_matches(lib):
+    cfg = lbm.make_config(dict(flow=9, nx=16, ny=8), 10)
+    assert cfg.struct_size == ctypes.sizeof(lbm.LbmConfig) == 160
+    bad = lbm.make_config(dict(flow=9, nx=16, ny=8), 10)
+    bad.struct_size = 150
+    out = ctypes.c_uint64()
+    assert lib.lbm_required_bytes(ctypes.byref(bad), ctypes.byref(out)) == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("params,ok", [
+    (dict(flow=9, nx=16, ny=8), True),
+    (dict(flow=9, nx=16, ny=8, nz=2), False),          # 2D needs nz = 1
+    (dict(flow=19, nx=16, ny=8, nz=2), False),         # 3D needs nz >= 3
+    (dict(flow=19, scalar=5, nx=16, ny=8, nz=4), False),
+    (dict(flow=9, scalar=7, nx=16, ny=8), False),
+    (dict(flow=9, nx=2, ny=8), False),
+    (dict(flow=9, nx=16, ny=8, tau=0.5), False),
+    (dict(flow=9, nx=16, ny=8, switch_fn="ramp", switch_param=0.0), False),
+    (dict(flow=9, nx=16, ny=8, u_in=1.0), False),
+    (dict(flow=19, scalar=7, nx=16, ny=8, nz=6), True),
+])
+def test_config_validation(lib, params, ok):
+    cfg = lbm.make_config(params, 10)
+    out = ctypes.c_uint64()
+    st = lib.lbm_required_bytes(ctypes.byref(cfg), ctypes.byref(out))
+    assert (st == lbm.LBM_OK) == ok
+
+
+def _bytes(params, nsteps, **kw):
+    return lbm.lbm_required_bytes(lbm.make_config(params, nsteps, **kw))
+
+
+def test_checkpoint_plan_sizes(lib):
+    p = dict(flow=19, nx=256, ny=128, nz=128)
+    state = 19 * 256 * 128 * 128 * 4
+    total = _bytes(p, 2000)                      # C = 45, S = 45: 45 + 44 + 4 states
+    assert abs(total - 93 * state) < 0.01 * state + 64 * 2**20
+    # a budget that holds everything stores all steps (C = N: 1 + 1999 + 4 states)
+    big = _bytes(p, 2000, hbm_budget_bytes=10**15)
+    assert abs(big - 2004 * state) < 0.01 * state + 64 * 2**20
+    # a budget between picks the largest interval that fits
+    mid = _bytes(p, 2000, hbm_budget_bytes=200 * state)
+    assert mid <= 200 * state
+    # a budget below the sqrt plan is refused
+    cfg = lbm.make_config(p, 2000, hbm_budget_bytes=50 * state)
+    out = ctypes.c_uint64()
+    assert lib.lbm_required_bytes(ctypes.byref(cfg), ctypes.byref(out)) == lbm.LBM_ENOMEM
+    # explicit interval
+    c500 = _bytes(dict(flow=9, scalar=5, nx=512, ny=256), 20000, checkpoint_interval=500)
+    st2 = 14 * 512 * 256 * 4
+    assert abs(c500 - (40 + 499 + 4) * st2) < 0.01 * st2 + 2**20
