@@ -1,0 +1,209 @@
+"""Benchmark: one design evaluation (J and dJ/dw) of the adjoint LBM hot path.
+
+A bench step is the whole hot path over one design field: set the design,
+reset, N recorded primal steps, objective, N adjoint steps (with segment
+recomputes from checkpoints) and the gradient export.  Default workload: the
+D3Q19 Brinkman channel 256x128x128 (4.19M nodes), N = 2000, FP32.
+
+Prints ONE JSON line.  ``value`` is the gradient-evaluation throughput in
+MLUPS: lattice nodes x primal steps differentiated per second (forward,
+recompute and adjoint all inside the timed region).  Kernel-level figures
+come from HIP events recorded on the library's stream inside the timed steps:
+the primal kernel over the N forward launches, the adjoint kernel over the
+launches of the last trajectory segment (which needs no recompute).
+
+Only one GPU is supported: ``--gpus N`` with N > 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "primal/adjoint MLUPS + HBM roofline frac; served gradients/s, p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def _class_counts(p):
+    """Node counts per class for a channel (interior, wall, inlet, outlet)."""
+    nx, ny, nz = p["nx"], p["ny"], p["nz"]
+    if p.get("periodic"):
+        return nx * ny * nz, 0, 0, 0
+    rows_fluid = (ny - 2) * (nz - 2 if p["flow"] == 19 else 1)
+    rows_total = ny * nz
+    wall = (rows_total - rows_fluid) * nx
+    return rows_fluid * (nx - 2), wall, rows_fluid, rows_fluid
+
+
+def algorithmic_bytes(p, precision):
+    """Bytes one primal launch and one adjoint launch must move, by node class.
+
+    primal:  interior 2*Qt*s + s (pull Qt, store Qt, read w); other classes 2*Qt*s
+    adjoint: interior 3*Qt*s + 3s (primal pull, cotangent pull, store, w, grad
+             read+write); outlet 3*Qt*s; inlet and wall 2*Qt*s (their transposed
+             Jacobians do not depend on the primal state)."""
+    s = 4 if precision == "fp32" else 8
+    qt = p["flow"] + p.get("scalar", 0)
+    ni, nw, nin, nout = _class_counts(p)
+    primal = ni * (2 * qt * s + s) + (nw + nin + nout) * 2 * qt * s
+    adjoint = ni * (3 * qt * s + 3 * s) + nout * 3 * qt * s + (nw + nin) * 2 * qt * s
+    return primal, adjoint
+
+
+def cpu_baseline(p, w64, steps):
+    import oracle
+    cores = oracle.threads()
+    t0 = time.perf_counter()
+    oracle.adjoint(p, w64, steps)
+    dt = time.perf_counter() - t0
+    n = p["nx"] * p["ny"] * p["nz"]
+    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "%dx%dx%d D3Q19 grid, %d primal + %d adjoint steps of the FP64 oracle (adjoint by complex-step "
+                      "local Jacobians), %.1f s" % (p["nx"], p["ny"], p["nz"], steps, steps, dt)}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="d3q19_channel_256x128x128")
+    ap.add_argument("--lbm-steps", type=int, default=None, help="override the primal horizon N")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
+                    help="also run one device copy of MB megabytes (counter calibration for profiles)")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (the hot path runs on a single MI355X; no multi-GPU path is "
+              "built): run with --gpus 1", file=sys.stderr)
+        return 2
+    if args.steps < 1 or args.warmup < 0:
+        print("need --steps >= 1 and --warmup >= 0", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1501_04741_amd import inputs
+    from paper_1501_04741_amd.lbm import Lbm, lbm_objective_async
+
+    wl = inputs.workload(args.workload)
+    if args.lbm_steps:
+        wl["steps"] = args.lbm_steps
+    p = inputs.model_params(wl)
+    N = int(wl["steps"])
+    prec = wl["precision"]
+    print("[bench] workload %s, N=%d, %s; building context" % (args.workload, N, prec), file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L = Lbm(p, nsteps=N, precision=prec, checkpoint_interval=wl.get("checkpoint_interval", 0), device=dev)
+    plan = L.plan()
+    C = plan["interval"]
+    k_last = N - ((N - 1) // C) * C  # adjoint steps of the last segment (in the ring, no recompute)
+    w_np = inputs.design_for(wl)
+    w = torch.from_numpy(w_np).to(dev)
+    grad = torch.empty(L.N, dtype=L.dtype, device=dev)
+    J_dev = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def one(ev):
+        L.set_design(w)
+        L.reset()
+        ev[0].record()
+        L.primal_steps(N, record=True)
+        ev[1].record()
+        lbm_objective_async(L.ctx, J_dev)
+        L.adjoint_steps(1)  # seeds lambda^N, zeroes the gradient, first reverse step
+        ev[2].record()
+        if k_last > 1:
+            L.adjoint_steps(k_last - 1)
+        ev[3].record()
+        L.adjoint_steps(N - k_last)
+        ev[4].record()
+        L.gradient(out=grad)
+
+    mk = lambda: [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    for i in range(args.warmup):
+        one(mk())
+    torch.cuda.synchronize()
+    print("[bench] warmup done; timing %d steps" % args.steps, file=sys.stderr, flush=True)
+    evs = [mk() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one(evs[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    adj_seg_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in evs])) if k_last > 1 else float("nan")
+    bwd_ms = float(np.mean([e[1].elapsed_time(e[4]) for e in evs]))
+    primal_launch_ms = fwd_ms / N
+    adjoint_launch_ms = adj_seg_ms / (k_last - 1) if k_last > 1 else float("nan")
+    J = float(J_dev.item())
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe * 2**20 // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    nodes = L.N
+    pb, ab = algorithmic_bytes(p, prec)
+    prim_gbs = pb / (primal_launch_ms * 1e-3) / 1e9
+    adj_gbs = ab / (adjoint_launch_ms * 1e-3) / 1e9 if k_last > 1 else None
+    rec = {
+        "metric": METRIC,
+        "value": nodes * N / (ms_per_step * 1e-3) / 1e6,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "lattice": "D3Q19" if p["flow"] == 19 else "D2Q9",
+                   "scalar": p.get("scalar", 0), "grid": [p["nx"], p["ny"], p["nz"]], "nodes": nodes,
+                   "lbm_steps": N, "precision": prec, "checkpoint_interval": C,
+                   "checkpoints": plan["checkpoints"], "ring_slots": plan["ring"],
+                   "workspace_gb": round(L.workspace_bytes / 1e9, 3), "switch": "%s(%g)" % (p["switch_fn"],
+                                                                                          p["switch_param"])},
+        "value_definition": "nodes x primal steps differentiated per second: one step = design set, "
+                            "recorded forward, objective, adjoint with recompute, gradient",
+        "J": J,
+        "gradients_per_s": 1e3 / ms_per_step,
+        "primal_mlups": nodes / (primal_launch_ms * 1e-3) / 1e6,
+        "adjoint_kernel_mlups": (nodes / (adjoint_launch_ms * 1e-3) / 1e6) if k_last > 1 else None,
+        "backward_mlups": nodes * N / (bwd_ms * 1e-3) / 1e6,
+        "forward_ms": fwd_ms,
+        "backward_ms": bwd_ms,
+        "roofline": {"bound": "hbm", "kernel": "k_primal<19,0,float>", "achieved": prim_gbs, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": prim_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": pb, "avg_launch_us": primal_launch_ms * 1e3},
+        "roofline_adjoint": {"bound": "hbm", "kernel": "k_adjoint<19,0,float>", "achieved": adj_gbs,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": (adj_gbs / HBM_PEAK_GBS) if adj_gbs else None, "traffic": None,
+                             "bytes_per_launch": ab,
+                             "avg_launch_us": adjoint_launch_ms * 1e3 if k_last > 1 else None},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] GPU timing done; timing the CPU oracle sample", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(p, w_np.astype(np.float64), args.cpu_steps)
+    else:
+        rec["cpu_baseline"] = None
+    L.close()
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,84 @@
+"""The primal/adjoint pair as a ``torch.autograd.Function``.
+
+forward(w)   -> J: records N primal steps of the library (checkpoints every C
+                steps plus a ring of C - 1 states, sized to the workspace) and
+                evaluates the objective on the device (no host sync).
+backward(gJ) -> gJ * dJ/dw: the hand-written adjoint kernel, run N reverse
+                steps with segment recomputes from the checkpoints
+                (theorem of Section 2.2, unsteady form), then the gradient.
+
+The context (``Lbm``) holds one recorded trajectory at a time: a second
+forward on the same context before the first one's backward raises.
+"""
+from __future__ import annotations
+
+import torch
+
+from .lbm import Lbm, lbm_objective_async
+
+
+class LbmObjective(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, w: torch.Tensor, solver: "LbmSolver"):
+        L = solver.lbm
+        if solver._pending:
+            raise RuntimeError("LbmObjective: a previous forward on this solver has not been back-propagated")
+        L.set_design(w.detach().reshape(-1))
+        L.reset()
+        L.primal_steps(solver.nsteps, record=True)
+        J = torch.empty(1, dtype=torch.float64, device=L.device)
+        lbm_objective_async(L.ctx, J)
+        solver._pending = True
+        ctx.solver = solver
+        ctx.w_shape = w.shape
+        ctx.w_dtype = w.dtype
+        return J.reshape(())
+
+    @staticmethod
+    def backward(ctx, gJ):
+        solver = ctx.solver
+        L = solver.lbm
+        try:
+            L.adjoint_steps(solver.nsteps)
+            g = L.gradient()
+        finally:
+            solver._pending = False
+        grad_w = (gJ.to(g.dtype) * g).reshape(ctx.w_shape).to(ctx.w_dtype)
+        return grad_w, None
+
+
+class LbmSolver:
+    """Owns one GPU context sized for ``nsteps`` and exposes J(w) as a
+    differentiable function: ``J = solver(w); J.backward()``."""
+
+    def __init__(self, params: dict, nsteps: int, precision: str = "fp32", checkpoint_interval: int = 0,
+                 hbm_budget_bytes: int = 0, device=None, differentiable: bool = True):
+        """differentiable=False sizes the workspace for unrecorded forwards only
+        (five states instead of the checkpoint plan); such a solver offers value()."""
+        self.nsteps = int(nsteps)
+        self.differentiable = differentiable
+        self.lbm = Lbm(params, nsteps=self.nsteps if differentiable else 0, precision=precision,
+                       checkpoint_interval=checkpoint_interval, hbm_budget_bytes=hbm_budget_bytes, device=device)
+        self._pending = False
+
+    @property
+    def dtype(self):
+        return self.lbm.dtype
+
+    def __call__(self, w: torch.Tensor) -> torch.Tensor:
+        if not self.differentiable:
+            raise RuntimeError("LbmSolver built with differentiable=False offers value() only")
+        return LbmObjective.apply(w, self)
+
+    def value(self, w: torch.Tensor) -> float:
+        """J(w) only (unrecorded forward, synchronises)."""
+        L = self.lbm
+        if self._pending:
+            raise RuntimeError("LbmSolver.value: a recorded forward is waiting for its backward")
+        L.set_design(torch.as_tensor(w).reshape(-1))
+        L.reset()
+        L.primal_steps(self.nsteps, record=False)
+        return L.objective()[0]
+
+    def close(self):
+        self.lbm.close()

@@ -5,7 +5,7 @@
 // the caller's workspace.  Workspace layout (each slice 256-byte aligned):
 //   w        N x Real      design field (copied in by lbm_set_design)
 //   grad     N x Real      dJ/dw accumulator
-//   glob     16 doubles    boundary sums + J of the last objective evaluation
+//   glob     boundary sums + J of the last objective evaluation, objective partials
 //   desc     batch descriptor table (kMaxBatch entries)
 //   lam[2]   2 states      adjoint ping-pong
 //   pp[2]    2 states      primal ping-pong (unrecorded steps, final state)
@@ -39,6 +39,13 @@ namespace {
 
 constexpr uint64_t kAlign = 256;
 constexpr int kMaxBatch = 64;
+// Streaming stores bypass the caches when two primal states (what one step
+// reads and writes) exceed the 256 MB last-level cache; below that, plain
+// stores let the next step re-read the state from that cache.
+constexpr uint64_t kLastLevelCacheBytes = 256ull << 20;
+// glob region: kGlobSlots doubles of results, then the objective partial sums.
+constexpr int kGlobSlots = 16;
+constexpr uint64_t kGlobBytes = (kGlobSlots + kObjBlocks * kNG) * sizeof(double);
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -133,7 +140,7 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
 
 uint64_t plan_total(const Plan& p, int64_t C, int64_t S) {
   (void)C;
-  uint64_t t = 2 * p.node_bytes + align_up(16 * sizeof(double)) + align_up(kMaxBatch * 256);
+  uint64_t t = 2 * p.node_bytes + align_up(kGlobBytes) + align_up(kMaxBatch * 256);
   t += (uint64_t)(2 + 2 + S + std::max<int64_t>(C - 1, 0)) * p.state_bytes;
   return t;
 }
@@ -232,14 +239,22 @@ template <int Q, int QS, typename Real>
 struct Ops {
   static Params<Real> P(lbm_ctx* c) { return make_params<Real>(c->cfg, c->plan.N); }
 
+  static bool nt(lbm_ctx* c) { return 2 * c->plan.state_bytes > kLastLevelCacheBytes; }
   static void primal(lbm_ctx* c, const void* src, void* dst) {
     Geo g = node_geometry(c->cfg);
-    hipLaunchKernelGGL((k_primal<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src, (Real*)dst,
-                       (const Real*)c->w);
+    if (nt(c))
+      hipLaunchKernelGGL((k_primal<Q, QS, Real, true>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
+                         (Real*)dst, (const Real*)c->w);
+    else
+      hipLaunchKernelGGL((k_primal<Q, QS, Real, false>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
+                         (Real*)dst, (const Real*)c->w);
   }
   static void objective(lbm_ctx* c, const void* src, double* out) {
-    hipLaunchKernelGGL((k_objective<Q, QS, Real>), dim3(1), dim3(kObjThreads), 0, c->stream, P(c),
-                       (const Real*)src, out);
+    double* part = c->glob + kGlobSlots;
+    hipLaunchKernelGGL((k_objective_partial<Q, QS, Real>), dim3(kObjBlocks), dim3(kObjThreads), 0, c->stream, P(c),
+                       (const Real*)src, part);
+    hipLaunchKernelGGL((k_objective_final<Q, QS, Real>), dim3(1), dim3(64), 0, c->stream, P(c),
+                       (const double*)part, out);
   }
   static void seed(lbm_ctx* c, const void* src, void* lam) {
     Geo g = node_geometry(c->cfg);
@@ -248,8 +263,16 @@ struct Ops {
   }
   static void adjoint(lbm_ctx* c, const void* prim, const void* lin, void* lout) {
     Geo g = node_geometry(c->cfg);
-    hipLaunchKernelGGL((k_adjoint<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)prim,
-                       (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
+    if (nt(c))
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true>), g.grid, g.block, 0, c->stream, P(c), (const Real*)prim,
+                         (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
+    else
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false>), g.grid, g.block, 0, c->stream, P(c), (const Real*)prim,
+                         (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
+  }
+  static void get_adjoint(lbm_ctx* c, const void* lam, double* lf, double* lg) {
+    Geo g = node_geometry(c->cfg);
+    hipLaunchKernelGGL((k_get_adjoint<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)lam, lf, lg);
   }
   static void fields(lbm_ctx* c, const void* src, double* rho, double* u, double* s) {
     Geo g = node_geometry(c->cfg);
@@ -272,9 +295,6 @@ struct Ops {
   }
   static void copy(lbm_ctx* c, const void* a, void* b, size_t n) {
     hipLaunchKernelGGL((k_copy<Real>), flat_grid(n), dim3(256), 0, c->stream, (const Real*)a, (Real*)b, n);
-  }
-  static void to_double(lbm_ctx* c, const void* a, double* b, size_t n) {
-    hipLaunchKernelGGL((k_to_double<Real>), flat_grid(n), dim3(256), 0, c->stream, (const Real*)a, b, n);
   }
 };
 
@@ -412,10 +432,7 @@ struct RunGetState {
 template <class O>
 struct RunGetAdjoint {
   static lbm_status run(lbm_ctx* c, double* lf, double* lg) {
-    const size_t n = (size_t)c->plan.N;
-    const char* base = (const char*)c->lam[c->lam_cur];
-    O::to_double(c, base, lf, (size_t)c->plan.Q * n);
-    if (lg && c->plan.QS) O::to_double(c, base + (size_t)c->plan.Q * n * c->plan.rs, lg, (size_t)c->plan.QS * n);
+    O::get_adjoint(c, c->lam[c->lam_cur], lf, c->plan.QS ? lg : nullptr);
     return launch_check(c, "get_adjoint");
   }
 };
@@ -492,7 +509,7 @@ lbm_status lbm_create(const lbm_config* cfg, void* hip_stream, void* workspace_d
   c->grad = q;
   q += p.node_bytes;
   c->glob = (double*)q;
-  q += align_up(16 * sizeof(double));
+  q += align_up(kGlobBytes);
   c->desc = q;
   q += align_up(kMaxBatch * 256);
   for (int i = 0; i < 2; ++i) {
