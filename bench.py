@@ -68,6 +68,65 @@ def cpu_baseline(p, w64, steps):
                       "local Jacobians), %.1f s" % (p["nx"], p["ny"], p["nz"], steps, steps, dt)}
 
 
+def serve_main(args):
+    """Replays a Poisson trace through the continuous-batching server and, on the
+    same GPU, one request at a time (FIFO, no overlap); prints one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_1501_04741_amd import inputs
+    from paper_1501_04741_amd.serve import GpuExecutor, Job, Server, run_one_at_a_time, summarize
+
+    trace = inputs.poisson_trace(args.requests, args.rate, seed=1, steps=args.serve_steps)
+
+    def jobs():
+        return [Job(rid=r.rid, params=r.params, steps=r.steps, design=inputs.request_design(r),
+                    precision="fp32", arrival=r.arrival_s) for r in trace]
+
+    torch.cuda.set_device(0)
+    # warm-up: one small request through both paths (kernel loading, allocator)
+    warm = jobs()[:2]
+    for j in warm:
+        j.arrival = 0.0
+    Server(GpuExecutor(), int(args.budget_gb * 2**30), quantum=args.quantum).replay(warm, realtime=False)
+    torch.cuda.synchronize()
+    print("[bench] serving %d requests at %.1f/s" % (args.requests, args.rate), file=sys.stderr, flush=True)
+    srv = Server(GpuExecutor(), int(args.budget_gb * 2**30), quantum=args.quantum)
+    served = srv.replay(jobs(), realtime=True)
+    s_batched = summarize(served)
+    s_batched["max_concurrent_gb"] = None
+    rec = {
+        "metric": "served gradients/s, p50/p99 ms",
+        "value": s_batched.get("gradients_per_s"),
+        "unit": "gradients/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "poisson_trace", "requests": args.requests, "rate_per_s": args.rate,
+                   "sizes": ["D2Q9 256x128", "D2Q9 1024x512", "D3Q19 96x48x48", "D3Q19 192x96x96"],
+                   "steps": args.serve_steps, "quantum": args.quantum, "budget_gb": args.budget_gb,
+                   "trace_seed": 1},
+        "serving": s_batched,
+        "scheduler": dict(srv.stats),
+    }
+    if not args.no_baseline:
+        print("[bench] one-at-a-time replay", file=sys.stderr, flush=True)
+        base = run_one_at_a_time(jobs())
+        rec["one_at_a_time"] = summarize(base)
+        bg = rec["one_at_a_time"].get("gradients_per_s")
+        rec["speedup_vs_one_at_a_time"] = (s_batched["gradients_per_s"] / bg) if bg else None
+        by_id = {j.rid: j for j in base}
+        dj = [abs(j.J - by_id[j.rid].J) / max(abs(by_id[j.rid].J), 1e-300) for j in served if j.rid in by_id]
+        dg = [np.linalg.norm(j.grad - by_id[j.rid].grad) / max(np.linalg.norm(by_id[j.rid].grad), 1e-300)
+              for j in served if j.rid in by_id and j.grad is not None]
+        rec["served_vs_alone"] = {"max_rel_J": float(max(dj)) if dj else None,
+                                  "max_rel_l2_grad": float(max(dg)) if dg else None}
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,7 +138,17 @@ def main(argv=None):
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run one device copy of MB megabytes (counter calibration for profiles)")
+    ap.add_argument("--serve", action="store_true",
+                    help="measure the serving loop on a Poisson request trace instead (own JSON line)")
+    ap.add_argument("--requests", type=int, default=400)
+    ap.add_argument("--rate", type=float, default=20.0, help="mean arrivals per second")
+    ap.add_argument("--serve-steps", type=int, default=2000, help="primal (= adjoint) steps per request")
+    ap.add_argument("--budget-gb", type=float, default=240.0, help="HBM budget for admitted requests")
+    ap.add_argument("--quantum", type=int, default=50, help="steps per request per scheduling tick")
+    ap.add_argument("--no-baseline", action="store_true", help="skip the one-at-a-time replay")
     args = ap.parse_args(argv)
+    if args.serve and args.gpus == 1:
+        return serve_main(args)
 
     if args.gpus != 1:
         print("bench.py measures one GPU only (the hot path runs on a single MI355X; no multi-GPU path is "

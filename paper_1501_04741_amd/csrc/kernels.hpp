@@ -872,6 +872,75 @@ __global__ __launch_bounds__(256) void k_get_adjoint(Params<Real> p, const Real*
   }
 }
 
+// --------------------------------------------------------- batched launches
+// One launch advances many contexts of the same (Q, QS, Real) by one step.
+// Blocks are one wave wide (64 x-nodes of one row); block b belongs to the
+// context k with start[k] <= b < start[k+1].  The per-node code is the same
+// device function as in the single-context kernels, so results are bitwise
+// identical to them.
+constexpr int kBatchMax = 32;
+constexpr int kBatchBX = 64;
+
+// Per-context constants, stored once in the context's own workspace.
+template <typename Real>
+struct BatchStatic {
+  Params<Real> p;
+  const Real* w;
+  Real* grad;
+  int gx;  // blocks per row: ceil(nx / kBatchBX)
+  int nt;  // non-temporal stores
+};
+
+// Per-launch arguments, passed by value (about 1.2 KB for kBatchMax = 32).
+template <typename Real>
+struct BatchArgs {
+  int n;
+  int start[kBatchMax + 1];
+  const BatchStatic<Real>* st[kBatchMax];
+  const Real* a[kBatchMax];  // primal: source state; adjoint: primal state h^{n-1}
+  const Real* b[kBatchMax];  // adjoint: lambda^{n+1}
+  Real* c[kBatchMax];        // primal: destination; adjoint: lambda^n
+};
+
+template <typename Real>
+__device__ __forceinline__ int batch_find(const BatchArgs<Real>& A, int blk) {
+  int k = 0;
+  while (k + 1 < A.n && blk >= A.start[k + 1]) ++k;
+  return k;
+}
+
+template <int Q, int QS, typename Real>
+__global__ __launch_bounds__(kBatchBX) void k_primal_batch(BatchArgs<Real> A) {
+  const int blk = blockIdx.x;
+  const int k = batch_find(A, blk);
+  const BatchStatic<Real>& S = *A.st[k];
+  const int lb = blk - A.start[k];
+  const int bx = lb % S.gx, row = lb / S.gx;
+  const int x = bx * kBatchBX + threadIdx.x;
+  if (x >= S.p.nx) return;
+  const int y = row % S.p.ny, z = row / S.p.ny;
+  if (S.nt)
+    primal_node<Q, QS, Real, true>(S.p, A.a[k], A.c[k], S.w, x, y, z);
+  else
+    primal_node<Q, QS, Real, false>(S.p, A.a[k], A.c[k], S.w, x, y, z);
+}
+
+template <int Q, int QS, typename Real>
+__global__ __launch_bounds__(kBatchBX) void k_adjoint_batch(BatchArgs<Real> A) {
+  const int blk = blockIdx.x;
+  const int k = batch_find(A, blk);
+  const BatchStatic<Real>& S = *A.st[k];
+  const int lb = blk - A.start[k];
+  const int bx = lb % S.gx, row = lb / S.gx;
+  const int x = bx * kBatchBX + threadIdx.x;
+  if (x >= S.p.nx) return;
+  const int y = row % S.p.ny, z = row / S.p.ny;
+  if (S.nt)
+    adjoint_node<Q, QS, Real, true>(S.p, A.a[k], A.b[k], A.c[k], S.w, S.grad, x, y, z);
+  else
+    adjoint_node<Q, QS, Real, false>(S.p, A.a[k], A.b[k], A.c[k], S.w, S.grad, x, y, z);
+}
+
 // ------------------------------------------------------- small helpers
 template <typename T>
 __global__ __launch_bounds__(256) void k_fill(T* __restrict__ a, size_t n, T v) {

@@ -6,7 +6,7 @@
 //   w        N x Real      design field (copied in by lbm_set_design)
 //   grad     N x Real      dJ/dw accumulator
 //   glob     boundary sums + J of the last objective evaluation, objective partials
-//   desc     batch descriptor table (kMaxBatch entries)
+//   desc     this context's batch descriptor (constants for batched launches)
 //   lam[2]   2 states      adjoint ping-pong
 //   pp[2]    2 states      primal ping-pong (unrecorded steps, final state)
 //   ckpt[S]  S states      checkpoints h^{sC-1}, s = 0..S-1 (ckpt[0] = h^{-1})
@@ -38,7 +38,7 @@ using namespace lbmk;
 namespace {
 
 constexpr uint64_t kAlign = 256;
-constexpr int kMaxBatch = 64;
+constexpr uint64_t kDescBytes = 1024;  // >= sizeof(BatchStatic<double>)
 // Streaming stores bypass the caches when two primal states (what one step
 // reads and writes) exceed the 256 MB last-level cache; below that, plain
 // stores let the next step re-read the state from that cache.
@@ -90,6 +90,8 @@ struct lbm_ctx {
   int lam_cur = 0;
   int64_t ring_seg = -1;  // trajectory segment currently held by the ring
   std::string err;
+  // host copy of the batch descriptor; stays alive while its upload is in flight
+  alignas(16) unsigned char host_desc[kDescBytes];
 };
 
 namespace {
@@ -140,7 +142,7 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
 
 uint64_t plan_total(const Plan& p, int64_t C, int64_t S) {
   (void)C;
-  uint64_t t = 2 * p.node_bytes + align_up(kGlobBytes) + align_up(kMaxBatch * 256);
+  uint64_t t = 2 * p.node_bytes + align_up(kGlobBytes) + align_up(kDescBytes);
   t += (uint64_t)(2 + 2 + S + std::max<int64_t>(C - 1, 0)) * p.state_bytes;
   return t;
 }
@@ -237,9 +239,33 @@ lbm_status launch_check(lbm_ctx* c, const char* what) {
 // Typed operations on one context.
 template <int Q, int QS, typename Real>
 struct Ops {
+  using RealT = Real;
+  static constexpr int kQ = Q, kQS = QS;
   static Params<Real> P(lbm_ctx* c) { return make_params<Real>(c->cfg, c->plan.N); }
+  static int batch_blocks(lbm_ctx* c) {
+    return (c->cfg.nx + kBatchBX - 1) / kBatchBX * c->cfg.ny * c->cfg.nz;
+  }
+  static void primal_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks) {
+    hipLaunchKernelGGL((k_primal_batch<Q, QS, Real>), dim3(blocks), dim3(kBatchBX), 0, st, A);
+  }
+  static void adjoint_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks) {
+    hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real>), dim3(blocks), dim3(kBatchBX), 0, st, A);
+  }
 
   static bool nt(lbm_ctx* c) { return 2 * c->plan.state_bytes > kLastLevelCacheBytes; }
+  static lbm_status write_static(lbm_ctx* c) {
+    static_assert(sizeof(BatchStatic<Real>) <= kDescBytes, "descriptor region too small");
+    BatchStatic<Real> h;
+    h.p = P(c);
+    h.w = (const Real*)c->w;
+    h.grad = (Real*)c->grad;
+    h.gx = (c->cfg.nx + kBatchBX - 1) / kBatchBX;
+    h.nt = nt(c) ? 1 : 0;
+    std::memcpy(c->host_desc, &h, sizeof h);
+    hipError_t e = hipMemcpyAsync(c->desc, c->host_desc, sizeof h, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return fail(c, LBM_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+    return LBM_OK;
+  }
   static void primal(lbm_ctx* c, const void* src, void* dst) {
     Geo g = node_geometry(c->cfg);
     if (nt(c))
@@ -362,19 +388,24 @@ void recompute_segment(lbm_ctx* c, int64_t s) {
   c->ring_seg = s;
 }
 
+// Seeds lambda^N = dJ/df^N and zeroes the gradient (first adjoint call).
+template <class O>
+void start_adjoint(lbm_ctx* c) {
+  const int64_t C = c->plan.C;
+  O::objective(c, c->cur, c->glob);
+  O::seed(c, c->cur, c->lam[0]);
+  O::fill(c, c->grad, (size_t)c->plan.N);
+  c->lam_cur = 0;
+  c->t_adj = c->rec_len;
+  c->ring_seg = c->rec_len > 0 ? (c->rec_len - 1) / C : -1;
+  c->adj_started = true;
+}
+
 template <class O>
 struct RunAdjoint {
   static lbm_status run(lbm_ctx* c, int64_t nsteps) {
     const int64_t C = c->plan.C;
-    if (!c->adj_started) {
-      O::objective(c, c->cur, c->glob);
-      O::seed(c, c->cur, c->lam[0]);
-      O::fill(c, c->grad, (size_t)c->plan.N);
-      c->lam_cur = 0;
-      c->t_adj = c->rec_len;
-      c->ring_seg = c->rec_len > 0 ? (c->rec_len - 1) / C : -1;
-      c->adj_started = true;
-    }
+    if (!c->adj_started) start_adjoint<O>(c);
     for (int64_t i = 0; i < nsteps; ++i) {
       const int64_t n = c->t_adj - 1;
       const int64_t s = n / C;
@@ -453,6 +484,131 @@ struct RunSetDesign {
   }
 };
 
+template <class O>
+struct RunWriteStatic {
+  static lbm_status run(lbm_ctx* c) { return O::write_static(c); }
+};
+
+// Batched primal steps: one launch per step covers every context.
+template <class O>
+struct RunPrimalBatch {
+  static lbm_status run(lbm_ctx* c0, lbm_ctx* const* cs, int n, int64_t nsteps, int record) {
+    using Real = typename O::RealT;
+    BatchArgs<Real> A;
+    std::memset(&A, 0, sizeof A);
+    A.n = n;
+    for (int64_t i = 0; i < nsteps; ++i) {
+      int total = 0;
+      for (int k = 0; k < n; ++k) {
+        lbm_ctx* c = cs[k];
+        void* dst = record ? rec_dst(c, c->t) : ((c->cur == c->pp[0]) ? c->pp[1] : c->pp[0]);
+        A.start[k] = total;
+        A.st[k] = (const BatchStatic<Real>*)c->desc;
+        A.a[k] = (const Real*)c->cur;
+        A.b[k] = nullptr;
+        A.c[k] = (Real*)dst;
+        total += O::batch_blocks(c);
+        c->cur = dst;
+        ++c->t;
+      }
+      A.start[n] = total;
+      O::primal_batch(c0->stream, A, total);
+    }
+    return launch_check(c0, "batched primal step");
+  }
+};
+
+// Batched adjoint steps.  Contexts that still have to be seeded are seeded
+// first; before each reverse step, the contexts whose next step lies in a
+// segment missing from their ring recompute it, batched together.
+template <class O>
+struct RunAdjointBatch {
+  static lbm_status run(lbm_ctx* c0, lbm_ctx* const* cs, int n, int64_t nsteps) {
+    using Real = typename O::RealT;
+    for (int k = 0; k < n; ++k)
+      if (!cs[k]->adj_started) start_adjoint<O>(cs[k]);
+    BatchArgs<Real> A;
+    std::memset(&A, 0, sizeof A);
+    for (int64_t i = 0; i < nsteps; ++i) {
+      // segment recomputes
+      lbm_ctx* need[kBatchMax];
+      int64_t first[kBatchMax], last[kBatchMax], seg[kBatchMax];
+      const void* src[kBatchMax];
+      int nn = 0;
+      int64_t longest = 0;
+      for (int k = 0; k < n; ++k) {
+        lbm_ctx* c = cs[k];
+        const int64_t C = c->plan.C;
+        const int64_t s = (c->t_adj - 1) / C;
+        if (s == c->ring_seg) continue;
+        need[nn] = c;
+        seg[nn] = s;
+        first[nn] = s * C;
+        last[nn] = std::min<int64_t>(s * C + C - 2, c->rec_len - 2);
+        src[nn] = ckpt_slot(c, s);
+        longest = std::max<int64_t>(longest, last[nn] - first[nn] + 1);
+        ++nn;
+      }
+      for (int64_t r = 0; r < longest; ++r) {
+        int m = 0, total = 0;
+        for (int q = 0; q < nn; ++q) {
+          const int64_t kk = first[q] + r;
+          if (kk > last[q]) continue;
+          lbm_ctx* c = need[q];
+          void* dst = ring_slot(c, kk + 1 - seg[q] * c->plan.C);
+          A.start[m] = total;
+          A.st[m] = (const BatchStatic<Real>*)c->desc;
+          A.a[m] = (const Real*)src[q];
+          A.b[m] = nullptr;
+          A.c[m] = (Real*)dst;
+          total += O::batch_blocks(c);
+          src[q] = dst;
+          ++m;
+        }
+        A.n = m;
+        A.start[m] = total;
+        O::primal_batch(c0->stream, A, total);
+      }
+      for (int q = 0; q < nn; ++q) need[q]->ring_seg = seg[q];
+      // one reverse step for every context
+      int total = 0;
+      A.n = n;
+      for (int k = 0; k < n; ++k) {
+        lbm_ctx* c = cs[k];
+        const int64_t C = c->plan.C;
+        const int64_t nstep = c->t_adj - 1;
+        const int64_t s = nstep / C, r = nstep - s * C;
+        A.start[k] = total;
+        A.st[k] = (const BatchStatic<Real>*)c->desc;
+        A.a[k] = (const Real*)((r == 0) ? ckpt_slot(c, s) : ring_slot(c, r));
+        A.b[k] = (const Real*)c->lam[c->lam_cur];
+        A.c[k] = (Real*)c->lam[1 - c->lam_cur];
+        total += O::batch_blocks(c);
+        c->lam_cur ^= 1;
+        --c->t_adj;
+      }
+      A.start[n] = total;
+      O::adjoint_batch(c0->stream, A, total);
+    }
+    return launch_check(c0, "batched adjoint step");
+  }
+};
+
+// Checks shared by every batched call: same lattice/precision/stream, distinct.
+lbm_status check_batch(lbm_ctx* const* cs, int32_t n) {
+  if (!cs || n < 1 || n > kBatchMax) return LBM_EINVAL;
+  for (int k = 0; k < n; ++k) {
+    if (!cs[k]) return LBM_EINVAL;
+    for (int q = 0; q < k; ++q)
+      if (cs[q] == cs[k]) return fail(cs[0], LBM_EINVAL, "batch: context %d appears twice", k);
+    const lbm_config &a = cs[0]->cfg, &b = cs[k]->cfg;
+    if (a.flow != b.flow || a.scalar != b.scalar || a.precision != b.precision)
+      return fail(cs[0], LBM_EINVAL, "batch: context %d has another lattice or precision", k);
+    if (cs[k]->stream != cs[0]->stream) return fail(cs[0], LBM_EINVAL, "batch: context %d uses another stream", k);
+  }
+  return LBM_OK;
+}
+
 void reset_times(lbm_ctx* c) {
   c->t = 0;
   c->rec_len = 0;
@@ -511,7 +667,7 @@ lbm_status lbm_create(const lbm_config* cfg, void* hip_stream, void* workspace_d
   c->glob = (double*)q;
   q += align_up(kGlobBytes);
   c->desc = q;
-  q += align_up(kMaxBatch * 256);
+  q += align_up(kDescBytes);
   for (int i = 0; i < 2; ++i) {
     c->lam[i] = q;
     q += p.state_bytes;
@@ -526,6 +682,7 @@ lbm_status lbm_create(const lbm_config* cfg, void* hip_stream, void* workspace_d
   q += (uint64_t)std::max<int64_t>(p.C - 1, 0) * p.state_bytes;
   reset_times(c);
   s = dispatch<RunReset>(c);
+  if (s == LBM_OK) s = dispatch<RunWriteStatic>(c);
   if (s != LBM_OK) {
     delete c;
     return s;
@@ -679,18 +836,50 @@ lbm_status lbm_plan(const lbm_ctx* c, int64_t* interval, int64_t* n_checkpoints,
 }
 
 lbm_status lbm_primal_steps_batch(lbm_ctx* const* ctxs, int32_t n, int64_t nsteps, int32_t record) {
-  (void)ctxs;
-  (void)n;
-  (void)nsteps;
-  (void)record;
-  return LBM_EINVAL;
+  lbm_status s = check_batch(ctxs, n);
+  if (s != LBM_OK) return s;
+  lbm_ctx* c0 = ctxs[0];
+  if (nsteps < 0) return fail(c0, LBM_EINVAL, "primal_steps_batch: negative count");
+  for (int k = 0; k < n; ++k) {
+    lbm_ctx* c = ctxs[k];
+    if (!c->design_set) return fail(c0, LBM_ESTATE, "primal_steps_batch: context %d has no design", k);
+    if (c->adj_started) return fail(c0, LBM_ESTATE, "primal_steps_batch: context %d is in its adjoint", k);
+    if (record && !(c->rec_open && c->t == c->rec_len))
+      return fail(c0, LBM_ESTATE, "primal_steps_batch: context %d cannot continue recording", k);
+    if (record && c->t + nsteps > c->cfg.nsteps)
+      return fail(c0, LBM_EINVAL, "primal_steps_batch: context %d would exceed its horizon", k);
+  }
+  if (nsteps == 0) return LBM_OK;
+  s = dispatch<RunPrimalBatch>(c0, ctxs, (int)n, nsteps, (int)(record != 0));
+  for (int k = 0; k < n; ++k) {
+    if (record) ctxs[k]->rec_len = ctxs[k]->t;
+    else ctxs[k]->rec_open = false;
+  }
+  return s;
 }
 
 lbm_status lbm_adjoint_steps_batch(lbm_ctx* const* ctxs, int32_t n, int64_t nsteps) {
-  (void)ctxs;
-  (void)n;
-  (void)nsteps;
-  return LBM_EINVAL;
+  lbm_status s = check_batch(ctxs, n);
+  if (s != LBM_OK) return s;
+  lbm_ctx* c0 = ctxs[0];
+  if (nsteps < 0) return fail(c0, LBM_EINVAL, "adjoint_steps_batch: negative count");
+  for (int k = 0; k < n; ++k) {
+    lbm_ctx* c = ctxs[k];
+    if (!c->adj_started) {
+      if (!c->design_set) return fail(c0, LBM_ESTATE, "adjoint_steps_batch: context %d has no design", k);
+      if (!(c->rec_open && c->t == c->rec_len))
+        return fail(c0, LBM_ESTATE, "adjoint_steps_batch: context %d has no complete recorded run", k);
+      if (nsteps > c->rec_len) return fail(c0, LBM_EINVAL, "adjoint_steps_batch: context %d: too many steps", k);
+    } else if (nsteps > c->t_adj) {
+      return fail(c0, LBM_EINVAL, "adjoint_steps_batch: context %d: only %lld steps remain", k,
+                  (long long)c->t_adj);
+    }
+  }
+  if (nsteps == 0) {
+    // still seed, so that a zero-step call behaves like the single-context form
+    return dispatch<RunAdjointBatch>(c0, ctxs, (int)n, (int64_t)0);
+  }
+  return dispatch<RunAdjointBatch>(c0, ctxs, (int)n, nsteps);
 }
 
 const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : "NULL context"; }

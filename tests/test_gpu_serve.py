@@ -1,0 +1,146 @@
+"""Batched launches and the serving loop on the GPU: every request's result is
+bitwise the same alone (single-context kernels) and in the mix (batched
+kernels, other requests admitted mid-flight)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1501_04741_amd import inputs
+from paper_1501_04741_amd import lbm as L
+from paper_1501_04741_amd.lbm import Lbm
+from paper_1501_04741_amd.serve import DONE, FAILED, GpuExecutor, Job, Server
+
+pytestmark = pytest.mark.gpu
+
+
+def _p(flow, scalar, nx, ny, nz, **kw):
+    p = dict(flow=flow, scalar=scalar, nx=nx, ny=ny, nz=nz, tau=0.8, tau_s=0.6, u_in=0.02, switch_fn="ramp",
+             switch_param=0.01, c_dp=1.0)
+    if scalar:
+        p.update(c_var=1.0, c_dp=0.1, s_in_lo=0.0, s_in_hi=1.0, s_split_axis=1)
+    p.update(kw)
+    return p
+
+
+def _alone(p, w, steps, prec, interval=0):
+    ctx = Lbm(p, nsteps=steps, precision=prec, checkpoint_interval=interval)
+    J, g = ctx.value_and_grad(torch.from_numpy(w))
+    out = (J, g.cpu().numpy())
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("kind", ["d2q9", "d3q19_d3q7"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_batched_abi_bitwise_equals_single(kind, prec):
+    if kind == "d2q9":
+        ps = [_p(9, 0, 40, 12, 1), _p(9, 0, 70, 9, 1), _p(9, 0, 300, 6, 1), _p(9, 0, 130, 17, 1)]
+    else:
+        ps = [_p(19, 7, 18, 8, 7), _p(19, 7, 33, 6, 5), _p(19, 7, 70, 9, 6)]
+    steps = 37
+    intervals = [0, 5, 37, 1, 9][: len(ps)]
+    dt = np.float32 if prec == "fp32" else np.float64
+    ws = [inputs.porosity(p["nx"], p["ny"], p["nz"], i, 3, dt) for i, p in enumerate(ps)]
+    ref = [_alone(p, w, steps, prec, c) for p, w, c in zip(ps, ws, intervals)]
+    ctxs = [Lbm(p, nsteps=steps, precision=prec, checkpoint_interval=c) for p, c in zip(ps, intervals)]
+    for c, w in zip(ctxs, ws):
+        c.set_design(torch.from_numpy(w))
+        c.reset()
+    handles = [c.ctx for c in ctxs]
+    for k in (7, 13, steps - 20):
+        L.lbm_primal_steps_batch(handles, k, record=True)
+    Js = [c.objective()[0] for c in ctxs]
+    for k in (5, 11, steps - 16):
+        L.lbm_adjoint_steps_batch(handles, k)
+    for c, (J, g), Jb in zip(ctxs, ref, Js):
+        assert Jb == J
+        assert np.array_equal(c.gradient().cpu().numpy(), g)
+
+
+def test_batched_abi_rejects_mixed_kinds_and_bad_state():
+    a = Lbm(_p(9, 0, 20, 8, 1), nsteps=4, precision="fp32")
+    b = Lbm(_p(19, 0, 8, 6, 5), nsteps=4, precision="fp32")
+    c = Lbm(_p(9, 0, 20, 8, 1), nsteps=4, precision="fp64")
+    for x in (a, b, c):
+        x.set_design(torch.full((x.N,), 0.8, dtype=x.dtype))
+    with pytest.raises(L.LbmError):
+        L.lbm_primal_steps_batch([a.ctx, b.ctx], 1, record=True)
+    with pytest.raises(L.LbmError):
+        L.lbm_primal_steps_batch([a.ctx, c.ctx], 1, record=True)
+    with pytest.raises(L.LbmError):
+        L.lbm_primal_steps_batch([a.ctx, a.ctx], 1, record=True)
+    with pytest.raises(L.LbmError):
+        L.lbm_adjoint_steps_batch([a.ctx], 1)  # nothing recorded
+    with pytest.raises(L.LbmError):
+        L.lbm_primal_steps_batch([a.ctx], 5, record=True)  # beyond the horizon
+    # nothing ran: a full single run still works
+    J, g = a.value_and_grad(torch.full((a.N,), 0.8, dtype=a.dtype))
+    assert np.isfinite(J)
+
+
+def _jobs(n_each=3, steps=60, prec="fp32"):
+    sizes = [_p(9, 0, 96, 20, 1), _p(9, 0, 256, 12, 1), _p(19, 0, 24, 10, 8), _p(19, 0, 40, 12, 10)]
+    jobs = []
+    rid = 0
+    dt = np.float32 if prec == "fp32" else np.float64
+    for rep in range(n_each):
+        for p in sizes:
+            w = inputs.porosity(p["nx"], p["ny"], p["nz"], rid, 3, dt)
+            jobs.append(Job(rid=rid, params=p, steps=steps + 7 * (rid % 3), design=w, precision=prec,
+                            arrival=0.001 * rid))
+            rid += 1
+    return jobs
+
+
+def test_served_results_equal_alone_bitwise():
+    jobs = _jobs()
+    ex = GpuExecutor()
+    srv = Server(ex, hbm_budget_bytes=8 << 30, quantum=17)
+    # stagger: half submitted now, the rest after a few ticks (joining running batches)
+    for j in jobs[:6]:
+        srv.submit(j)
+    for _ in range(3):
+        srv.tick()
+    for j in jobs[6:]:
+        srv.submit(j)
+    srv.drain()
+    assert all(j.state == DONE for j in jobs), [(j.rid, j.state, j.error) for j in jobs]
+    for j in jobs:
+        ctx = Lbm(j.params, nsteps=j.steps, precision=j.precision, hbm_budget_bytes=ex._plan_bytes(j))
+        J, g = ctx.value_and_grad(torch.from_numpy(j.design))
+        assert j.J == J, (j.rid, j.J, J)
+        assert np.array_equal(j.grad, g.cpu().numpy()), j.rid
+        ctx.close()
+
+
+def test_served_fp32_results_match_oracle():
+    jobs = _jobs(n_each=1, steps=40)
+    srv = Server(GpuExecutor(), hbm_budget_bytes=8 << 30, quantum=9)
+    srv.replay(jobs, realtime=False)
+    for j in jobs:
+        assert j.state == DONE
+        ref = oracle.adjoint(j.params, j.design.astype(np.float64), j.steps)
+        assert abs(j.J - ref["J"]) <= 1e-4 * abs(ref["J"])
+        assert np.linalg.norm(j.grad - ref["grad"]) <= 1e-3 * np.linalg.norm(ref["grad"])
+
+
+def test_serving_failure_isolation():
+    jobs = _jobs(n_each=1, steps=30)
+    bad = jobs[1]
+    bad.design = bad.design.copy()
+    bp = bad.params
+    bad.design[bp["nx"] // 2 + bp["nx"] * (bp["ny"] // 2 + bp["ny"] * (bp["nz"] // 2))] = np.nan  # interior node
+    ex = GpuExecutor()
+    srv = Server(ex, hbm_budget_bytes=8 << 30, quantum=11)
+    srv.replay(jobs, realtime=False)
+    assert bad.state == FAILED and "finite" in bad.error
+    for j in jobs:
+        if j is bad:
+            continue
+        assert j.state == DONE
+        ctx = Lbm(j.params, nsteps=j.steps, precision=j.precision, hbm_budget_bytes=ex._plan_bytes(j))
+        J, g = ctx.value_and_grad(torch.from_numpy(j.design))
+        assert j.J == J and np.array_equal(j.grad, g.cpu().numpy())
+        ctx.close()
+    assert srv.used == 0
