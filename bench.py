@@ -107,13 +107,17 @@ def serve_main(args):
     warm = jobs()[:2]
     for j in warm:
         j.arrival = 0.0
-    Server(GpuExecutor(), int(args.budget_gb * 2**30), quantum=args.quantum).replay(warm, realtime=False)
+    cap = int(args.max_active_gb * 2**30) if args.max_active_gb > 0 else None
+    budget = int(args.budget_gb * 2**30)
+    ex = GpuExecutor(arena_bytes=budget)  # workspaces are carved from one reserved arena
+    Server(ex, budget, quantum=args.quantum).replay(warm, realtime=False)
     torch.cuda.synchronize()
     print("[bench] serving %d requests at %.1f/s" % (args.requests, args.rate), file=sys.stderr, flush=True)
-    srv = Server(GpuExecutor(), int(args.budget_gb * 2**30), quantum=args.quantum)
+    qms = args.quantum_ms if args.quantum_ms > 0 else None
+    srv = Server(ex, budget, quantum=args.quantum, policy=args.policy, max_active_state_bytes=cap,
+                 quantum_ms=qms)
     served = srv.replay(jobs(), realtime=True)
     s_batched = summarize(served)
-    s_batched["max_concurrent_gb"] = None
     rec = {
         "metric": "served gradients/s, p50/p99 ms",
         "value": s_batched.get("gradients_per_s"),
@@ -126,10 +130,15 @@ def serve_main(args):
         "config": {"workload": "poisson_trace", "requests": args.requests, "rate_per_s": args.rate,
                    "sizes": ["D2Q9 256x128", "D2Q9 1024x512", "D3Q19 96x48x48", "D3Q19 192x96x96"],
                    "steps": args.serve_steps, "quantum": args.quantum, "budget_gb": args.budget_gb,
+                   "policy": args.policy, "max_active_gb": args.max_active_gb, "quantum_ms": args.quantum_ms,
                    "trace_seed": 1},
         "serving": s_batched,
         "scheduler": dict(srv.stats),
     }
+    del srv, ex
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
     if not args.no_baseline:
         print("[bench] one-at-a-time replay", file=sys.stderr, flush=True)
         base = run_one_at_a_time(jobs())
@@ -164,7 +173,12 @@ def main(argv=None):
     ap.add_argument("--serve-steps", type=int, default=2000, help="primal (= adjoint) steps per request")
     ap.add_argument("--budget-gb", type=float, default=240.0, help="HBM budget for admitted requests")
     ap.add_argument("--quantum", type=int, default=50, help="steps per request per scheduling tick")
+    ap.add_argument("--quantum-ms", type=float, default=5.0,
+                    help="device time per cost class per tick (0 = fixed --quantum steps)")
     ap.add_argument("--no-baseline", action="store_true", help="skip the one-at-a-time replay")
+    ap.add_argument("--policy", default="sjf", choices=["sjf", "fifo"])
+    ap.add_argument("--max-active-gb", type=float, default=0.4,
+                    help="cap on the summed state size of admitted requests (0 = none)")
     args = ap.parse_args(argv)
     if args.serve and args.gpus == 1:
         return serve_main(args)

@@ -902,6 +902,13 @@ struct BatchArgs {
   Real* c[kBatchMax];        // primal: destination; adjoint: lambda^n
 };
 
+// Stores a context's batch descriptor (passed by value, so the upload is a
+// stream-ordered launch with no host-side staging).
+template <typename Real>
+__global__ void k_write_desc(BatchStatic<Real> h, BatchStatic<Real>* __restrict__ d) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *d = h;
+}
+
 template <typename Real>
 __device__ __forceinline__ int batch_find(const BatchArgs<Real>& A, int blk) {
   int k = 0;

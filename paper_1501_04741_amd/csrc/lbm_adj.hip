@@ -90,8 +90,6 @@ struct lbm_ctx {
   int lam_cur = 0;
   int64_t ring_seg = -1;  // trajectory segment currently held by the ring
   std::string err;
-  // host copy of the batch descriptor; stays alive while its upload is in flight
-  alignas(16) unsigned char host_desc[kDescBytes];
 };
 
 namespace {
@@ -261,10 +259,8 @@ struct Ops {
     h.grad = (Real*)c->grad;
     h.gx = (c->cfg.nx + kBatchBX - 1) / kBatchBX;
     h.nt = nt(c) ? 1 : 0;
-    std::memcpy(c->host_desc, &h, sizeof h);
-    hipError_t e = hipMemcpyAsync(c->desc, c->host_desc, sizeof h, hipMemcpyHostToDevice, c->stream);
-    if (e != hipSuccess) return fail(c, LBM_EHIP, "descriptor upload: %s", hipGetErrorString(e));
-    return LBM_OK;
+    hipLaunchKernelGGL((k_write_desc<Real>), dim3(1), dim3(64), 0, c->stream, h, (BatchStatic<Real>*)c->desc);
+    return launch_check(c, "descriptor upload");
   }
   static void primal(lbm_ctx* c, const void* src, void* dst) {
     Geo g = node_geometry(c->cfg);

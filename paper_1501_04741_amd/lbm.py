@@ -270,7 +270,9 @@ class Lbm:
     horizon a recorded run may reach.  Device memory comes from torch."""
 
     def __init__(self, params: dict, nsteps: int, precision: str = "fp32", checkpoint_interval: int = 0,
-                 hbm_budget_bytes: int = 0, device=None, stream=None):
+                 hbm_budget_bytes: int = 0, device=None, stream=None, workspace=None):
+        """workspace: optional caller-owned uint8 device tensor (256-byte aligned) of at
+        least lbm_required_bytes; by default one is allocated with torch.empty."""
         library()
         self.device = torch.device(device if device is not None else "cuda")
         self.params = dict(params)
@@ -283,7 +285,11 @@ class Lbm:
         self.nsteps = nsteps
         self.workspace_bytes = lbm_required_bytes(self.cfg)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        elif workspace.numel() < self.workspace_bytes or workspace.data_ptr() % 256:
+            raise ValueError("workspace must be 256-byte aligned and hold %d bytes" % self.workspace_bytes)
+        self.workspace = workspace
         self.ctx = lbm_create(self.cfg, self.stream.cuda_stream, self.workspace.data_ptr(), self.workspace_bytes)
         self._design = None
 

@@ -2,15 +2,22 @@
 
 Requests of different lattice sizes arrive over time.  The scheduler:
 
-* admits queued requests, oldest first, while the sum of their workspace
-  footprints (lattice, checkpoints, ring, adjoint states) fits the HBM budget;
-  a request that alone exceeds the budget is rejected;
+* admits queued requests while the sum of their workspace footprints
+  (lattice, checkpoints, ring, adjoint states) fits the HBM budget and the
+  active set's per-step state bytes stay under a cap (enough parallel work to
+  fill the GPU without time-slicing every large request at once); the next
+  request is the one with the shortest estimated device time minus its
+  waiting time ("sjf" with linear aging, so large requests cannot starve) or
+  the oldest ("fifo"); a request that alone exceeds the budget is rejected;
 * keeps every admitted request's context resident on the device until its
   gradient is ready;
-* on each tick advances, per lattice kind (flow, scalar, precision), all
-  requests in their primal phase by one quantum of steps with ONE batched
-  launch per step, then all requests in their adjoint phase likewise (the
-  adjoint call seeds newcomers and recomputes trajectory segments as needed);
+* on each tick advances, per lattice kind (flow, scalar, precision) and
+  per-step cost class (power-of-two state size), all requests in their
+  primal phase by one quantum with ONE batched launch per step, then all
+  requests in their adjoint phase likewise (the adjoint call seeds newcomers
+  and recomputes trajectory segments as needed).  With a time quantum, each
+  class advances by the number of steps that takes about that much device
+  time, so small requests are not held to the pace of large ones;
 * finishes requests whose adjoint reached t = 0 (objective and gradient are
   read back after a stream event), frees their memory and admits more.
 
@@ -34,6 +41,11 @@ import numpy as np
 QUEUED, PRIMAL, ADJOINT, FINISHING, DONE, FAILED = "queued", "primal", "adjoint", "finishing", "done", "failed"
 
 
+class DeferAdmission(Exception):
+    """Raised by an executor's open() when the request cannot be placed now
+    (e.g. transient device-memory exhaustion); the request stays queued."""
+
+
 @dataclasses.dataclass
 class Job:
     rid: int
@@ -44,6 +56,8 @@ class Job:
     arrival: float = 0.0         # seconds on the server clock
     state: str = QUEUED
     footprint: int = 0
+    estimate: float = 0.0        # estimated device seconds
+    step_bytes: int = 0          # state bytes the request adds to every step
     handle: Any = None
     t: int = 0                   # primal steps done
     t_adj: int = 0               # adjoint steps remaining
@@ -65,6 +79,8 @@ class Executor:
     max_batch = 32
 
     def footprint(self, job: Job) -> int: ...
+    def estimate(self, job: Job) -> float: ...      # device seconds for the whole evaluation
+    def step_bytes(self, job: Job) -> int: ...      # bytes of one state of the request
     def kind(self, job: Job): ...
     def open(self, job: Job) -> Any: ...
     def primal(self, handles: List[Any], k: int) -> None: ...
@@ -79,10 +95,19 @@ class Executor:
 
 class Server:
     def __init__(self, executor: Executor, hbm_budget_bytes: int, quantum: int = 50,
-                 clock: Callable[[], float] = time.perf_counter, max_inflight_ticks: int = 2):
+                 clock: Callable[[], float] = time.perf_counter, max_inflight_ticks: int = 2,
+                 policy: str = "sjf", max_active_state_bytes: Optional[int] = None, aging: float = 1.0,
+                 quantum_ms: Optional[float] = None):
+        if policy not in ("sjf", "fifo"):
+            raise ValueError("policy must be 'sjf' or 'fifo'")
         self.ex = executor
         self.budget = int(hbm_budget_bytes)
         self.quantum = int(quantum)
+        self.policy = policy
+        self.max_active_state = max_active_state_bytes
+        self.aging = float(aging)
+        self.quantum_s = None if quantum_ms is None else float(quantum_ms) * 1e-3
+        self.active_state = 0
         self.clock = clock
         self.t0 = clock()
         self.queue: collections.deque = collections.deque()
@@ -99,6 +124,8 @@ class Server:
     # --------------------------------------------------------------- intake
     def submit(self, job: Job) -> Job:
         job.footprint = self.ex.footprint(job)
+        job.estimate = self.ex.estimate(job)
+        job.step_bytes = self.ex.step_bytes(job)
         if job.footprint > self.budget:
             job.state = FAILED
             job.error = "footprint %d B exceeds the budget %d B" % (job.footprint, self.budget)
@@ -110,11 +137,45 @@ class Server:
         self.stats["submitted"] += 1
         return job
 
+    def _fits(self, job: Job) -> bool:
+        if self.used + job.footprint > self.budget:
+            return False
+        if self.max_active_state is not None and self.active and \
+                self.active_state + job.step_bytes > self.max_active_state:
+            return False
+        return True
+
+    def _next(self) -> Optional[Job]:
+        if not self.queue:
+            return None
+        if self.policy == "fifo":
+            head = self.queue[0]
+            return head if self._fits(head) else None
+        now = self.now()
+        for job in sorted(self.queue, key=lambda j: (j.estimate - self.aging * (now - j.arrival), j.arrival)):
+            if self._fits(job):
+                return job
+        return None
+
     def _admit(self):
-        while self.queue and self.used + self.queue[0].footprint <= self.budget:
-            job = self.queue.popleft()
+        while True:
+            job = self._next()
+            if job is None:
+                return
+            self.queue.remove(job)
             try:
                 job.handle = self.ex.open(job)
+            except DeferAdmission as e:
+                if self.active:  # memory will come back when running requests finish
+                    self.queue.appendleft(job)
+                    self.stats["deferred"] += 1
+                    return
+                job.state = FAILED
+                job.error = "open: %s" % e
+                job.finished = self.now()
+                self.finished.append(job)
+                self.stats["failed"] += 1
+                continue
             except Exception as e:  # allocation or validation failure: fail this request only
                 job.state = FAILED
                 job.error = "open: %s" % e
@@ -123,6 +184,7 @@ class Server:
                 self.stats["failed"] += 1
                 continue
             self.used += job.footprint
+            self.active_state += job.step_bytes
             job.state = PRIMAL
             job.t = 0
             job.admitted = self.now()
@@ -134,10 +196,19 @@ class Server:
         groups: Dict[Any, List[Job]] = collections.OrderedDict()
         for j in self.active:
             if j.state == state:
-                groups.setdefault(self.ex.kind(j), []).append(j)
+                cls = int(math.log2(max(j.step_bytes, 1))) if self.quantum_s is not None else 0
+                groups.setdefault((self.ex.kind(j), cls), []).append(j)
         for key, jobs in groups.items():
             for i in range(0, len(jobs), self.ex.max_batch):
                 yield jobs[i:i + self.ex.max_batch]
+
+    def _steps(self, jobs: List[Job], remaining: int) -> int:
+        if self.quantum_s is None:
+            k = self.quantum
+        else:
+            per_step = max(j.estimate / (2.0 * max(j.steps, 1)) for j in jobs)  # primal or adjoint step
+            k = max(1, int(self.quantum_s / max(per_step, 1e-9)))
+        return min(k, remaining)
 
     def tick(self) -> bool:
         """One scheduling round; returns True if any device work was issued."""
@@ -145,7 +216,7 @@ class Server:
         self._admit()
         issued = False
         for jobs in self._groups(PRIMAL):
-            k = min(self.quantum, min(j.steps - j.t for j in jobs))
+            k = self._steps(jobs, min(j.steps - j.t for j in jobs))
             if k > 0:
                 self.ex.primal([j.handle for j in jobs], k)
                 issued = True
@@ -156,7 +227,7 @@ class Server:
                     j.state = ADJOINT
                     j.t_adj = j.steps
         for jobs in self._groups(ADJOINT):
-            k = min(self.quantum, min(j.t_adj for j in jobs))
+            k = self._steps(jobs, min(j.t_adj for j in jobs))
             self.ex.adjoint([j.handle for j in jobs], k)
             issued = True
             self.stats["adjoint_launch_steps"] += k
@@ -190,6 +261,7 @@ class Server:
                 self.ex.close(j.handle)
                 j.handle = None
                 self.used -= j.footprint
+                self.active_state -= j.step_bytes
                 self.finished.append(j)
             else:
                 still.append(j)
@@ -231,6 +303,7 @@ class Server:
 
 def summarize(jobs: List[Job], t_first_arrival: float = 0.0) -> dict:
     done = [j for j in jobs if j.state == DONE]
+    errors = collections.Counter(j.error.split(":")[0] for j in jobs if j.state == FAILED)
     lat = np.array([j.latency for j in done]) * 1e3
     if not done:
         return {"completed": 0, "failed": len(jobs)}
@@ -243,16 +316,66 @@ def summarize(jobs: List[Job], t_first_arrival: float = 0.0) -> dict:
         "p99_ms": float(np.percentile(lat, 99)),
         "mean_ms": float(lat.mean()),
         "span_s": span,
+        "failure_reasons": dict(errors),
     }
 
 
 # ------------------------------------------------------------------ GPU
+class Arena:
+    """First-fit sub-allocator over one device buffer reserved up front
+    (address-ordered free list, neighbours merged on release), so that serving
+    makes no device allocation or free calls.  Blocks are 256-byte aligned."""
+
+    ALIGN = 256
+
+    def __init__(self, nbytes: int, device):
+        import torch
+        self.size = int(nbytes) // self.ALIGN * self.ALIGN
+        self.buf = torch.empty(self.size, dtype=torch.uint8, device=device)
+        self.free = [(0, self.size)]
+
+    def _round(self, n):
+        return (int(n) + self.ALIGN - 1) // self.ALIGN * self.ALIGN
+
+    def alloc(self, nbytes: int):
+        n = self._round(nbytes)
+        for i, (off, sz) in enumerate(self.free):
+            if sz >= n:
+                if sz == n:
+                    del self.free[i]
+                else:
+                    self.free[i] = (off + n, sz - n)
+                return off, self.buf[off:off + n]
+        return None
+
+    def release(self, off: int, nbytes: int):
+        n = self._round(nbytes)
+        i = 0
+        while i < len(self.free) and self.free[i][0] < off:
+            i += 1
+        self.free.insert(i, (off, n))
+        if i + 1 < len(self.free) and off + n == self.free[i + 1][0]:
+            self.free[i] = (off, n + self.free[i + 1][1])
+            del self.free[i + 1]
+        if i > 0 and self.free[i - 1][0] + self.free[i - 1][1] == self.free[i][0]:
+            self.free[i - 1] = (self.free[i - 1][0], self.free[i - 1][1] + self.free[i][1])
+            del self.free[i]
+
+    def free_bytes(self) -> int:
+        return sum(sz for _, sz in self.free)
+
+
 class GpuExecutor(Executor):
-    """Device back end: one library context per request, batched launches."""
+    """Device back end: one library context per request, batched launches.
+
+    Workspaces come from an ``Arena`` when ``arena_bytes`` is given (no device
+    allocation while serving); designs are uploaded and results read back
+    through pinned host buffers with asynchronous copies, so the host never
+    waits for queued device work except when it chooses to (tick pacing)."""
 
     max_batch = 32
 
-    def __init__(self, device=None, per_request_cap_bytes: int = 4 << 30):
+    def __init__(self, device=None, per_request_cap_bytes: int = 4 << 30, arena_bytes: Optional[int] = None):
         import torch
 
         from . import lbm as _lbm
@@ -261,6 +384,7 @@ class GpuExecutor(Executor):
         self.device = torch.device(device if device is not None else "cuda")
         self.stream = torch.cuda.current_stream(self.device)
         self.cap = int(per_request_cap_bytes)
+        self.arena = Arena(arena_bytes, self.device) if arena_bytes else None
 
     def _plan_bytes(self, job: Job) -> int:
         """Workspace for the request: store-all (no recompute) when it fits the
@@ -282,12 +406,49 @@ class GpuExecutor(Executor):
         p = job.params
         return (p["flow"], p.get("scalar", 0), job.precision)
 
+    def step_bytes(self, job: Job) -> int:
+        p = job.params
+        s = 4 if job.precision == "fp32" else 8
+        return (p["flow"] + p.get("scalar", 0)) * p["nx"] * p["ny"] * p["nz"] * s
+
+    def estimate(self, job: Job) -> float:
+        # forward (2 states/step) + recompute (2) + adjoint (3) at ~5.5 TB/s, plus launch overhead
+        return job.steps * (7.0 * self.step_bytes(job) / 5.5e12 + 3 * 6e-6)
+
     def open(self, job: Job):
-        L = self.lbm.Lbm(job.params, nsteps=job.steps, precision=job.precision, hbm_budget_bytes=job._budget,
-                         device=self.device, stream=self.stream)
-        L.set_design(job.design)
+        torch = self.torch
+        block = None
+        ws = None
+        if self.arena is not None:
+            block = self.arena.alloc(job.footprint)
+            if block is None:
+                raise DeferAdmission("arena: no free block of %d B" % job.footprint)
+            ws = block[1]
+        make = lambda: self.lbm.Lbm(job.params, nsteps=job.steps, precision=job.precision,
+                                    hbm_budget_bytes=job._budget, device=self.device, stream=self.stream,
+                                    workspace=ws)
+        try:
+            try:
+                L = make()
+            except torch.cuda.OutOfMemoryError:
+                torch.cuda.empty_cache()
+                try:
+                    L = make()
+                except torch.cuda.OutOfMemoryError as e:
+                    raise DeferAdmission("device memory: %s" % str(e).splitlines()[0])
+        except Exception:
+            if block is not None:
+                self.arena.release(block[0], job.footprint)
+            raise
+        L._block = block
+        L._footprint = job.footprint
+        dt = torch.float32 if job.precision == "fp32" else torch.float64
+        host = torch.as_tensor(np.ascontiguousarray(np.asarray(job.design).reshape(-1)), dtype=dt).pin_memory()
+        L._w_host = host
+        L._w_dev = host.to(self.device, non_blocking=True)
+        L.set_design(L._w_dev)
         L.reset()
-        L._J = self.torch.empty(1, dtype=self.torch.float64, device=self.device)
+        L._J = torch.empty(1, dtype=torch.float64, device=self.device)
         return L
 
     def primal(self, handles, k):
@@ -301,21 +462,29 @@ class GpuExecutor(Executor):
         self.lbm.lbm_adjoint_steps_batch([h.ctx for h in handles], k)
 
     def finish(self, handle):
+        torch = self.torch
         g = handle.gradient()
-        ev = self.torch.cuda.Event()
+        host_g = torch.empty(g.shape, dtype=g.dtype, pin_memory=True)
+        host_J = torch.empty(1, dtype=torch.float64, pin_memory=True)
+        host_g.copy_(g, non_blocking=True)
+        host_J.copy_(handle._J, non_blocking=True)
+        ev = torch.cuda.Event()
         ev.record(self.stream)
-        handle._grad = g
-        return ev
+        return (ev, host_g, host_J, g)
 
     def ready(self, token) -> bool:
-        return token.query()
+        return token[0].query()
 
     def result(self, handle, token):
-        token.synchronize()
-        return float(handle._J.item()), handle._grad.detach().cpu().numpy()
+        ev, host_g, host_J, _ = token
+        ev.synchronize()
+        return float(host_J[0]), host_g.numpy().copy()
 
     def close(self, handle):
         handle.close()
+        if getattr(handle, "_block", None) is not None:
+            self.arena.release(handle._block[0], handle._footprint)
+            handle._block = None
 
     def mark(self):
         ev = self.torch.cuda.Event()
@@ -377,6 +546,14 @@ class FakeExecutor(Executor):
 
     def kind(self, job):
         return (job.params["flow"], job.params.get("scalar", 0), job.precision)
+
+    def step_bytes(self, job):
+        p = job.params
+        return (p["flow"] + p.get("scalar", 0)) * p["nx"] * p["ny"] * p["nz"] * 8
+
+    def estimate(self, job):
+        p = job.params
+        return max(self.sec, 1e-9) * p["nx"] * p["ny"] * p["nz"] * job.steps
 
     def open(self, job):
         if job.rid in self.fail_on_open:

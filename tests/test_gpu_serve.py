@@ -144,3 +144,17 @@ def test_serving_failure_isolation():
         assert j.J == J and np.array_equal(j.grad, g.cpu().numpy())
         ctx.close()
     assert srv.used == 0
+
+
+def test_arena_backed_server_results_equal_alone():
+    jobs = _jobs(n_each=2, steps=45)
+    ex = GpuExecutor(arena_bytes=2 << 30)
+    srv = Server(ex, hbm_budget_bytes=2 << 30, quantum_ms=2.0, max_active_state_bytes=8 << 20)
+    srv.replay(jobs, realtime=False)
+    assert all(j.state == DONE for j in jobs), [(j.rid, j.state, j.error) for j in jobs]
+    assert ex.arena.free_bytes() == ex.arena.size
+    for j in jobs:
+        ctx = Lbm(j.params, nsteps=j.steps, precision=j.precision, hbm_budget_bytes=ex._plan_bytes(j))
+        J, g = ctx.value_and_grad(torch.from_numpy(j.design))
+        assert j.J == J and np.array_equal(j.grad, g.cpu().numpy()), j.rid
+        ctx.close()

@@ -161,3 +161,115 @@ def test_replay_submits_in_arrival_order():
     assert len(done) == 12 and all(j.state == DONE for j in done)
     arr = [r.arrival_s for r in trace]
     assert arr == sorted(arr) and arr[0] == 0.0
+
+
+def test_sjf_admits_short_requests_first_and_fifo_keeps_order():
+    ex = FakeExecutor(lambda j: (1.0, None), seconds_per_node_step=1e-9)
+    big = _job(0, 64, 64, steps=20)
+    small = [_job(i, 16, 8, steps=20) for i in (1, 2)]
+    budget = ex.footprint(big)
+    for policy in ("sjf", "fifo"):
+        srv = Server(FakeExecutor(lambda j: (1.0, None), seconds_per_node_step=1e-9), hbm_budget_bytes=budget,
+                     quantum=5, policy=policy, clock=FakeClock())
+        jobs = [_job(0, 64, 64, steps=20)] + [_job(i, 16, 8, steps=20) for i in (1, 2)]
+        for j in jobs:
+            srv.submit(j)
+        order = []
+        while not srv.idle():
+            srv.tick()
+            for j in srv.finished:
+                if j.rid not in order:
+                    order.append(j.rid)
+        if policy == "sjf":
+            assert order.index(1) < order.index(0) and order.index(2) < order.index(0)
+        else:
+            assert order[0] == 0
+
+
+def test_active_state_cap_and_aging():
+    ex = FakeExecutor(lambda j: (1.0, None), seconds_per_node_step=1e-6)
+    one = ex.step_bytes(_job(0, 32, 32))
+    clock = FakeClock()
+    srv = Server(ex, hbm_budget_bytes=10 ** 12, quantum=5, policy="sjf", max_active_state_bytes=2 * one,
+                 aging=1.0, clock=clock)
+    for i in range(5):
+        srv.submit(_job(i, 32, 32, steps=20))
+    while not srv.idle():
+        srv.tick()
+        assert srv.active_state <= 2 * one
+        assert sum(1 for j in srv.active) <= 2
+    # aging: an old large request overtakes newer short ones once it has waited longer
+    # than the difference of their estimated times
+    srv = Server(FakeExecutor(lambda j: (1.0, None), seconds_per_node_step=1e-6), hbm_budget_bytes=10 ** 12,
+                 quantum=5, policy="sjf", max_active_state_bytes=1, clock=clock)
+    clock.t = 0.0
+    srv.t0 = 0.0
+    big = _job(0, 64, 64, steps=20, arrival=0.0)     # estimate 64*64*20*1e-6 = 0.082 s
+    srv.submit(big)
+    clock.t = 1.0
+    late = _job(1, 16, 8, steps=20, arrival=1.0)     # estimate 0.00256 s, waited 0
+    srv.submit(late)
+    assert srv._next() is big
+
+
+def test_time_quantum_lets_small_requests_take_more_steps_per_tick():
+    ex = FakeExecutor(lambda j: (1.0, None), seconds_per_node_step=1e-8)
+    srv = Server(ex, hbm_budget_bytes=10 ** 12, quantum_ms=1.0)
+    big = _job(0, 128, 128, steps=400)
+    small = _job(1, 16, 8, steps=400)
+    srv.submit(big)
+    srv.submit(small)
+    srv.tick()
+    steps = {rids: k for kind, rids, k in ex.log if kind == "primal"}
+    assert steps[(1,)] > steps[(0,)]           # separate cost classes, more steps for the small one
+    srv.drain()
+    assert small.finished <= big.finished
+
+
+def test_deferred_admission_keeps_request_queued():
+    from paper_1501_04741_amd.serve import DeferAdmission
+
+    class Tight(FakeExecutor):
+        def __init__(self):
+            super().__init__(lambda j: (1.0, None))
+            self.busy = False
+
+        def open(self, job):
+            if self.busy:
+                raise DeferAdmission("device memory")
+            self.busy = True
+            return super().open(job)
+
+        def close(self, handle):
+            self.busy = False
+            super().close(handle)
+
+    ex = Tight()
+    srv = Server(ex, hbm_budget_bytes=10 ** 12, quantum=5)
+    jobs = [_job(i, 16, 8, steps=10) for i in range(3)]
+    for j in jobs:
+        srv.submit(j)
+    srv.drain()
+    assert all(j.state == DONE for j in jobs)
+    assert srv.stats["deferred"] >= 2
+
+
+def test_arena_first_fit_and_coalescing():
+    import torch
+
+    from paper_1501_04741_amd.serve import Arena
+    a = Arena(10 * 256, "cpu")
+    blocks = [a.alloc(256) for _ in range(10)]
+    assert all(b is not None for b in blocks) and a.alloc(1) is None
+    offs = [b[0] for b in blocks]
+    assert offs == [256 * i for i in range(10)]
+    for i in (1, 2, 5):
+        a.release(offs[i], 256)
+    assert a.free == [(256, 512), (1280, 256)]
+    b = a.alloc(300)                       # rounds to 512, first fit at 256
+    assert b[0] == 256 and b[1].numel() == 512
+    a.release(256, 300)
+    for i in (0, 3, 4, 6, 7, 8, 9):
+        a.release(offs[i], 256)
+    assert a.free == [(0, 2560)] and a.free_bytes() == 2560
+    assert a.buf.dtype == torch.uint8
