@@ -99,6 +99,8 @@ def _load():
         "lbmo_step_tangent": (ctypes.c_int, [c, d, d, d, d, d, d, d, d]),
         "lbmo_step_adjoint": (ctypes.c_int, [c, d, d, d, d, d, d, d, d]),
         "lbmo_objective_seed": (ctypes.c_int, [c, d, d, d, d, d]),
+        "lbmo_oneshot": (ctypes.c_int, [c, d, d, d, ctypes.c_int64, ctypes.c_double, ctypes.c_double, d, d, d, d,
+                                        d, d]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -313,3 +315,24 @@ def objective_seed(params, f, g=None):
     _check(_load().lbmo_objective_seed(ctypes.byref(cfg), _dp(fa), _dp(ga), ctypes.byref(J), _dp(lf), _dp(lg)),
            "objective_seed")
     return J.value, lf.reshape(q, n), lg[: qs * n].reshape(qs, n)
+
+
+def oneshot(params, w, iters, zeta, c_pen=0.0, f0=None, g0=None):
+    """One-shot descent iterations (primal step, stationary-adjoint step with
+    the objective source, gradient estimate, clipped design update).
+    Returns dict(w, f, g, lam_f, lam_g, grad, J) after ``iters`` iterations;
+    grad and J belong to the last iteration's state."""
+    cfg = _cfg(params)
+    n, q, qs = _sizes(cfg)
+    wa = _f64(w, n).copy()
+    fa, ga = _state_args(cfg, f0, g0)
+    fN = np.zeros(q * n)
+    gN = np.zeros(max(qs, 1) * n)
+    lf = np.zeros(q * n)
+    lg = np.zeros(max(qs, 1) * n)
+    gr = np.zeros(n)
+    J = ctypes.c_double()
+    _check(_load().lbmo_oneshot(ctypes.byref(cfg), _dp(wa), _opt(fa), _opt(ga), int(iters), float(zeta), float(c_pen),
+                                _dp(fN), _dp(gN), _dp(lf), _dp(lg), _dp(gr), ctypes.byref(J)), "oneshot")
+    return dict(w=wa, f=fN.reshape(q, n), g=gN[: qs * n].reshape(qs, n), lam_f=lf.reshape(q, n),
+                lam_g=lg[: qs * n].reshape(qs, n), grad=gr, J=J.value)

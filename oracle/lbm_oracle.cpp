@@ -792,4 +792,51 @@ int lbmo_objective_seed(const lbmo_cfg* cfg, const double* f, const double* g, d
   return 0;
 }
 
+// One-shot descent (Section 3.3, eq. gradient:update).  Iteration n, on the
+// current pre-collision state f^n, adjoint lam^n and design w^n:
+//   s        = dJ/df (f^n)                                   (objective source)
+//   lam^{n+1}= (dW/df)^T(f^n) S^{-1} lam^n + s               (eq. adjoint:iteration)
+//   g^n      = (dW/dw)^T(f^n) S^{-1} lam^n                   (eq. adjoint:derivative)
+//   f^{n+1}  = S W(f^n, w^n)                                 (eq. normal:iteration)
+//   w^{n+1}  = clip(w^n + zeta (g^n + c_pen (1 - 2 w^n)), 0, 1) at interior nodes
+// where c_pen weighs the penalty P = sum w(1-w) (eq. P).  lam^0 = 0 unless given.
+// w is updated in place; outputs: final state, adjoint, last g and last J.
+int lbmo_oneshot(const lbmo_cfg* cfg, double* w, const double* f0, const double* g0, int64_t iters, double zeta,
+                 double c_pen, double* fN, double* gN, double* lam_f, double* lam_g, double* g_last, double* J_last) {
+  Model M;
+  if (!make_model(cfg, &M) || iters < 0) return -1;
+  const lbmo_cfg& c = M.c;
+  State<double> cur, nxt, lam, lam_new, seed;
+  init_state(M, f0, g0, cur);
+  nxt.resize(M);
+  lam.resize(M);
+  std::vector<double> gw(M.n, 0.0);
+  double J = 0.0;
+  for (int64_t it = 0; it < iters; ++it) {
+    objective_seed(M, cur, &J, seed);
+    std::fill(gw.begin(), gw.end(), 0.0);
+    adjoint_step(M, w, cur, lam, lam_new, gw.data());
+    for (size_t k = 0; k < lam_new.f.size(); ++k) lam_new.f[k] += seed.f[k];
+    for (size_t k = 0; k < lam_new.g.size(); ++k) lam_new.g[k] += seed.g[k];
+    step(M, w, cur, nxt);
+    std::swap(cur, nxt);
+    std::swap(lam, lam_new);
+    for (int z = 0; z < c.nz; ++z)
+      for (int y = 0; y < c.ny; ++y)
+        for (int x = 0; x < c.nx; ++x) {
+          if (node_class(c, x, y, z) != INTERIOR) continue;
+          const int64_t n = node_index(c, x, y, z);
+          double v = w[n] + zeta * (gw[n] + c_pen * (1.0 - 2.0 * w[n]));
+          w[n] = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+        }
+  }
+  if (fN) std::memcpy(fN, cur.f.data(), sizeof(double) * cur.f.size());
+  if (gN && M.S.q) std::memcpy(gN, cur.g.data(), sizeof(double) * cur.g.size());
+  if (lam_f) std::memcpy(lam_f, lam.f.data(), sizeof(double) * lam.f.size());
+  if (lam_g && M.S.q) std::memcpy(lam_g, lam.g.data(), sizeof(double) * lam.g.size());
+  if (g_last) std::memcpy(g_last, gw.data(), sizeof(double) * M.n);
+  if (J_last) *J_last = J;
+  return 0;
+}
+
 }  // extern "C"

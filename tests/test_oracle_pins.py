@@ -537,3 +537,45 @@ def test_adjoint_checkpointing_is_exact():
         a = oracle.adjoint(p, w, steps)
         _, dJ = oracle.directional(p, w, dw, steps)
         assert abs(a["grad"] @ dw - dJ) <= 1e-12 * max(abs(dJ), 1e-300) or (steps == 0 and dJ == 0)
+
+
+# ---------------------------------------------------------------- one-shot
+@pytest.mark.parametrize("scalar", [0, 5])
+def test_oneshot_steady_gradient_equals_fd_of_converged_objective(scalar):
+    """With zeta = 0 the one-shot iteration is the primal iteration plus the
+    stationary adjoint iteration; once both have converged the gradient
+    estimate equals dJ/dw of the converged objective (Section 2.2 theorem)."""
+    nx, ny = (16, 8) if not scalar else (12, 6)
+    p = dict(flow=9, scalar=scalar, nx=nx, ny=ny, nz=1, tau=0.8, tau_s=0.7, u_in=0.02, switch_fn="ramp",
+             switch_param=0.1, c_dp=1.0)
+    if scalar:
+        p.update(c_dp=-0.1, c_hf=1.0, c_var=0.5, scalar_wall="dirichlet", s_wall=1.0)
+    w = inputs.porosity(nx, ny, 1, 0, 3)
+    iters = 2000
+    r = oracle.oneshot(p, w, iters, 0.0)
+    assert np.array_equal(r["w"], w)                       # zeta = 0 leaves the design alone
+    eps = 1e-4                                             # truncation ~1e-8 rel; smaller eps is rounding-bound
+    fd = np.zeros_like(w)
+    for k in range(w.size):
+        wp = w.copy(); wp[k] += eps
+        wm = w.copy(); wm[k] -= eps
+        fd[k] = (oracle.primal(p, wp, iters)["J"] - oracle.primal(p, wm, iters)["J"]) / (2 * eps)
+    assert np.linalg.norm(fd - r["grad"]) <= 1e-6 * np.linalg.norm(fd)
+    assert abs(r["J"] - oracle.primal(p, w, iters - 1)["J"]) <= 1e-12 * abs(r["J"])
+
+
+def test_oneshot_penalty_update_closed_form():
+    """With all objective weights zero the adjoint source vanishes, so the update
+    is w <- w + zeta c (1 - 2w) at interior nodes: w_n = 1/2 + (1 - 2 zeta c)^n (w_0 - 1/2);
+    other nodes keep their value; a large step clips to [0, 1]."""
+    p = dict(flow=9, nx=14, ny=7, nz=1, c_dp=0.0, c_hf=0.0, c_var=0.0, switch_fn="ramp", switch_param=0.1)
+    w0 = inputs.porosity(14, 7, 1, 2, 3)
+    zeta, c, n = 0.05, 0.8, 25
+    r = oracle.oneshot(p, w0, n, zeta, c)
+    interior = oracle.mask(p) == 0
+    want = 0.5 + (1 - 2 * zeta * c) ** n * (w0 - 0.5)
+    assert np.allclose(r["w"][interior], want[interior], rtol=0, atol=1e-14)
+    assert np.array_equal(r["w"][~interior], w0[~interior])
+    assert np.all(r["lam_f"] == 0) and np.all(r["grad"] == 0)
+    rc = oracle.oneshot(p, w0, 3, 10.0, -1.0)               # pushes away from 1/2 past the bounds
+    assert set(np.unique(rc["w"][interior])) <= {0.0, 1.0}
