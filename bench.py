@@ -75,6 +75,16 @@ def algorithmic_bytes(p, precision):
     return primal, adjoint
 
 
+def oneshot_bytes(p, precision):
+    """Bytes one fused one-shot launch must move: every node pulls and stores its
+    state and adjoint state (4*Qt*s) and writes its gradient estimate (s);
+    interior nodes also read and write the design value (2s)."""
+    s = 4 if precision == "fp32" else 8
+    qt = p["flow"] + p.get("scalar", 0)
+    ni, nw, nin, nout = _class_counts(p)
+    return ni * (4 * qt * s + 3 * s) + (nw + nin + nout) * (4 * qt * s + s)
+
+
 def cpu_baseline(p, w64, steps):
     import oracle
     cores = oracle.threads()
@@ -256,8 +266,25 @@ def main(argv=None):
         b.copy_(a)
         torch.cuda.synchronize()
 
+    # one-shot descent iterations (fused primal + stationary adjoint + update), zeta = 0
+    os_iters = 200
+    L.close()
+    O = Lbm(p, nsteps=0, precision=prec, device=dev)
+    O.set_design(w)
+    O.reset()
+    O.oneshot_steps(20, 0.0, 0.0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    O.oneshot_steps(os_iters, 0.0, 0.0)
+    e1.record()
+    torch.cuda.synchronize()
+    os_launch_ms = e0.elapsed_time(e1) / os_iters
+    O.close()
+
     nodes = L.N
     pb, ab = algorithmic_bytes(p, prec)
+    ob = oneshot_bytes(p, prec)
+    os_gbs = ob / (os_launch_ms * 1e-3) / 1e9
     prim_gbs = pb / (primal_launch_ms * 1e-3) / 1e9
     adj_gbs = ab / (adjoint_launch_ms * 1e-3) / 1e9 if k_last > 1 else None
     rec = {
@@ -298,13 +325,17 @@ def main(argv=None):
                              "traffic": _measured_traffic(args.workload, "k_adjoint"),
                              "bytes_per_launch": ab,
                              "avg_launch_us": adjoint_launch_ms * 1e3 if k_last > 1 else None},
+        "oneshot": {"kernel": "k_oneshot<19,0,float>", "iterations_timed": os_iters,
+                    "mlups": nodes / (os_launch_ms * 1e-3) / 1e6,
+                    "roofline": {"bound": "hbm", "achieved": os_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": os_gbs / HBM_PEAK_GBS, "bytes_per_launch": ob,
+                                 "avg_launch_us": os_launch_ms * 1e3}},
     }
     if not args.no_cpu_baseline:
         print("[bench] GPU timing done; timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(p, w_np.astype(np.float64), args.cpu_steps)
     else:
         rec["cpu_baseline"] = None
-    L.close()
     print(json.dumps(rec), flush=True)
     return 0
 

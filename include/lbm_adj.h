@@ -29,11 +29,12 @@
  *     lbm_create (NULL = the default stream).  Only calls with a "_host"
  *     output synchronise that stream.  Asynchronous HIP faults surface as
  *     LBM_EHIP at a later call.
- *   - Layout: node n = x + nx*(y + ny*z), x fastest.  A state is stored
- *     structure-of-arrays: population j of node n at j*N + n, flow populations
- *     first, then scalar populations.  Design field w and gradient are N
- *     values of the context precision (float for LBM_FP32, double for
- *     LBM_FP64).  Exported states, adjoints and fields are double.
+ *   - Layout: node n = x + nx*(y + ny*z), x fastest.  Every state the ABI
+ *     exchanges (set/get state, adjoint, fields) is plane-major double:
+ *     population j of node n at j*N + n, flow populations first, then scalar
+ *     populations.  Design field w and gradient are N values of the context
+ *     precision (float for LBM_FP32, double for LBM_FP64).  The workspace's
+ *     internal layout is private to the library.
  *   - Velocity order: the paper's D3Q19 list e_1..e_19 (Section 3), 0-based;
  *     D2Q9 is its z = 0 subset in the same order; D3Q7 / D2Q5 are the first
  *     7 / 5 members.
@@ -159,7 +160,8 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, int64_t nsteps);
 
 /* Writes dJ/dw (N values, context precision) to grad_dev (eq.
  * adjoint:derivative summed over all steps).  Requires the adjoint to have
- * reached t = 0 (LBM_ESTATE otherwise).  Asynchronous. */
+ * reached t = 0, or a one-shot iteration (then the last gradient estimate);
+ * LBM_ESTATE otherwise.  Asynchronous. */
 lbm_status lbm_gradient(lbm_ctx* ctx, void* grad_dev);
 
 /* Macroscopic fields of the current pre-collision state, reconstructed at the
@@ -181,6 +183,24 @@ lbm_status lbm_get_adjoint(lbm_ctx* ctx, double* lf_dev, double* lg_dev);
  * index of node (x - e_j) mod L (Q x N int64), computed by the same device
  * code the step kernels use.  Device pointers (either nullable), asynchronous. */
 lbm_status lbm_export_maps(lbm_ctx* ctx, uint8_t* mask_dev, int64_t* src_dev);
+
+/* One-shot descent (Section 3.3, eq. gradient:update): nsteps iterations,
+ * each one fused kernel on the current pre-collision state f^n, adjoint
+ * lambda^n (zero at the first call after a reset) and design w:
+ *   lambda^{n+1} = (dW/df)^T S^{-1} lambda^n + dJ/df(f^n)   (eq. adjoint:iteration)
+ *   g            = (dW/dw)^T S^{-1} lambda^n                (eq. adjoint:derivative)
+ *   f^{n+1}      = S W(f^n, w)                              (eq. normal:iteration)
+ *   w           <- clip(w + zeta*(g + penalty*(1 - 2w)), 0, 1) at interior nodes,
+ * where 1 - 2w is the derivative of the penalty P = sum w(1-w) (eq. P); a
+ * negative zeta*penalty drives w toward 0 and 1.  The design is updated in
+ * the workspace (read it with lbm_get_design); lbm_gradient returns the last
+ * g.  Unrecorded: the primal uses the ping-pong buffers.  Errors: LBM_ESTATE
+ * (no design, or an unsteady adjoint in progress), LBM_EINVAL. */
+lbm_status lbm_oneshot_steps(lbm_ctx* ctx, int64_t nsteps, double zeta, double penalty);
+
+/* Copies the context's current design field (N values, context precision)
+ * to w_dev (device); the one-shot iteration changes it.  Asynchronous. */
+lbm_status lbm_get_design(lbm_ctx* ctx, void* w_dev);
 
 /* Times: t (primal), recorded length, adjoint time (-1 before seeding). */
 lbm_status lbm_times(const lbm_ctx* ctx, int64_t* t, int64_t* recorded, int64_t* t_adj);

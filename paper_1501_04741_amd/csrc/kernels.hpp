@@ -478,19 +478,14 @@ __global__ __launch_bounds__(64) void k_objective_final(Params<Real> p, const do
 }
 
 // ------------------------------------------------------------ adjoint seed
-// lambda^N = dJ/df^N: non-zero only at inlet/outlet nodes.  Uses the sums
-// written by the objective kernel (glob[0..7]).
+// dJ/df and dJ/dg of one node's pre-collision state (zero except at inlet and
+// outlet nodes); glob holds the boundary sums of the current state.
 template <int Q, int QS, typename Real>
-__device__ __forceinline__ void seed_node(const Params<Real>& p, const Real* __restrict__ src,
-                                          const double* __restrict__ glob, Real* __restrict__ lam, int x, int y,
-                                          int z) {
+__device__ __forceinline__ void seed_values(const Params<Real>& p, int cls, const Real (&f)[Q],
+                                            const Real (&g)[QS > 0 ? QS : 1], const double* __restrict__ glob,
+                                            double (&lf)[Q], double (&lg)[QS > 0 ? QS : 1]) {
   using L = Lat<Q>;
   using S = SLat<QS>;
-  constexpr bool is3d = (Q == 19);
-  constexpr int QT = Q + QS;
-  const Nbr b = make_nbr(p, x, y, z);
-  const int cls = node_class(p, x, y, z, is3d);
-  double lf[Q], lg[QS > 0 ? QS : 1];
 #pragma unroll
   for (int j = 0; j < Q; ++j) lf[j] = 0.0;
 #pragma unroll
@@ -505,8 +500,6 @@ __device__ __forceinline__ void seed_node(const Params<Real>& p, const Real* __r
     if (cls == OUTLET && glob[3] > 0) {
       const double G3 = glob[3];
       const double A4 = p.c_hf, A5 = -2.0 * p.c_var * glob[5] / (G3 * G3), A6 = p.c_var / G3;
-      Real f[Q], g[QS];
-      pull_state<Q, QS, Real>(src, b, f, g);
       double s0 = 0, sp = 0, rest = 0;
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
@@ -528,6 +521,29 @@ __device__ __forceinline__ void seed_node(const Params<Real>& p, const Real* __r
       for (int i = 0; i < QS; ++i) lg[i] = (i == kMX) ? 0.0 : dT / (1.0 - a);
     }
   }
+}
+
+// lambda^N = dJ/df^N: non-zero only at inlet/outlet nodes.  Uses the sums
+// written by the objective kernel (glob[0..7]).
+template <int Q, int QS, typename Real>
+__device__ __forceinline__ void seed_node(const Params<Real>& p, const Real* __restrict__ src,
+                                          const double* __restrict__ glob, Real* __restrict__ lam, int x, int y,
+                                          int z) {
+  constexpr bool is3d = (Q == 19);
+  constexpr int QT = Q + QS;
+  const Nbr b = make_nbr(p, x, y, z);
+  const int cls = node_class(p, x, y, z, is3d);
+  Real f[Q], g[QS > 0 ? QS : 1];
+  if (QS > 0 && cls == OUTLET) {
+    pull_state<Q, QS, Real>(src, b, f, g);
+  } else {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) f[j] = Real(0);
+#pragma unroll
+    for (int i = 0; i < (QS > 0 ? QS : 1); ++i) g[i] = Real(0);
+  }
+  double lf[Q], lg[QS > 0 ? QS : 1];
+  seed_values<Q, QS, Real>(p, cls, f, g, glob, lf, lg);
 #pragma unroll
   for (int j = 0; j < Q; ++j) lam[own_addr<QT>(b, j)] = (Real)lf[j];
 #pragma unroll
@@ -543,28 +559,20 @@ __global__ __launch_bounds__(256) void k_seed(Params<Real> p, const Real* __rest
 }
 
 // ------------------------------------------------------------ adjoint step
-// lambda^n(x) = (dW^x/df)^T(f^n(x)) mu(x),  mu_j(x) = lambda^{n+1}_j(x + e_j)
-// grad(x)    += (dW^x/dw)^T mu(x)            (interior nodes only)
-// The vector-Jacobian products below are hand-derived from the operators above.
-template <int Q, int QS, typename Real, bool NT>
-__device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* __restrict__ prim,
-                                             const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
-                                             const Real* __restrict__ w, Real* __restrict__ grad, int x, int y,
-                                             int z) {
+// Vector-Jacobian product of one node operator: given the pre-collision state
+// (f, g) and design value wn of the node and the cotangents (mu, nu) of its
+// post-collision populations, returns lambda = (dW/d(f,g))^T (mu, nu) and
+// gw = (dW/dw)^T (mu, nu) (zero except at interior nodes).  Wall and inlet
+// operators are affine in (f, g): their products do not read f or g.
+// Hand-derived from the operators above.
+template <int Q, int QS, typename Real>
+__device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, const Real (&f)[Q],
+                                            const Real (&g)[QS > 0 ? QS : 1], Real wn, const Real (&mu)[Q],
+                                            const Real (&nu)[QS > 0 ? QS : 1], Real (&lf)[Q],
+                                            Real (&lg)[QS > 0 ? QS : 1], Real& gw) {
   using L = Lat<Q>;
   using S = SLat<QS>;
-  constexpr bool is3d = (Q == 19);
-  constexpr int QSA = QS > 0 ? QS : 1;
-  constexpr int QT = Q + QS;
-  const Nbr b = make_nbr(p, x, y, z);
-  const int n = own_node(b);
-  Real mu[Q], nu[QSA];
-#pragma unroll
-  for (int j = 0; j < Q; ++j) mu[j] = lam_in[push_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))];
-#pragma unroll
-  for (int i = 0; i < QS; ++i) nu[i] = lam_in[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
-  const int cls = node_class(p, x, y, z, is3d);
-  Real lf[Q], lg[QSA];
+  gw = Real(0);
   const Real om1 = Real(1) - p.om;
   const Real oms1 = Real(1) - p.oms;
   if (cls == WALL) {
@@ -600,8 +608,6 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
       for (int i = 0; i < QS; ++i) lg[i] = (i == kPX) ? Real(0) : oms1 * (nu[i] - nu[kPX]);
     }
   } else {
-    Real f[Q], g[QSA];
-    pull_state<Q, QS, Real>(prim, b, f, g);
     if (cls == INTERIOR) {
       Real drho = 0, mx = 0, my = 0, mz = 0;
 #pragma unroll
@@ -616,7 +622,7 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
       const Real ux = mx * inv, uy = my * inv, uz = mz * inv;
       const Real usq = ux * ux + uy * uy + uz * uz;
       Real G, dG;
-      switch_fn(p, w[n], G, dG);
+      switch_fn(p, wn, G, dG);
       const Real G2 = G * G;
       // cotangent moments M0 = sum mu w, M1 = sum mu w e, P = sum mu w (e.u) e
       Real M0 = 0, M1x = 0, M1y = 0, M1z = 0, Px = 0, Py = 0, Pz = 0;
@@ -672,7 +678,7 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
         if (L::ez(k)) v += Real(L::ez(k)) * dmz;
         lf[k] = v;
       }
-      grad[n] += dG * dLdG;
+      gw = dG * dLdG;
     } else {  // OUTLET
       Real s0 = 0, sp = 0;
 #pragma unroll
@@ -723,6 +729,41 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
       }
     }
   }
+}
+
+// lambda^n(x) = (dW^x/df)^T(f^n(x)) mu(x),  mu_j(x) = lambda^{n+1}_j(x + e_j)
+// grad(x)    += (dW^x/dw)^T mu(x)            (interior nodes only)
+// The vector-Jacobian products below are hand-derived from the operators above.
+template <int Q, int QS, typename Real, bool NT>
+__device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* __restrict__ prim,
+                                             const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
+                                             const Real* __restrict__ w, Real* __restrict__ grad, int x, int y,
+                                             int z) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  constexpr bool is3d = (Q == 19);
+  constexpr int QSA = QS > 0 ? QS : 1;
+  constexpr int QT = Q + QS;
+  const Nbr b = make_nbr(p, x, y, z);
+  const int n = own_node(b);
+  Real mu[Q], nu[QSA];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) mu[j] = lam_in[push_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))];
+#pragma unroll
+  for (int i = 0; i < QS; ++i) nu[i] = lam_in[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
+  const int cls = node_class(p, x, y, z, is3d);
+  Real f[Q], g[QSA], lf[Q], lg[QSA], gw;
+  if (cls == INTERIOR || cls == OUTLET) {
+    pull_state<Q, QS, Real>(prim, b, f, g);
+  } else {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) f[j] = Real(0);
+#pragma unroll
+    for (int i = 0; i < QSA; ++i) g[i] = Real(0);
+  }
+  const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
+  adjoint_vjp<Q, QS, Real>(p, cls, f, g, wn, mu, nu, lf, lg, gw);
+  if (cls == INTERIOR) grad[n] += gw;
 #pragma unroll
   for (int j = 0; j < Q; ++j) put<NT>(lam_out + own_addr<QT>(b, j), lf[j]);
 #pragma unroll
@@ -869,6 +910,73 @@ __global__ __launch_bounds__(256) void k_get_adjoint(Params<Real> p, const Real*
   if (lg) {
 #pragma unroll
     for (int i = 0; i < QS; ++i) lg[(size_t)i * p.N + n] = (double)lam[own_addr<QT>(b, Q + i)];
+  }
+}
+
+// ----------------------------------------------------------- one-shot step
+// One iteration of the one-shot descent (Section 3.3, eq. gradient:update),
+// fused for one node: the primal state f^n is pulled once and used by
+//   lambda^{n+1}(x) = (dW/df)^T(f^n(x)) mu(x) + dJ/df(f^n(x))   (eq. adjoint:iteration)
+//   g(x)            = (dW/dw)^T(f^n(x)) mu(x)                   (eq. adjoint:derivative)
+//   h^n(x)          = W(f^n(x), w(x))                           (eq. normal:iteration)
+//   w(x)           <- clip(w + zeta (g + c_pen (1 - 2w)), 0, 1) (interior nodes; eq. P)
+// with mu_j(x) = lambda^n_j(x + e_j).  Each node owns its w, so the in-place
+// update races with nothing.
+template <int Q, int QS, typename Real, bool NT>
+__global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __restrict__ prim_in,
+                                                 Real* __restrict__ prim_out, const Real* __restrict__ lam_in,
+                                                 Real* __restrict__ lam_out, Real* __restrict__ w,
+                                                 Real* __restrict__ grad, const double* __restrict__ glob, Real zeta,
+                                                 Real c_pen) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  constexpr bool is3d = (Q == 19);
+  constexpr int QSA = QS > 0 ? QS : 1;
+  constexpr int QT = Q + QS;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  const int y = blockIdx.y, z = blockIdx.z;
+  const Nbr b = make_nbr(p, x, y, z);
+  const int n = own_node(b);
+  const int cls = node_class(p, x, y, z, is3d);
+  Real f[Q], g[QSA], mu[Q], nu[QSA];
+  pull_state<Q, QS, Real>(prim_in, b, f, g);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) mu[j] = lam_in[push_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))];
+#pragma unroll
+  for (int i = 0; i < QS; ++i) nu[i] = lam_in[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
+  const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
+  Real lf[Q], lg[QSA], gw;
+  adjoint_vjp<Q, QS, Real>(p, cls, f, g, wn, mu, nu, lf, lg, gw);
+  if (cls == INLET || cls == OUTLET) {
+    double sf[Q], sg[QSA];
+    seed_values<Q, QS, Real>(p, cls, f, g, glob, sf, sg);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) lf[j] += (Real)sf[j];
+#pragma unroll
+    for (int i = 0; i < QS; ++i) lg[i] += (Real)sg[i];
+  }
+  if (cls == INTERIOR) {
+    collide_interior<Q, QS, Real>(p, wn, f, g);
+  } else if (cls == WALL) {
+    collide_wall<Q, QS, Real>(p, f, g);
+  } else if (cls == INLET) {
+    collide_inlet<Q, QS, Real>(p, y, z, f, g);
+  } else {
+    collide_outlet<Q, QS, Real>(p, f, g);
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) put<NT>(prim_out + own_addr<QT>(b, j), f[j]);
+#pragma unroll
+  for (int i = 0; i < QS; ++i) put<NT>(prim_out + own_addr<QT>(b, Q + i), g[i]);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) put<NT>(lam_out + own_addr<QT>(b, j), lf[j]);
+#pragma unroll
+  for (int i = 0; i < QS; ++i) put<NT>(lam_out + own_addr<QT>(b, Q + i), lg[i]);
+  grad[n] = gw;
+  if (cls == INTERIOR) {
+    const Real v = wn + zeta * (gw + c_pen * (Real(1) - Real(2) * wn));
+    w[n] = v < Real(0) ? Real(0) : (v > Real(1) ? Real(1) : v);
   }
 }
 

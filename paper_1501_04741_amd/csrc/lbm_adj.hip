@@ -89,6 +89,7 @@ struct lbm_ctx {
   int64_t t_adj = -1;     // adjoint time (lambda^{t_adj} in lam[lam_cur])
   int lam_cur = 0;
   int64_t ring_seg = -1;  // trajectory segment currently held by the ring
+  bool os_active = false; // one-shot iteration running (adjoint state in lam[lam_cur])
   std::string err;
 };
 
@@ -292,6 +293,18 @@ struct Ops {
       hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false>), g.grid, g.block, 0, c->stream, P(c), (const Real*)prim,
                          (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
   }
+  static void oneshot(lbm_ctx* c, const void* src, void* dst, const void* lin, void* lout, double zeta,
+                      double pen) {
+    Geo g = node_geometry(c->cfg);
+    if (nt(c))
+      hipLaunchKernelGGL((k_oneshot<Q, QS, Real, true>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
+                         (Real*)dst, (const Real*)lin, (Real*)lout, (Real*)c->w, (Real*)c->grad,
+                         (const double*)c->glob, (Real)zeta, (Real)pen);
+    else
+      hipLaunchKernelGGL((k_oneshot<Q, QS, Real, false>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
+                         (Real*)dst, (const Real*)lin, (Real*)lout, (Real*)c->w, (Real*)c->grad,
+                         (const double*)c->glob, (Real)zeta, (Real)pen);
+  }
   static void get_adjoint(lbm_ctx* c, const void* lam, double* lf, double* lg) {
     Geo g = node_geometry(c->cfg);
     hipLaunchKernelGGL((k_get_adjoint<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)lam, lf, lg);
@@ -480,6 +493,39 @@ struct RunSetDesign {
   }
 };
 
+// One-shot iterations: each is [objective sums of f^n when the seed depends
+// on them] + one fused k_oneshot launch.  The first call zeroes lambda.
+template <class O>
+struct RunOneshot {
+  static lbm_status run(lbm_ctx* c, int64_t nsteps, double zeta, double pen) {
+    if (!c->os_active) {
+      O::fill(c, c->lam[0], (size_t)c->plan.QT * c->plan.N);
+      c->lam_cur = 0;
+      O::objective(c, c->cur, c->glob);
+      c->os_active = true;
+      c->rec_open = false;
+    }
+    const bool state_dependent_seed = (c->cfg.c_var != 0.0);
+    for (int64_t i = 0; i < nsteps; ++i) {
+      if (state_dependent_seed && i > 0) O::objective(c, c->cur, c->glob);
+      void* dst = (c->cur == c->pp[0]) ? c->pp[1] : c->pp[0];
+      O::oneshot(c, c->cur, dst, c->lam[c->lam_cur], c->lam[1 - c->lam_cur], zeta, pen);
+      c->cur = dst;
+      c->lam_cur ^= 1;
+      ++c->t;
+    }
+    return launch_check(c, "one-shot step");
+  }
+};
+
+template <class O>
+struct RunGetDesign {
+  static lbm_status run(lbm_ctx* c, void* out) {
+    O::copy(c, c->w, out, (size_t)c->plan.N);
+    return launch_check(c, "get_design");
+  }
+};
+
 template <class O>
 struct RunWriteStatic {
   static lbm_status run(lbm_ctx* c) { return O::write_static(c); }
@@ -614,6 +660,7 @@ void reset_times(lbm_ctx* c) {
   c->t_adj = -1;
   c->lam_cur = 0;
   c->ring_seg = -1;
+  c->os_active = false;
 }
 
 lbm_status sync_check(lbm_ctx* c, const char* what) {
@@ -727,6 +774,7 @@ lbm_status lbm_primal_steps(lbm_ctx* c, int64_t nsteps, int32_t record) {
   if (nsteps < 0) return fail(c, LBM_EINVAL, "primal_steps: negative count");
   if (!c->design_set) return fail(c, LBM_ESTATE, "primal_steps: no design field set");
   if (c->adj_started) return fail(c, LBM_ESTATE, "primal_steps: adjoint started; call lbm_reset first");
+  if (record && c->os_active) return fail(c, LBM_ESTATE, "primal_steps: one-shot running; call lbm_reset first");
   if (record) {
     if (!(c->rec_open && c->t == c->rec_len))
       return fail(c, LBM_ESTATE, "primal_steps: recording must start at t = 0 or continue a recorded run");
@@ -769,6 +817,7 @@ lbm_status lbm_objective(lbm_ctx* c, double* J_host, double* globals_host) {
 lbm_status lbm_adjoint_steps(lbm_ctx* c, int64_t nsteps) {
   if (!c) return LBM_EINVAL;
   if (nsteps < 0) return fail(c, LBM_EINVAL, "adjoint_steps: negative count");
+  if (c->os_active) return fail(c, LBM_ESTATE, "adjoint_steps: one-shot running; call lbm_reset first");
   if (!c->adj_started) {
     if (!c->design_set) return fail(c, LBM_ESTATE, "adjoint_steps: no design field set");
     if (!(c->rec_open && c->t == c->rec_len))
@@ -783,7 +832,8 @@ lbm_status lbm_adjoint_steps(lbm_ctx* c, int64_t nsteps) {
 lbm_status lbm_gradient(lbm_ctx* c, void* grad_dev) {
   if (!c) return LBM_EINVAL;
   if (!grad_dev) return fail(c, LBM_EINVAL, "gradient: NULL output");
-  if (!(c->adj_started && c->t_adj == 0)) return fail(c, LBM_ESTATE, "gradient: adjoint has not reached t = 0");
+  if (!(c->adj_started && c->t_adj == 0) && !c->os_active)
+    return fail(c, LBM_ESTATE, "gradient: adjoint has not reached t = 0 and no one-shot iteration ran");
   return dispatch<RunGradient>(c, grad_dev);
 }
 
@@ -804,13 +854,29 @@ lbm_status lbm_get_state(lbm_ctx* c, double* f_dev, double* g_dev) {
 lbm_status lbm_get_adjoint(lbm_ctx* c, double* lf_dev, double* lg_dev) {
   if (!c) return LBM_EINVAL;
   if (!lf_dev) return fail(c, LBM_EINVAL, "get_adjoint: NULL output");
-  if (!c->adj_started) return fail(c, LBM_ESTATE, "get_adjoint: adjoint not seeded");
+  if (!c->adj_started && !c->os_active) return fail(c, LBM_ESTATE, "get_adjoint: no adjoint state");
   return dispatch<RunGetAdjoint>(c, lf_dev, lg_dev);
 }
 
 lbm_status lbm_export_maps(lbm_ctx* c, uint8_t* mask_dev, int64_t* src_dev) {
   if (!c) return LBM_EINVAL;
   return dispatch<RunMaps>(c, mask_dev, src_dev);
+}
+
+lbm_status lbm_oneshot_steps(lbm_ctx* c, int64_t nsteps, double zeta, double penalty) {
+  if (!c) return LBM_EINVAL;
+  if (nsteps < 0) return fail(c, LBM_EINVAL, "oneshot_steps: negative count");
+  if (!std::isfinite(zeta) || !std::isfinite(penalty)) return fail(c, LBM_EINVAL, "oneshot_steps: non-finite step");
+  if (!c->design_set) return fail(c, LBM_ESTATE, "oneshot_steps: no design field set");
+  if (c->adj_started) return fail(c, LBM_ESTATE, "oneshot_steps: unsteady adjoint started; call lbm_reset first");
+  return dispatch<RunOneshot>(c, nsteps, zeta, penalty);
+}
+
+lbm_status lbm_get_design(lbm_ctx* c, void* w_dev) {
+  if (!c) return LBM_EINVAL;
+  if (!w_dev) return fail(c, LBM_EINVAL, "get_design: NULL output");
+  if (!c->design_set) return fail(c, LBM_ESTATE, "get_design: no design field set");
+  return dispatch<RunGetDesign>(c, w_dev);
 }
 
 lbm_status lbm_times(const lbm_ctx* c, int64_t* t, int64_t* recorded, int64_t* t_adj) {

@@ -137,6 +137,8 @@ def library():
             "lbm_get_adjoint": [vp, vp, vp],
             "lbm_export_maps": [vp, vp, vp],
             "lbm_times": [vp, P(i64), P(i64), P(i64)],
+            "lbm_oneshot_steps": [vp, i64, d, d],
+            "lbm_get_design": [vp, vp],
             "lbm_plan": [vp, P(i64), P(i64), P(i64), P(u64)],
             "lbm_primal_steps_batch": [P(vp), i32, i64, i32],
             "lbm_adjoint_steps_batch": [P(vp), i32, i64],
@@ -235,6 +237,14 @@ def lbm_get_adjoint(ctx, lf, lg=None):
 
 def lbm_export_maps(ctx, mask=None, src=None):
     _chk(library().lbm_export_maps(ctx, _ptr(mask), _ptr(src)), "lbm_export_maps", ctx)
+
+
+def lbm_oneshot_steps(ctx, nsteps: int, zeta: float, penalty: float = 0.0):
+    _chk(library().lbm_oneshot_steps(ctx, int(nsteps), float(zeta), float(penalty)), "lbm_oneshot_steps", ctx)
+
+
+def lbm_get_design(ctx, w):
+    _chk(library().lbm_get_design(ctx, _ptr(w)), "lbm_get_design", ctx)
 
 
 def lbm_times(ctx):
@@ -366,6 +376,14 @@ class Lbm:
         src = torch.empty(self.Q, self.N, dtype=torch.int64, device=self.device)
         lbm_export_maps(self.ctx, mask, src)
         return mask, src
+
+    def oneshot_steps(self, nsteps: int, zeta: float, penalty: float = 0.0):
+        lbm_oneshot_steps(self.ctx, nsteps, zeta, penalty)
+
+    def design(self):
+        out = torch.empty(self.N, dtype=self.dtype, device=self.device)
+        lbm_get_design(self.ctx, out)
+        return out
 
     def times(self):
         return lbm_times(self.ctx)
