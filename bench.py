@@ -60,18 +60,25 @@ def _class_counts(p):
     return rows_fluid * (nx - 2), wall, rows_fluid, rows_fluid
 
 
-def algorithmic_bytes(p, precision):
-    """Bytes one primal launch and one adjoint launch must move, by node class.
+def moment_values(p):
+    """Values per node the recorded primal keeps for the adjoint (rho, u[, scalar])."""
+    return (3 if p["flow"] == 19 else 2) + 1 + (1 if p.get("scalar", 0) else 0)
 
-    primal:  interior 2*Qt*s + s (pull Qt, store Qt, read w); other classes 2*Qt*s
-    adjoint: interior 3*Qt*s + 3s (primal pull, cotangent pull, store, w, grad
-             read+write); outlet 3*Qt*s; inlet and wall 2*Qt*s (their transposed
+
+def algorithmic_bytes(p, precision):
+    """Bytes one recorded primal launch and one adjoint launch must move, by node class.
+
+    primal (recorded): interior 2*Qt*s + s + M*s (pull Qt, store Qt, read w, write
+             the M moments the adjoint needs); outlet 2*Qt*s + M*s; wall/inlet 2*Qt*s
+    adjoint: interior 2*Qt*s + M*s + 3s (cotangent pull, store, moments, w, grad
+             read+write); outlet 2*Qt*s + M*s; inlet and wall 2*Qt*s (their transposed
              Jacobians do not depend on the primal state)."""
     s = 4 if precision == "fp32" else 8
     qt = p["flow"] + p.get("scalar", 0)
+    m = moment_values(p)
     ni, nw, nin, nout = _class_counts(p)
-    primal = ni * (2 * qt * s + s) + (nw + nin + nout) * 2 * qt * s
-    adjoint = ni * (3 * qt * s + 3 * s) + nout * 3 * qt * s + (nw + nin) * 2 * qt * s
+    primal = ni * (2 * qt * s + s + m * s) + nout * (2 * qt * s + m * s) + (nw + nin) * 2 * qt * s
+    adjoint = ni * (2 * qt * s + m * s + 3 * s) + nout * (2 * qt * s + m * s) + (nw + nin) * 2 * qt * s
     return primal, adjoint
 
 
@@ -216,10 +223,12 @@ def main(argv=None):
     print("[bench] workload %s, N=%d, %s; building context" % (args.workload, N, prec), file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    L = Lbm(p, nsteps=N, precision=prec, checkpoint_interval=wl.get("checkpoint_interval", 0), device=dev)
+    budget = int(wl.get("hbm_budget_gb", 0) * 2**30)
+    L = Lbm(p, nsteps=N, precision=prec, checkpoint_interval=wl.get("checkpoint_interval", 0),
+            hbm_budget_bytes=budget, device=dev)
     plan = L.plan()
     C = plan["interval"]
-    k_last = N - ((N - 1) // C) * C  # adjoint steps of the last segment (in the ring, no recompute)
+    k_last = N - ((N - 1) // C) * C  # adjoint steps of the last segment (moments held, no recompute)
     w_np = inputs.design_for(wl)
     w = torch.from_numpy(w_np).to(dev)
     grad = torch.empty(L.N, dtype=L.dtype, device=dev)
@@ -303,7 +312,7 @@ def main(argv=None):
         "config": {"workload": args.workload, "lattice": "D3Q19" if p["flow"] == 19 else "D2Q9",
                    "scalar": p.get("scalar", 0), "grid": [p["nx"], p["ny"], p["nz"]], "nodes": nodes,
                    "lbm_steps": N, "precision": prec, "checkpoint_interval": C,
-                   "checkpoints": plan["checkpoints"], "ring_slots": plan["ring"],
+                   "checkpoints": plan["checkpoints"], "moment_sets": plan["moment_sets"],
                    "workspace_gb": round(L.workspace_bytes / 1e9, 3), "switch": "%s(%g)" % (p["switch_fn"],
                                                                                           p["switch_param"])},
         "value_definition": "nodes x primal steps differentiated per second: one step = design set, "

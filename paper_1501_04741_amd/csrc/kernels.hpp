@@ -346,11 +346,72 @@ __device__ __forceinline__ void collide_outlet(const Params<Real>& p, Real (&f)[
   }
 }
 
+// Moments of a node's pre-collision state that its transposed Jacobian needs:
+// interior nodes (rho, u, and the scalar T = sum g), outlet nodes (u_x of the
+// Zou-He reconstruction and the scalar sum over the known populations); wall
+// and inlet operators are affine and need none.  The primal step records them
+// (Mom::N values per node per step, plane-major) so the adjoint step does not
+// re-read the Qt populations.  The sums follow the operators' order exactly.
+template <int Q, int QS>
+struct Mom {
+  static constexpr int D = Lat<Q>::D;
+  static constexpr int N = D + 1 + (QS > 0 ? 1 : 0);  // values per node
+  static constexpr int T = D + 1;                      // index of the scalar value
+};
+
+template <int Q, int QS, typename Real>
+__device__ __forceinline__ void node_moments(const Params<Real>& p, int cls, const Real (&f)[Q],
+                                             const Real (&g)[QS > 0 ? QS : 1], Real (&m)[Mom<Q, QS>::N]) {
+  using L = Lat<Q>;
+  using M = Mom<Q, QS>;
+#pragma unroll
+  for (int k = 0; k < M::N; ++k) m[k] = Real(0);
+  if (cls == INTERIOR) {
+    Real drho = 0, mx = 0, my = 0, mz = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      drho += f[j];
+      if (L::ex(j)) mx += Real(L::ex(j)) * f[j];
+      if (L::ey(j)) my += Real(L::ey(j)) * f[j];
+      if (L::ez(j)) mz += Real(L::ez(j)) * f[j];
+    }
+    const Real rho = Real(1) + drho;
+    const Real inv = Real(1) / rho;
+    m[0] = rho;
+    m[1] = mx * inv;
+    m[2] = my * inv;
+    if constexpr (M::D == 3) m[3] = mz * inv;
+    if constexpr (QS > 0) {
+      Real T = 0;
+#pragma unroll
+      for (int i = 0; i < QS; ++i) T += g[i];
+      m[M::T] = T;
+    }
+  } else if (cls == OUTLET) {
+    Real s0 = 0, sp = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      if (L::ex(j) == 0) s0 += f[j];
+      else if (L::ex(j) == 1) sp += f[j];
+    }
+    const Real ro = p.rho_out;
+    m[1] = (s0 + Real(2) * sp - (ro - Real(1))) / ro;
+    if constexpr (QS > 0) {
+      Real rest = 0;
+#pragma unroll
+      for (int i = 0; i < QS; ++i)
+        if (i != kMX) rest += g[i];
+      m[M::T] = rest;
+    }
+  }
+}
+
 // One primal node update: pull, collide by node class, store (coalesced).
-template <int Q, int QS, typename Real, bool NT>
+// With MOM, also records the node's pre-collision moments (see Mom).
+template <int Q, int QS, typename Real, bool NT, bool MOM>
 __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* __restrict__ src,
-                                            Real* __restrict__ dst, const Real* __restrict__ w, int x, int y,
-                                            int z) {
+                                            Real* __restrict__ dst, const Real* __restrict__ w,
+                                            Real* __restrict__ mom, int x, int y, int z) {
   constexpr bool is3d = (Q == 19);
   constexpr int QT = Q + QS;
   const Nbr b = make_nbr(p, x, y, z);
@@ -358,6 +419,14 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* _
   Real f[Q], g[QS > 0 ? QS : 1];
   pull_state<Q, QS, Real>(src, b, f, g);
   const int cls = node_class(p, x, y, z, is3d);
+  if constexpr (MOM) {
+    if (cls == INTERIOR || cls == OUTLET) {  // the only classes whose transposes read them
+      Real m[Mom<Q, QS>::N];
+      node_moments<Q, QS, Real>(p, cls, f, g, m);
+#pragma unroll
+      for (int k = 0; k < Mom<Q, QS>::N; ++k) put<NT>(mom + (size_t)k * p.N + n, m[k]);
+    }
+  }
   if (cls == INTERIOR) {
     collide_interior<Q, QS, Real>(p, w[n], f, g);
   } else if (cls == WALL) {
@@ -373,12 +442,13 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* _
   for (int i = 0; i < QS; ++i) put<NT>(dst + own_addr<QT>(b, Q + i), g[i]);
 }
 
-template <int Q, int QS, typename Real, bool NT>
+template <int Q, int QS, typename Real, bool NT, bool MOM>
 __global__ __launch_bounds__(256) void k_primal(Params<Real> p, const Real* __restrict__ src,
-                                                Real* __restrict__ dst, const Real* __restrict__ w) {
+                                                Real* __restrict__ dst, const Real* __restrict__ w,
+                                                Real* __restrict__ mom) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
-  primal_node<Q, QS, Real, NT>(p, src, dst, w, x, blockIdx.y, blockIdx.z);
+  primal_node<Q, QS, Real, NT, MOM>(p, src, dst, w, mom, x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------------ objective
@@ -559,19 +629,19 @@ __global__ __launch_bounds__(256) void k_seed(Params<Real> p, const Real* __rest
 }
 
 // ------------------------------------------------------------ adjoint step
-// Vector-Jacobian product of one node operator: given the pre-collision state
-// (f, g) and design value wn of the node and the cotangents (mu, nu) of its
-// post-collision populations, returns lambda = (dW/d(f,g))^T (mu, nu) and
-// gw = (dW/dw)^T (mu, nu) (zero except at interior nodes).  Wall and inlet
-// operators are affine in (f, g): their products do not read f or g.
-// Hand-derived from the operators above.
+// Vector-Jacobian product of one node operator: given the moments m of the
+// node's pre-collision state (see Mom), its design value wn and the cotangents
+// (mu, nu) of its post-collision populations, returns lambda =
+// (dW/d(f,g))^T (mu, nu) and gw = (dW/dw)^T (mu, nu) (zero except at interior
+// nodes).  Wall and inlet operators are affine in (f, g): their products do
+// not read m.  Hand-derived from the operators above.
 template <int Q, int QS, typename Real>
-__device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, const Real (&f)[Q],
-                                            const Real (&g)[QS > 0 ? QS : 1], Real wn, const Real (&mu)[Q],
-                                            const Real (&nu)[QS > 0 ? QS : 1], Real (&lf)[Q],
-                                            Real (&lg)[QS > 0 ? QS : 1], Real& gw) {
+__device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, const Real (&m)[Mom<Q, QS>::N],
+                                            Real wn, const Real (&mu)[Q], const Real (&nu)[QS > 0 ? QS : 1],
+                                            Real (&lf)[Q], Real (&lg)[QS > 0 ? QS : 1], Real& gw) {
   using L = Lat<Q>;
   using S = SLat<QS>;
+  using M = Mom<Q, QS>;
   gw = Real(0);
   const Real om1 = Real(1) - p.om;
   const Real oms1 = Real(1) - p.oms;
@@ -609,17 +679,11 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
     }
   } else {
     if (cls == INTERIOR) {
-      Real drho = 0, mx = 0, my = 0, mz = 0;
-#pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        drho += f[j];
-        if (L::ex(j)) mx += Real(L::ex(j)) * f[j];
-        if (L::ey(j)) my += Real(L::ey(j)) * f[j];
-        if (L::ez(j)) mz += Real(L::ez(j)) * f[j];
-      }
-      const Real rho = Real(1) + drho;
+      const Real rho = m[0];
       const Real inv = Real(1) / rho;
-      const Real ux = mx * inv, uy = my * inv, uz = mz * inv;
+      const Real ux = m[1], uy = m[2];
+      Real uz = Real(0);
+      if constexpr (M::D == 3) uz = m[3];
       const Real usq = ux * ux + uy * uy + uz * uz;
       Real G, dG;
       switch_fn(p, wn, G, dG);
@@ -647,10 +711,10 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
       Real duz = rho * (c1 * M1z + c2 * Pz - c3 * uz);
       Real dLdG = rho * (Real(3) * Mu + Real(9) * G * Pu - Real(3) * G * M0 * usq);
       if constexpr (QS > 0) {
-        Real T = 0, N0 = 0, N1x = 0, N1y = 0, N1z = 0;
+        const Real T = m[M::T];
+        Real N0 = 0, N1x = 0, N1y = 0, N1z = 0;
 #pragma unroll
         for (int i = 0; i < QS; ++i) {
-          T += g[i];
           const Real a = nu[i] * Real(S::w(i));
           N0 += a;
           if (S::ex(i)) N1x += Real(S::ex(i)) * a;
@@ -680,14 +744,8 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
       }
       gw = dG * dLdG;
     } else {  // OUTLET
-      Real s0 = 0, sp = 0;
-#pragma unroll
-      for (int j = 0; j < Q; ++j) {
-        if (L::ex(j) == 0) s0 += f[j];
-        else if (L::ex(j) == 1) sp += f[j];
-      }
       const Real ro = p.rho_out;
-      const Real ux = (s0 + Real(2) * sp - (ro - Real(1))) / ro;
+      const Real ux = m[1];
       Real dux = 0, dNy = 0, dNz = 0;
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
@@ -701,10 +759,10 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
       }
       if constexpr (QS > 0) {
         const Real ic2 = Real(1.0 / S::c2());
-        Real rest = 0, N0 = 0, N1x = 0;
+        const Real rest = m[M::T];
+        Real N0 = 0, N1x = 0;
 #pragma unroll
         for (int i = 0; i < QS; ++i) {
-          if (i != kMX) rest += g[i];
           const Real a = nu[i] * Real(S::w(i));
           N0 += a;
           if (S::ex(i)) N1x += Real(S::ex(i)) * a;
@@ -735,7 +793,7 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
 // grad(x)    += (dW^x/dw)^T mu(x)            (interior nodes only)
 // The vector-Jacobian products below are hand-derived from the operators above.
 template <int Q, int QS, typename Real, bool NT>
-__device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* __restrict__ prim,
+__device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* __restrict__ mom,
                                              const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
                                              const Real* __restrict__ w, Real* __restrict__ grad, int x, int y,
                                              int z) {
@@ -752,17 +810,15 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
 #pragma unroll
   for (int i = 0; i < QS; ++i) nu[i] = lam_in[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
   const int cls = node_class(p, x, y, z, is3d);
-  Real f[Q], g[QSA], lf[Q], lg[QSA], gw;
+  Real m[Mom<Q, QS>::N], lf[Q], lg[QSA], gw;
+#pragma unroll
+  for (int k = 0; k < Mom<Q, QS>::N; ++k) m[k] = Real(0);
   if (cls == INTERIOR || cls == OUTLET) {
-    pull_state<Q, QS, Real>(prim, b, f, g);
-  } else {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) f[j] = Real(0);
-#pragma unroll
-    for (int i = 0; i < QSA; ++i) g[i] = Real(0);
+    for (int k = 0; k < Mom<Q, QS>::N; ++k) m[k] = mom[(size_t)k * p.N + n];
   }
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
-  adjoint_vjp<Q, QS, Real>(p, cls, f, g, wn, mu, nu, lf, lg, gw);
+  adjoint_vjp<Q, QS, Real>(p, cls, m, wn, mu, nu, lf, lg, gw);
   if (cls == INTERIOR) grad[n] += gw;
 #pragma unroll
   for (int j = 0; j < Q; ++j) put<NT>(lam_out + own_addr<QT>(b, j), lf[j]);
@@ -771,12 +827,12 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
 }
 
 template <int Q, int QS, typename Real, bool NT>
-__global__ __launch_bounds__(256) void k_adjoint(Params<Real> p, const Real* __restrict__ prim,
+__global__ __launch_bounds__(256) void k_adjoint(Params<Real> p, const Real* __restrict__ mom,
                                                  const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
                                                  const Real* __restrict__ w, Real* __restrict__ grad) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
-  adjoint_node<Q, QS, Real, NT>(p, prim, lam_in, lam_out, w, grad, x, blockIdx.y, blockIdx.z);
+  adjoint_node<Q, QS, Real, NT>(p, mom, lam_in, lam_out, w, grad, x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------ inspection kernels
@@ -946,8 +1002,9 @@ __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __r
 #pragma unroll
   for (int i = 0; i < QS; ++i) nu[i] = lam_in[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
-  Real lf[Q], lg[QSA], gw;
-  adjoint_vjp<Q, QS, Real>(p, cls, f, g, wn, mu, nu, lf, lg, gw);
+  Real m[Mom<Q, QS>::N], lf[Q], lg[QSA], gw;
+  node_moments<Q, QS, Real>(p, cls, f, g, m);
+  adjoint_vjp<Q, QS, Real>(p, cls, m, wn, mu, nu, lf, lg, gw);
   if (cls == INLET || cls == OUTLET) {
     double sf[Q], sg[QSA];
     seed_values<Q, QS, Real>(p, cls, f, g, glob, sf, sg);
@@ -1005,9 +1062,10 @@ struct BatchArgs {
   int n;
   int start[kBatchMax + 1];
   const BatchStatic<Real>* st[kBatchMax];
-  const Real* a[kBatchMax];  // primal: source state; adjoint: primal state h^{n-1}
+  const Real* a[kBatchMax];  // primal: source state; adjoint: moments of f^n
   const Real* b[kBatchMax];  // adjoint: lambda^{n+1}
   Real* c[kBatchMax];        // primal: destination; adjoint: lambda^n
+  Real* m[kBatchMax];        // primal: where to record moments (null: do not record)
 };
 
 // Stores a context's batch descriptor (passed by value, so the upload is a
@@ -1034,10 +1092,17 @@ __global__ __launch_bounds__(kBatchBX) void k_primal_batch(BatchArgs<Real> A) {
   const int x = bx * kBatchBX + threadIdx.x;
   if (x >= S.p.nx) return;
   const int y = row % S.p.ny, z = row / S.p.ny;
-  if (S.nt)
-    primal_node<Q, QS, Real, true>(S.p, A.a[k], A.c[k], S.w, x, y, z);
-  else
-    primal_node<Q, QS, Real, false>(S.p, A.a[k], A.c[k], S.w, x, y, z);
+  if (S.nt) {
+    if (A.m[k])
+      primal_node<Q, QS, Real, true, true>(S.p, A.a[k], A.c[k], S.w, A.m[k], x, y, z);
+    else
+      primal_node<Q, QS, Real, true, false>(S.p, A.a[k], A.c[k], S.w, nullptr, x, y, z);
+  } else {
+    if (A.m[k])
+      primal_node<Q, QS, Real, false, true>(S.p, A.a[k], A.c[k], S.w, A.m[k], x, y, z);
+    else
+      primal_node<Q, QS, Real, false, false>(S.p, A.a[k], A.c[k], S.w, nullptr, x, y, z);
+  }
 }
 
 template <int Q, int QS, typename Real>

@@ -4,21 +4,25 @@
 // The library never allocates device memory: every buffer below is a slice of
 // the caller's workspace.  Workspace layout (each slice 256-byte aligned):
 //   w        N x Real      design field (copied in by lbm_set_design)
-//   grad     N x Real      dJ/dw accumulator
+//   grad     N x Real      dJ/dw accumulator (one-shot: last estimate)
 //   glob     boundary sums + J of the last objective evaluation, objective partials
 //   desc     this context's batch descriptor (constants for batched launches)
 //   lam[2]   2 states      adjoint ping-pong
-//   pp[2]    2 states      primal ping-pong (unrecorded steps, final state)
+//   pp[2]    2 states      primal ping-pong
 //   ckpt[S]  S states      checkpoints h^{sC-1}, s = 0..S-1 (ckpt[0] = h^{-1})
-//   ring[C-1] states       h^{sC}..h^{sC+C-2} of the segment being reversed
-// A "state" is Qt x N values of the context precision.
+//   mom[C]   C moment sets the moments of f^k for the C steps k of one segment
+// A "state" is Qt x N values of the context precision; a "moment set" is
+// Mom::N x N values (rho, u and the scalar value: what the transposed
+// Jacobians read), so the trajectory the adjoint needs costs 4-5 values per
+// node and step instead of Qt.
 //
-// Trajectory bookkeeping (step k computes h^k from h^{k-1}, k = 0..N-1):
-// while recording, h^k goes to ckpt[(k+1)/C] when (k+1) % C == 0 (and a slot
-// is left), else to ring[(k+1) % C] when that is non-zero, else to a primal
-// ping-pong buffer.  The adjoint step n needs h^{n-1}: ckpt[s] when n = sC,
-// ring[n - sC] otherwise; a segment missing from the ring is recomputed from
-// its checkpoint (C - 1 primal steps).
+// Trajectory bookkeeping (step k computes h^k from h^{k-1}, k = 0..N-1): a
+// recorded step writes the moments of f^k to mom[k % C] and h^k to
+// ckpt[(k+1)/C] when (k+1) % C == 0 (while slots are left), else to a primal
+// ping-pong buffer.  The adjoint step n reads mom[n % C]; when segment
+// s = n / C is not the one held in mom, it is recomputed from ckpt[s] (C
+// primal steps through the ping-pong buffers).  With C = N (store-all) no
+// step is ever recomputed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -54,6 +58,7 @@ struct Plan {
   int64_t N = 0;             // nodes
   uint64_t rs = 0;           // bytes per value
   uint64_t state_bytes = 0;  // aligned
+  uint64_t mom_bytes = 0;    // aligned, one moment set
   uint64_t node_bytes = 0;   // aligned N x Real
   int64_t C = 1, S = 1;      // checkpoint interval and slots
   uint64_t total = 0;
@@ -78,7 +83,7 @@ struct lbm_ctx {
   void* lam[2] = {nullptr, nullptr};
   void* pp[2] = {nullptr, nullptr};
   char* ckpt = nullptr;
-  char* ring = nullptr;
+  char* mom = nullptr;
   // time bookkeeping
   int64_t t = 0;          // primal time: current state is h^{t-1}
   int64_t rec_len = 0;    // recorded steps (trajectory h^{-1}..h^{rec_len-1})
@@ -88,7 +93,7 @@ struct lbm_ctx {
   bool adj_started = false;
   int64_t t_adj = -1;     // adjoint time (lambda^{t_adj} in lam[lam_cur])
   int lam_cur = 0;
-  int64_t ring_seg = -1;  // trajectory segment currently held by the ring
+  int64_t mom_seg = -1;   // trajectory segment whose moments mom holds
   bool os_active = false; // one-shot iteration running (adjoint state in lam[lam_cur])
   std::string err;
 };
@@ -140,10 +145,14 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
 }
 
 uint64_t plan_total(const Plan& p, int64_t C, int64_t S) {
-  (void)C;
   uint64_t t = 2 * p.node_bytes + align_up(kGlobBytes) + align_up(kDescBytes);
-  t += (uint64_t)(2 + 2 + S + std::max<int64_t>(C - 1, 0)) * p.state_bytes;
+  t += (uint64_t)(2 + 2 + S) * p.state_bytes + (uint64_t)C * p.mom_bytes;
   return t;
+}
+
+// Values per node in one moment set (must equal Mom<Q,QS>::N of the kernels).
+int mom_values(const lbm_config* c) {
+  return (c->flow == LBM_D3Q19 ? 3 : 2) + 1 + (c->scalar ? 1 : 0);
 }
 
 lbm_status make_plan(const lbm_config* c, Plan* p, std::string* why) {
@@ -155,14 +164,23 @@ lbm_status make_plan(const lbm_config* c, Plan* p, std::string* why) {
   p->N = (int64_t)c->nx * c->ny * c->nz;
   p->rs = (c->precision == LBM_FP32) ? 4 : 8;
   p->state_bytes = align_up((uint64_t)p->QT * p->N * p->rs);
+  p->mom_bytes = align_up((uint64_t)mom_values(c) * p->N * p->rs);
   p->node_bytes = align_up((uint64_t)p->N * p->rs);
   const int64_t Nst = std::max<int64_t>(c->nsteps, 1);
   int64_t C;
   if (c->checkpoint_interval > 0) {
     C = std::min<int64_t>(c->checkpoint_interval, Nst);
   } else if (c->hbm_budget_bytes == 0) {
+    // smallest workspace: minimise S*state + C*moments
     C = 1;
-    while (C * C < Nst) ++C;
+    uint64_t best = plan_total(*p, 1, Nst);
+    for (int64_t cc = 2; cc <= Nst; ++cc) {
+      const uint64_t t = plan_total(*p, cc, (Nst + cc - 1) / cc);
+      if (t < best) {
+        best = t;
+        C = cc;
+      }
+    }
   } else {
     // largest C (fewest recomputed steps) whose workspace fits the budget
     C = 0;
@@ -263,14 +281,25 @@ struct Ops {
     hipLaunchKernelGGL((k_write_desc<Real>), dim3(1), dim3(64), 0, c->stream, h, (BatchStatic<Real>*)c->desc);
     return launch_check(c, "descriptor upload");
   }
-  static void primal(lbm_ctx* c, const void* src, void* dst) {
+  static_assert(Mom<Q, QS>::N == (Q == 19 ? 3 : 2) + 1 + (QS > 0 ? 1 : 0), "moment count mismatch");
+  // One primal step; records the moments of the pulled state when mom != null.
+  static void primal(lbm_ctx* c, const void* src, void* dst, void* mom = nullptr) {
     Geo g = node_geometry(c->cfg);
-    if (nt(c))
-      hipLaunchKernelGGL((k_primal<Q, QS, Real, true>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
-                         (Real*)dst, (const Real*)c->w);
-    else
-      hipLaunchKernelGGL((k_primal<Q, QS, Real, false>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
-                         (Real*)dst, (const Real*)c->w);
+    const Real* s = (const Real*)src;
+    Real* d = (Real*)dst;
+    const Real* w = (const Real*)c->w;
+    Real* m = (Real*)mom;
+    if (nt(c)) {
+      if (m)
+        hipLaunchKernelGGL((k_primal<Q, QS, Real, true, true>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+      else
+        hipLaunchKernelGGL((k_primal<Q, QS, Real, true, false>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+    } else {
+      if (m)
+        hipLaunchKernelGGL((k_primal<Q, QS, Real, false, true>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+      else
+        hipLaunchKernelGGL((k_primal<Q, QS, Real, false, false>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+    }
   }
   static void objective(lbm_ctx* c, const void* src, double* out) {
     double* part = c->glob + kGlobSlots;
@@ -284,13 +313,13 @@ struct Ops {
     hipLaunchKernelGGL((k_seed<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
                        (const double*)c->glob, (Real*)lam);
   }
-  static void adjoint(lbm_ctx* c, const void* prim, const void* lin, void* lout) {
+  static void adjoint(lbm_ctx* c, const void* mom, const void* lin, void* lout) {
     Geo g = node_geometry(c->cfg);
     if (nt(c))
-      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true>), g.grid, g.block, 0, c->stream, P(c), (const Real*)prim,
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
                          (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
     else
-      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false>), g.grid, g.block, 0, c->stream, P(c), (const Real*)prim,
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
                          (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
   }
   static void oneshot(lbm_ctx* c, const void* src, void* dst, const void* lin, void* lout, double zeta,
@@ -346,15 +375,16 @@ lbm_status dispatch(lbm_ctx* c, A&&... a) {
 }
 
 void* ckpt_slot(lbm_ctx* c, int64_t s) { return c->ckpt + (uint64_t)s * c->plan.state_bytes; }
-void* ring_slot(lbm_ctx* c, int64_t i) { return c->ring + (uint64_t)(i - 1) * c->plan.state_bytes; }
+// Moment set of step k (slot k mod C).
+void* mom_slot(lbm_ctx* c, int64_t k) { return c->mom + (uint64_t)(k % c->plan.C) * c->plan.mom_bytes; }
+void* other_pp(lbm_ctx* c, const void* cur) { return (cur == c->pp[0]) ? c->pp[1] : c->pp[0]; }
 
-// Destination of h^k while recording.
+// Destination of h^k while recording: a checkpoint slot or a ping-pong buffer.
 void* rec_dst(lbm_ctx* c, int64_t k) {
   const int64_t C = c->plan.C;
   const int64_t s = (k + 1) / C, i = (k + 1) % C;
   if (i == 0 && s < c->plan.S) return ckpt_slot(c, s);
-  if (i != 0) return ring_slot(c, i);
-  return (c->cur == c->pp[0]) ? c->pp[1] : c->pp[0];
+  return other_pp(c, c->cur);
 }
 
 template <class O>
@@ -362,8 +392,8 @@ struct RunPrimal {
   static lbm_status run(lbm_ctx* c, int64_t nsteps, int record) {
     for (int64_t i = 0; i < nsteps; ++i) {
       void* src = c->cur;
-      void* dst = record ? rec_dst(c, c->t) : ((c->cur == c->pp[0]) ? c->pp[1] : c->pp[0]);
-      O::primal(c, src, dst);
+      void* dst = record ? rec_dst(c, c->t) : other_pp(c, c->cur);
+      O::primal(c, src, dst, record ? mom_slot(c, c->t) : nullptr);
       c->cur = dst;
       ++c->t;
     }
@@ -383,18 +413,19 @@ struct RunObjective {
   }
 };
 
-// Recompute the trajectory segment s into the ring from its checkpoint.
+// Recompute segment s from its checkpoint: steps k = sC .. min(sC + C, N) - 1,
+// recording their moments (the states themselves go through the ping-pong).
 template <class O>
 void recompute_segment(lbm_ctx* c, int64_t s) {
   const int64_t C = c->plan.C;
-  const int64_t last = std::min<int64_t>(s * C + C - 2, c->rec_len - 2);
+  const int64_t end = std::min<int64_t>(s * C + C, c->rec_len);
   const void* src = ckpt_slot(c, s);
-  for (int64_t k = s * C; k <= last; ++k) {
-    void* dst = ring_slot(c, k + 1 - s * C);
-    O::primal(c, src, dst);
+  for (int64_t k = s * C; k < end; ++k) {
+    void* dst = other_pp(c, src);
+    O::primal(c, src, dst, mom_slot(c, k));
     src = dst;
   }
-  c->ring_seg = s;
+  c->mom_seg = s;
 }
 
 // Seeds lambda^N = dJ/df^N and zeroes the gradient (first adjoint call).
@@ -406,7 +437,7 @@ void start_adjoint(lbm_ctx* c) {
   O::fill(c, c->grad, (size_t)c->plan.N);
   c->lam_cur = 0;
   c->t_adj = c->rec_len;
-  c->ring_seg = c->rec_len > 0 ? (c->rec_len - 1) / C : -1;
+  c->mom_seg = c->rec_len > 0 ? (c->rec_len - 1) / C : -1;
   c->adj_started = true;
 }
 
@@ -418,10 +449,8 @@ struct RunAdjoint {
     for (int64_t i = 0; i < nsteps; ++i) {
       const int64_t n = c->t_adj - 1;
       const int64_t s = n / C;
-      if (s != c->ring_seg) recompute_segment<O>(c, s);
-      const int64_t r = n - s * C;
-      const void* prim = (r == 0) ? ckpt_slot(c, s) : ring_slot(c, r);
-      O::adjoint(c, prim, c->lam[c->lam_cur], c->lam[1 - c->lam_cur]);
+      if (s != c->mom_seg) recompute_segment<O>(c, s);
+      O::adjoint(c, mom_slot(c, n), c->lam[c->lam_cur], c->lam[1 - c->lam_cur]);
       c->lam_cur ^= 1;
       --c->t_adj;
     }
@@ -543,12 +572,13 @@ struct RunPrimalBatch {
       int total = 0;
       for (int k = 0; k < n; ++k) {
         lbm_ctx* c = cs[k];
-        void* dst = record ? rec_dst(c, c->t) : ((c->cur == c->pp[0]) ? c->pp[1] : c->pp[0]);
+        void* dst = record ? rec_dst(c, c->t) : other_pp(c, c->cur);
         A.start[k] = total;
         A.st[k] = (const BatchStatic<Real>*)c->desc;
         A.a[k] = (const Real*)c->cur;
         A.b[k] = nullptr;
         A.c[k] = (Real*)dst;
+        A.m[k] = record ? (Real*)mom_slot(c, c->t) : nullptr;
         total += O::batch_blocks(c);
         c->cur = dst;
         ++c->t;
@@ -562,7 +592,7 @@ struct RunPrimalBatch {
 
 // Batched adjoint steps.  Contexts that still have to be seeded are seeded
 // first; before each reverse step, the contexts whose next step lies in a
-// segment missing from their ring recompute it, batched together.
+// segment whose moments are not held recompute it, batched together.
 template <class O>
 struct RunAdjointBatch {
   static lbm_status run(lbm_ctx* c0, lbm_ctx* const* cs, int n, int64_t nsteps) {
@@ -582,11 +612,11 @@ struct RunAdjointBatch {
         lbm_ctx* c = cs[k];
         const int64_t C = c->plan.C;
         const int64_t s = (c->t_adj - 1) / C;
-        if (s == c->ring_seg) continue;
+        if (s == c->mom_seg) continue;
         need[nn] = c;
         seg[nn] = s;
         first[nn] = s * C;
-        last[nn] = std::min<int64_t>(s * C + C - 2, c->rec_len - 2);
+        last[nn] = std::min<int64_t>(s * C + C, c->rec_len) - 1;
         src[nn] = ckpt_slot(c, s);
         longest = std::max<int64_t>(longest, last[nn] - first[nn] + 1);
         ++nn;
@@ -597,12 +627,13 @@ struct RunAdjointBatch {
           const int64_t kk = first[q] + r;
           if (kk > last[q]) continue;
           lbm_ctx* c = need[q];
-          void* dst = ring_slot(c, kk + 1 - seg[q] * c->plan.C);
+          void* dst = other_pp(c, src[q]);
           A.start[m] = total;
           A.st[m] = (const BatchStatic<Real>*)c->desc;
           A.a[m] = (const Real*)src[q];
           A.b[m] = nullptr;
           A.c[m] = (Real*)dst;
+          A.m[m] = (Real*)mom_slot(c, kk);
           total += O::batch_blocks(c);
           src[q] = dst;
           ++m;
@@ -611,18 +642,17 @@ struct RunAdjointBatch {
         A.start[m] = total;
         O::primal_batch(c0->stream, A, total);
       }
-      for (int q = 0; q < nn; ++q) need[q]->ring_seg = seg[q];
+      for (int q = 0; q < nn; ++q) need[q]->mom_seg = seg[q];
       // one reverse step for every context
       int total = 0;
       A.n = n;
       for (int k = 0; k < n; ++k) {
         lbm_ctx* c = cs[k];
-        const int64_t C = c->plan.C;
         const int64_t nstep = c->t_adj - 1;
-        const int64_t s = nstep / C, r = nstep - s * C;
         A.start[k] = total;
         A.st[k] = (const BatchStatic<Real>*)c->desc;
-        A.a[k] = (const Real*)((r == 0) ? ckpt_slot(c, s) : ring_slot(c, r));
+        A.a[k] = (const Real*)mom_slot(c, nstep);
+        A.m[k] = nullptr;
         A.b[k] = (const Real*)c->lam[c->lam_cur];
         A.c[k] = (Real*)c->lam[1 - c->lam_cur];
         total += O::batch_blocks(c);
@@ -659,7 +689,7 @@ void reset_times(lbm_ctx* c) {
   c->adj_started = false;
   c->t_adj = -1;
   c->lam_cur = 0;
-  c->ring_seg = -1;
+  c->mom_seg = -1;
   c->os_active = false;
 }
 
@@ -721,8 +751,8 @@ lbm_status lbm_create(const lbm_config* cfg, void* hip_stream, void* workspace_d
   }
   c->ckpt = q;
   q += (uint64_t)p.S * p.state_bytes;
-  c->ring = q;
-  q += (uint64_t)std::max<int64_t>(p.C - 1, 0) * p.state_bytes;
+  c->mom = q;
+  q += (uint64_t)p.C * p.mom_bytes;
   reset_times(c);
   s = dispatch<RunReset>(c);
   if (s == LBM_OK) s = dispatch<RunWriteStatic>(c);
@@ -887,12 +917,12 @@ lbm_status lbm_times(const lbm_ctx* c, int64_t* t, int64_t* recorded, int64_t* t
   return LBM_OK;
 }
 
-lbm_status lbm_plan(const lbm_ctx* c, int64_t* interval, int64_t* n_checkpoints, int64_t* n_ring,
+lbm_status lbm_plan(const lbm_ctx* c, int64_t* interval, int64_t* n_checkpoints, int64_t* n_moment_sets,
                     uint64_t* state_bytes) {
   if (!c) return LBM_EINVAL;
   if (interval) *interval = c->plan.C;
   if (n_checkpoints) *n_checkpoints = c->plan.S;
-  if (n_ring) *n_ring = std::max<int64_t>(c->plan.C - 1, 0);
+  if (n_moment_sets) *n_moment_sets = c->plan.C;
   if (state_bytes) *state_bytes = c->plan.state_bytes;
   return LBM_OK;
 }

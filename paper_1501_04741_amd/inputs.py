@@ -60,10 +60,11 @@ WORKLOADS = {
         scalar_wall="adiabatic", s_in_lo=0.0, s_in_hi=1.0, s_split_axis=1,
         c_dp=0.1, c_hf=0.0, c_var=1.0, steps=5000, precision="fp32", filter=5, seed=0,
         checkpoint_interval=0),
-    # D3Q19 Brinkman channel 256x128x128 (4.19M nodes), J = pressure drop
+    # D3Q19 Brinkman channel 256x128x128 (4.19M nodes), J = pressure drop; the
+    # 160 GB budget holds the moments of all 2000 steps (no recompute)
     "d3q19_channel_256x128x128": dict(
         _CHANNEL, flow=19, scalar=0, nx=256, ny=128, nz=128, u_in=0.02, c_dp=1.0, c_hf=0.0, c_var=0.0,
-        steps=2000, precision="fp32", filter=5, seed=0, checkpoint_interval=0),
+        steps=2000, precision="fp32", filter=5, seed=0, checkpoint_interval=0, hbm_budget_gb=160),
 }
 
 # Request sizes of the serving stream (drawn uniformly).
@@ -74,7 +75,7 @@ SERVE_SIZES = (
     dict(_CHANNEL, flow=19, scalar=0, nx=192, ny=96, nz=96, u_in=0.02, filter=5),
 )
 
-RUN_KEYS = ("steps", "precision", "filter", "seed", "checkpoint_interval")
+RUN_KEYS = ("steps", "precision", "filter", "seed", "checkpoint_interval", "hbm_budget_gb")
 
 
 def model_params(workload: dict) -> dict:

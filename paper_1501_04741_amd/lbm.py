@@ -257,7 +257,7 @@ def lbm_plan(ctx):
     c, s, r, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64()
     _chk(library().lbm_plan(ctx, ctypes.byref(c), ctypes.byref(s), ctypes.byref(r), ctypes.byref(b)), "lbm_plan",
          ctx)
-    return dict(interval=c.value, checkpoints=s.value, ring=r.value, state_bytes=b.value)
+    return dict(interval=c.value, checkpoints=s.value, moment_sets=r.value, state_bytes=b.value)
 
 
 def lbm_primal_steps_batch(ctxs, nsteps: int, record: bool = False):

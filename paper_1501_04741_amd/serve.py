@@ -375,7 +375,7 @@ class GpuExecutor(Executor):
 
     max_batch = 32
 
-    def __init__(self, device=None, per_request_cap_bytes: int = 4 << 30, arena_bytes: Optional[int] = None):
+    def __init__(self, device=None, per_request_cap_bytes: int = 16 << 30, arena_bytes: Optional[int] = None):
         import torch
 
         from . import lbm as _lbm

@@ -65,21 +65,29 @@ def _bytes(params, nsteps, **kw):
 
 
 def test_checkpoint_plan_sizes(lib):
+    """Workspace = 4 states (2 adjoint, 2 primal ping-pong) + S checkpoints + C
+    moment sets (rho, u[, scalar]: 3-5 values per node) + small node arrays."""
+    MB = 2 ** 20
     p = dict(flow=19, nx=256, ny=128, nz=128)
-    state = 19 * 256 * 128 * 128 * 4
-    total = _bytes(p, 2000)                      # C = 45, S = 45: 45 + 44 + 4 states
-    assert abs(total - 93 * state) < 0.01 * state + 64 * 2**20
-    # a budget that holds everything stores all steps (C = N: 1 + 1999 + 4 states)
-    big = _bytes(p, 2000, hbm_budget_bytes=10**15)
-    assert abs(big - 2004 * state) < 0.01 * state + 64 * 2**20
-    # a budget between picks the largest interval that fits
-    mid = _bytes(p, 2000, hbm_budget_bytes=200 * state)
-    assert mid <= 200 * state
-    # a budget below the sqrt plan is refused
-    cfg = lbm.make_config(p, 2000, hbm_budget_bytes=50 * state)
+    n = 256 * 128 * 128
+    state, mom = 19 * n * 4, 4 * n * 4
+    total = lambda C, S: (4 + S) * state + C * mom
+    # default: the smallest workspace over all intervals
+    best = min(total(C, -(-2000 // C)) for C in range(1, 2001))
+    assert abs(_bytes(p, 2000) - best) < 64 * MB
+    # a budget that holds every step's moments stores all (C = N: no recompute)
+    assert abs(_bytes(p, 2000, hbm_budget_bytes=10 ** 15) - total(2000, 1)) < 64 * MB
+    # a budget in between picks the largest interval that fits
+    budget = 40 * 2 ** 30
+    got = _bytes(p, 2000, hbm_budget_bytes=budget)
+    assert got <= budget
+    C_fit = max(C for C in range(1, 2001) if total(C, -(-2000 // C)) + 64 * MB <= budget)
+    assert abs(got - total(C_fit, -(-2000 // C_fit))) < 64 * MB
+    # a budget below the smallest plan is refused
+    cfg = lbm.make_config(p, 2000, hbm_budget_bytes=best // 2)
     out = ctypes.c_uint64()
     assert lib.lbm_required_bytes(ctypes.byref(cfg), ctypes.byref(out)) == lbm.LBM_ENOMEM
-    # explicit interval
+    # explicit interval, 2D flow + scalar (4 moment values per node)
+    n2 = 512 * 256
     c500 = _bytes(dict(flow=9, scalar=5, nx=512, ny=256), 20000, checkpoint_interval=500)
-    st2 = 14 * 512 * 256 * 4
-    assert abs(c500 - (40 + 499 + 4) * st2) < 0.01 * st2 + 2**20
+    assert abs(c500 - ((4 + 40) * 14 * n2 * 4 + 500 * 4 * n2 * 4)) < 4 * MB
