@@ -534,9 +534,10 @@ struct RunOneshot {
       c->os_active = true;
       c->rec_open = false;
     }
+    // the variance term's source depends on the current outlet mean: refresh the sums every iteration
     const bool state_dependent_seed = (c->cfg.c_var != 0.0);
     for (int64_t i = 0; i < nsteps; ++i) {
-      if (state_dependent_seed && i > 0) O::objective(c, c->cur, c->glob);
+      if (state_dependent_seed) O::objective(c, c->cur, c->glob);
       void* dst = (c->cur == c->pp[0]) ? c->pp[1] : c->pp[0];
       O::oneshot(c, c->cur, dst, c->lam[c->lam_cur], c->lam[1 - c->lam_cur], zeta, pen);
       c->cur = dst;
