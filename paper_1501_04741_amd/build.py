@@ -1,8 +1,13 @@
 """Builds the gfx950 HIP library ``liblbmadj.so`` in place with hipcc.
 
 Flags: ``-O3`` with IEEE float division/sqrt (no fast-math), ``-fPIC -shared``,
-and ``-Xclang -target-feature -Xclang -packed-fp32-ops``: packed FP32 VALU
-instructions are turned off for all device code.
+``-Xclang -target-feature -Xclang -packed-fp32-ops`` (packed FP32 VALU
+instructions are turned off for all device code) and ``-ffp-contract=on``:
+a multiply is fused into an add only inside one source expression, so the
+fusion pattern is a property of the source, not of how a node function was
+inlined.  The single-context and batched kernels share the node functions,
+and with this flag they round identically (batched results are bitwise the
+single-context ones).
 """
 from __future__ import annotations
 
@@ -28,7 +33,7 @@ def hipcc() -> str:
 
 def command(out: str = LIB, extra=()) -> list:
     return [hipcc(), "--offload-arch=%s" % ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on",
             "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include"), *extra,
             "-o", out, *SOURCES]
 
