@@ -30,21 +30,30 @@ METRIC = "primal/adjoint MLUPS + HBM roofline frac; served gradients/s, p50/p99 
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE, each scaled by what the
-# counter reads for a 1 GiB device copy in the same run, for the kernel source whose SHA-256
-# prefix is given; reported only while the source still matches.
+# counter reads for a 1 GiB device copy in the same run.  The figures hold for the kernel sources
+# and compile flags whose SHA-256 prefix is given (kernels.hpp, lattice.hpp, build.py in that
+# order) and are reported only while those files still match.
 COUNTER_TRAFFIC = {
-    "kernels_sha256_16": "3012874cbcbd817b",
+    "sources_sha256_16": "6e1e49e2bf17905c",
     "workload": "d3q19_channel_256x128x128",
-    "k_primal": 653945054,
-    "k_adjoint": 997549319,
+    "k_primal": 718949807,
+    "k_adjoint": 751735607,
+    "k_oneshot": 1324817792,
 }
+_COUNTER_SOURCES = ("paper_1501_04741_amd/csrc/kernels.hpp", "paper_1501_04741_amd/csrc/lattice.hpp",
+                    "paper_1501_04741_amd/build.py")
+
+
+def sources_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in _COUNTER_SOURCES:
+        h.update(open(os.path.join(ROOT, rel), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def _measured_traffic(workload, kernel):
-    import hashlib
-    path = os.path.join(ROOT, "paper_1501_04741_amd", "csrc", "kernels.hpp")
-    sha = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
-    if sha != COUNTER_TRAFFIC["kernels_sha256_16"] or workload != COUNTER_TRAFFIC["workload"]:
+    if sources_sha() != COUNTER_TRAFFIC["sources_sha256_16"] or workload != COUNTER_TRAFFIC["workload"]:
         return None
     return COUNTER_TRAFFIC[kernel]
 
@@ -337,7 +346,8 @@ def main(argv=None):
         "oneshot": {"kernel": "k_oneshot<19,0,float>", "iterations_timed": os_iters,
                     "mlups": nodes / (os_launch_ms * 1e-3) / 1e6,
                     "roofline": {"bound": "hbm", "achieved": os_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                 "frac": os_gbs / HBM_PEAK_GBS, "bytes_per_launch": ob,
+                                 "frac": os_gbs / HBM_PEAK_GBS,
+                                 "traffic": _measured_traffic(args.workload, "k_oneshot"), "bytes_per_launch": ob,
                                  "avg_launch_us": os_launch_ms * 1e3}},
     }
     if not args.no_cpu_baseline:
