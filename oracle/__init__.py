@@ -52,13 +52,21 @@ class Config(ctypes.Structure):
         ("c_dp", ctypes.c_double),
         ("c_hf", ctypes.c_double),
         ("c_var", ctypes.c_double),
+        ("inlet_mode", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
+        ("rho_in", ctypes.c_double),
+        ("u_cap", ctypes.c_double),
+        ("c_mix", ctypes.c_double),
     ]
+
+NG = 9  # boundary sums ("globals") the objective is built from
 
 
 DEFAULTS = dict(
     flow=9, scalar=0, nx=16, ny=8, nz=1, periodic=0, tau=0.8, tau_s=0.6, u_in=0.01, rho_out=1.0,
     scalar_wall="adiabatic", s_split_axis=0, s_wall=1.0, s_in_lo=0.0, s_in_hi=0.0,
     switch_fn="power", switch_param=3.0, c_dp=1.0, c_hf=0.0, c_var=0.0,
+    inlet="velocity", rho_in=1.0, u_cap=0.0, c_mix=0.0,
 )
 CONFIG_KEYS = tuple(DEFAULTS)
 
@@ -123,13 +131,15 @@ def make_config(params: dict) -> Config:
     p.update(params)
     sw = {"adiabatic": 0, "dirichlet": 1}[p["scalar_wall"]] if isinstance(p["scalar_wall"], str) else int(p["scalar_wall"])
     fn = {"power": 0, "ramp": 1}[p["switch_fn"]] if isinstance(p["switch_fn"], str) else int(p["switch_fn"])
+    im = {"velocity": 0, "pressure": 1}[p["inlet"]] if isinstance(p["inlet"], str) else int(p["inlet"])
     return Config(
         flow_q=int(p["flow"]), scalar_q=int(p["scalar"]), nx=int(p["nx"]), ny=int(p["ny"]), nz=int(p["nz"]),
         periodic=int(p["periodic"]), tau=float(p["tau"]), tau_s=float(p["tau_s"]), u_in=float(p["u_in"]),
         rho_out=float(p["rho_out"]), scalar_wall=sw, s_split_axis=int(p["s_split_axis"]),
         s_wall=float(p["s_wall"]), s_in_lo=float(p["s_in_lo"]), s_in_hi=float(p["s_in_hi"]),
         switch_fn=fn, reserved=0, switch_param=float(p["switch_param"]), c_dp=float(p["c_dp"]),
-        c_hf=float(p["c_hf"]), c_var=float(p["c_var"]),
+        c_hf=float(p["c_hf"]), c_var=float(p["c_var"]), inlet_mode=im, reserved2=0, rho_in=float(p["rho_in"]),
+        u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]),
     )
 
 
@@ -219,7 +229,7 @@ def primal(params, w, nsteps, f0=None, g0=None):
     fa, ga = _state_args(cfg, f0, g0)
     fN = np.zeros(q * n)
     gN = np.zeros(max(qs, 1) * n)
-    G = np.zeros(8)
+    G = np.zeros(NG)
     J = ctypes.c_double()
     _check(_load().lbmo_primal(ctypes.byref(cfg), _dp(w), _opt(fa), _opt(ga), int(nsteps), _dp(fN), _dp(gN), _dp(G),
                                ctypes.byref(J)), "primal")

@@ -34,9 +34,13 @@
 //  * switching function G: POWER G(w) = w^theta (theta = 3), or RAMP
 //    G(w) = (1+q) w / (w+q); both satisfy G(0)=0, G(1)=1.
 //  * Brinkman forcing acts at interior nodes only; boundary nodes ignore w.
-//  * inlet: Zou-He velocity plug u = (u_in,0,0) at x = 0; outlet: Zou-He
-//    density rho_out at x = nx-1 with zero transverse velocity; the transverse
-//    momentum correction N_t = 1/2 sum_{e_x=0} f_k e_kt (Hecht-Harting form in 3D).
+//  * inlet: Zou-He velocity plug u = (u_in,0,0) at x = 0, or Zou-He pressure
+//    (density rho_in, u = (u_x,0,0)) whose velocity is limited to u_cap: a node
+//    whose pressure-form velocity would exceed u_cap takes the velocity form at
+//    u_cap instead (the setup of Section 4 states the limit, not how it acts);
+//    outlet: Zou-He density rho_out at x = nx-1 with zero transverse velocity;
+//    the transverse momentum correction N_t = 1/2 sum_{e_x=0} f_k e_kt
+//    (Hecht-Harting form in 3D).
 //  * walls: rows y in {0, ny-1} (and z in {0, nz-1} in 3D) use full-way
 //    bounce-back; wall rows win over inlet/outlet at corners.
 //  * scalar: D2Q5 weights (1/3, 1/6 x4), c^2 = 1/3; D3Q7 weights (1/4, 1/8 x6),
@@ -110,6 +114,7 @@ Lattice make_lattice(int q) {
 enum { INTERIOR = 0, WALL = 1, INLET = 2, OUTLET = 3 };
 enum { G_POWER = 0, G_RAMP = 1 };
 enum { S_ADIABATIC = 0, S_DIRICHLET = 1 };
+enum { IN_VELOCITY = 0, IN_PRESSURE = 1 };
 
 }  // namespace
 
@@ -128,7 +133,12 @@ struct lbmo_cfg {
   int32_t switch_fn;     // 0 POWER, 1 RAMP
   int32_t reserved;
   double switch_param;   // theta (POWER) or q (RAMP)
-  double c_dp, c_hf, c_var;  // J = c_dp*dp + c_hf*HF + c_var*Var
+  double c_dp, c_hf, c_var;  // J = c_dp*dp + c_hf*HF + c_var*Var + c_mix*Mix
+  int32_t inlet_mode;    // 0 velocity (u_in), 1 pressure (rho_in, velocity capped at u_cap)
+  int32_t reserved2;
+  double rho_in;         // inlet density of the pressure form
+  double u_cap;          // pressure form: largest inlet velocity (0: no limit)
+  double c_mix;          // weight of the mixing flux sum_outlet u_x (1 - T^2)
 };
 }
 
@@ -149,6 +159,8 @@ bool make_model(const lbmo_cfg* c, Model* m) {
   if (c->nx < 3 || c->ny < 3 || c->nz < 1) return false;
   if (c->scalar_q != 0 && !((c->flow_q == 9 && c->scalar_q == 5) || (c->flow_q == 19 && c->scalar_q == 7)))
     return false;
+  if (c->inlet_mode != IN_VELOCITY && c->inlet_mode != IN_PRESSURE) return false;
+  if (c->inlet_mode == IN_PRESSURE && !(c->rho_in > 0.0 && c->u_cap >= 0.0 && c->u_cap < 1.0)) return false;
   m->c = *c;
   m->F = make_lattice(c->flow_q);
   m->S = Lattice();
@@ -217,6 +229,33 @@ T switch_G(const lbmo_cfg& c, const T& w) {
 // Index of the velocity (+1,0,0) and (-1,0,0) in a lattice (paper order: 1, 2).
 constexpr int kPX = 1, kMX = 2;
 
+inline double re(double a) { return a; }
+inline double re(const cplx& a) { return a.real(); }
+
+// Density and normal velocity of an inlet node from P = sum_{e_x=0} f +
+// 2 sum_{e_x=-1} f, the part of the state that arrived from inside.  Mass and
+// x-momentum of the rebuilt state tie them by P = rho (1 - u_x) (Zou-He).
+// Velocity form: u_x = u_in, rho = P / (1 - u_in).  Pressure form: rho = rho_in,
+// u_x = 1 - P / rho_in, unless u_cap > 0 and that exceeds u_cap: then the
+// velocity form at u_cap (the two agree where u_x = u_cap, so rho and u_x are
+// continuous in f).  The branch is decided on the real part.
+template <class T>
+void inlet_state(const lbmo_cfg& c, const T& P, T* rho, T* ux) {
+  if (c.inlet_mode == IN_PRESSURE) {
+    T up = 1.0 - P / c.rho_in;
+    if (c.u_cap > 0.0 && re(up) > c.u_cap) {
+      *ux = T(c.u_cap);
+      *rho = P / (1.0 - c.u_cap);
+    } else {
+      *ux = up;
+      *rho = T(c.rho_in);
+    }
+    return;
+  }
+  *ux = T(c.u_in);
+  *rho = P / (1.0 - c.u_in);
+}
+
 // Local node operator W^x: pre-collision (f, g) at node x -> post-collision (h, gp).
 template <class T>
 void node_op(const Model& M, int cls, int y, int z, const T* f, const T* g, const T& w, T* h, T* gp) {
@@ -273,8 +312,7 @@ void node_op(const Model& M, int cls, int y, int z, const T* f, const T* g, cons
   }
   T rho, u[3] = {T(0.0), T(0.0), T(0.0)};
   if (cls == INLET) {
-    u[0] = T(c.u_in);
-    rho = (s0 + 2.0 * sk) / (1.0 - c.u_in);
+    inlet_state(c, s0 + 2.0 * sk, &rho, &u[0]);
   } else {
     rho = T(c.rho_out);
     u[0] = -1.0 + (s0 + 2.0 * sk) / c.rho_out;
@@ -314,8 +352,9 @@ void node_op(const Model& M, int cls, int y, int z, const T* f, const T* g, cons
 // Boundary sums contributed by one node's pre-collision state (the
 // "Globals" of Section 3.4):
 //  G0 sum inlet rho, G1 inlet count, G2 sum outlet rho, G3 outlet count,
-//  G4 sum outlet u_x*T, G5 sum outlet T, G6 sum outlet T^2, G7 sum outlet u_x.
-constexpr int kNG = 8;
+//  G4 sum outlet u_x*T, G5 sum outlet T, G6 sum outlet T^2, G7 sum outlet u_x,
+//  G8 sum outlet u_x*T^2.
+constexpr int kNG = 9;
 template <class T>
 void node_globals(const Model& M, int cls, const T* f, const T* g, T* G) {
   for (int k = 0; k < kNG; ++k) G[k] = T(0.0);
@@ -330,7 +369,8 @@ void node_globals(const Model& M, int cls, const T* f, const T* g, T* G) {
     else if (F.e[j][0] == -sgn) sk += f[j];
   }
   if (cls == INLET) {
-    G[0] = (s0 + 2.0 * sk) / (1.0 - c.u_in);
+    T ux;
+    inlet_state(c, s0 + 2.0 * sk, &G[0], &ux);
     G[1] = T(1.0);
     return;
   }
@@ -347,6 +387,7 @@ void node_globals(const Model& M, int cls, const T* f, const T* g, T* G) {
     G[4] = ux * sT;
     G[5] = sT;
     G[6] = sT * sT;
+    G[8] = ux * sT * sT;
   }
 }
 
@@ -364,6 +405,8 @@ T objective_from_globals(const Model& M, const T* G) {
     T mean = G[5] / G[3];
     J += c.c_var * (G[6] / G[3] - mean * mean);
   }
+  // mixing flux of the outlet, sum u_x (1 - T)(1 + T)  (eq. mixing:obj)
+  if (c.c_mix != 0.0) J += c.c_mix * (G[7] - G[8]);
   return J;
 }
 
@@ -682,7 +725,7 @@ int lbmo_adjoint(const lbmo_cfg* cfg, const double* w, const double* f0, const d
 // inlet/outlet the way the node operators reconstruct them.
 //   interior: rho = sum f, u = m / rho, T = sum g
 //   wall:     rho = sum f, u = 0, T = sum g (adiabatic) or T_wall (Dirichlet)
-//   inlet:    Zou-He rho, u = (u_in,0,0), T = inlet value
+//   inlet:    Zou-He rho and u = (u_x,0,0) of the inlet form, T = inlet value
 //   outlet:   rho_out, u = (u_x,0,0), T = reconstructed outflow value
 int lbmo_fields(const lbmo_cfg* cfg, const double* fs, const double* gs, double* rho, double* u, double* T) {
   Model M;
@@ -712,8 +755,11 @@ int lbmo_fields(const lbmo_cfg* cfg, const double* fs, const double* gs, double*
           double G[kNG];
           node_globals<double>(M, cls, f, g, G);
           if (cls == INLET) {
-            r = G[0];
-            uo[0] = c.u_in;
+            double s0 = 0, sk = 0;
+            for (int j = 0; j < Q; ++j)
+              if (M.F.e[j][0] == 0) s0 += f[j];
+              else if (M.F.e[j][0] == -1) sk += f[j];
+            inlet_state(c, s0 + 2.0 * sk, &r, &uo[0]);
             if (Qs) s = inlet_scalar(c, y, z);
           } else {
             r = c.rho_out;
