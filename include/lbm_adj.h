@@ -7,8 +7,9 @@
  *      (Section 2.1, eq. normal:iteration), with the node operators W^x of
  *      Section 3: BGK (eq. SRT) with exact-difference forcing (Section 3.1)
  *      carrying the Brinkman velocity switch u_post = G(w) u_pre (Section 3.2),
- *      Zou-He inlet/outlet, bounce-back walls, and an optional passive scalar
- *      on the first 5 (2D) / 7 (3D) velocities;
+ *      Zou-He inlet (velocity, or pressure with a velocity limit as in the
+ *      channel setup of Section 4) and outlet, bounce-back walls, and an
+ *      optional passive scalar on the first 5 (2D) / 7 (3D) velocities;
  *   2. the discrete adjoint step: reverse streaming (Lemma 1) followed by the
  *      transposed local Jacobian (eq. adjoint:operator), unsteady form over N
  *      steps, with the trajectory recovered by checkpoint + recompute;
@@ -68,6 +69,7 @@ enum { LBM_SCALAR_NONE = 0, LBM_D2Q5 = 5, LBM_D3Q7 = 7 };
 enum { LBM_FP32 = 4, LBM_FP64 = 8 };
 enum { LBM_WALL_ADIABATIC = 0, LBM_WALL_DIRICHLET = 1 };
 enum { LBM_G_POWER = 0, LBM_G_RAMP = 1 };
+enum { LBM_INLET_VELOCITY = 0, LBM_INLET_PRESSURE = 1 };
 
 /* Model and run configuration (the paper's "Settings", Section 3.4). */
 typedef struct lbm_config {
@@ -89,16 +91,29 @@ typedef struct lbm_config {
                           * G = (1+q) w / (w+q)  (Section 3.2)                */
   int32_t reserved0;     /* must be 0                                        */
   double switch_param;   /* theta or q                                       */
-  double c_dp, c_hf, c_var; /* J = c_dp*dp + c_hf*HF + c_var*Var, where      *
+  double c_dp, c_hf, c_var; /* J = c_dp*dp + c_hf*HF + c_var*Var + c_mix*Mix,  *
                           * dp = c_s^2 (mean inlet rho - mean outlet rho),   *
                           * HF = sum over outlet of u_x*s, Var = outlet      *
-                          * variance of s (the "Globals" of Section 3.4)     */
+                          * variance of s, Mix = sum over outlet of          *
+                          * u_x (1 - s^2) (eq. mixing:obj); the "Globals" of *
+                          * Section 3.4                                      */
   int64_t nsteps;        /* horizon N the context is sized for (>= 0); a     *
                           * recorded forward run may not exceed it           */
   int64_t checkpoint_interval; /* C >= 1, or 0 = automatic (see below)       */
-  uint64_t hbm_budget_bytes;   /* automatic C: 0 = C = ceil(sqrt(N)); else   *
-                          * the largest C whose workspace fits the budget    *
-                          * (C = N, store-all, when it fits)                 */
+  uint64_t hbm_budget_bytes;   /* automatic C: 0 = the C with the smallest   *
+                          * workspace; else the largest C whose workspace    *
+                          * fits the budget (C = N, store-all, when it fits) */
+  int32_t inlet;         /* LBM_INLET_VELOCITY: Zou-He velocity u = (u_in,0,0)*
+                          * LBM_INLET_PRESSURE: Zou-He density rho_in with   *
+                          * u = (u_x,0,0) from the known populations; a node *
+                          * whose u_x would exceed u_cap (> 0) takes the     *
+                          * velocity form at u_cap instead (Section 4 limits *
+                          * the inlet velocity; this is the reading)         */
+  int32_t reserved1;     /* must be 0                                        */
+  double rho_in;         /* pressure inlet density (> 0)                     */
+  double u_cap;          /* pressure inlet velocity limit, 0 <= u_cap < 1;   *
+                          * 0 = no limit                                     */
+  double c_mix;          /* weight of the mixing flux Mix (see c_dp)         */
 } lbm_config;
 
 /* Workspace size for cfg (cfg->nsteps and the checkpoint plan included).
@@ -140,9 +155,10 @@ lbm_status lbm_primal_steps(lbm_ctx* ctx, int64_t nsteps, int32_t record);
 
 /* Objective of the current pre-collision state f^t (the node-sum objective
  * of eq. objective:function through the boundary "Globals").  Synchronises.
- * globals_host (nullable) receives 8 doubles: sum inlet rho, inlet count,
+ * globals_host (nullable) receives 9 doubles: sum inlet rho, inlet count,
  * sum outlet rho, outlet count, sum outlet u_x*s, sum outlet s,
- * sum outlet s^2, sum outlet u_x.  Errors: LBM_ENONFINITE for NaN/inf. */
+ * sum outlet s^2, sum outlet u_x, sum outlet u_x*s^2.
+ * Errors: LBM_ENONFINITE for NaN/inf. */
 lbm_status lbm_objective(lbm_ctx* ctx, double* J_host, double* globals_host);
 
 /* Same as lbm_objective but writes J to device memory, no synchronisation. */

@@ -32,6 +32,7 @@ namespace lbmk {
 enum : int { INTERIOR = 0, WALL = 1, INLET = 2, OUTLET = 3 };
 enum : int { G_POWER = 0, G_RAMP = 1 };
 enum : int { S_ADIABATIC = 0, S_DIRICHLET = 1 };
+enum : int { IN_VELOCITY = 0, IN_PRESSURE = 1 };
 
 // Per-context parameters, passed by value to every kernel.
 template <typename Real>
@@ -44,7 +45,11 @@ struct Params {
   Real u_in, rho_out;
   Real s_wall, s_in_lo, s_in_hi;
   Real sw_param;            // theta (POWER) or q (RAMP)
-  double c_dp, c_hf, c_var; // objective weights
+  int inlet_mode;           // IN_VELOCITY (u_in) or IN_PRESSURE (rho_in, limited to u_cap)
+  Real drho_in;             // rho_in - 1 (pressure inlet; the state is stored shifted)
+  Real u_cap;               // pressure inlet velocity limit (0: none)
+  double rho_in;            // pressure inlet density, for the objective sums
+  double c_dp, c_hf, c_var, c_mix;  // objective weights
 };
 
 template <typename P>
@@ -121,6 +126,32 @@ __device__ __forceinline__ Real inlet_value(const P& p, int y, int z) {
   if (p.split_axis == 1) return (y < p.ny / 2) ? p.s_in_lo : p.s_in_hi;
   if (p.split_axis == 2) return (z < p.nz / 2) ? p.s_in_lo : p.s_in_hi;
   return p.s_in_lo;
+}
+
+// Density offset and normal velocity of an inlet node from the shifted sums
+// s0 = sum_{e_x=0} f~ and sm = sum_{e_x=-1} f~ of the populations that reached
+// x = 0 from inside (their unshifted P = s0 + 2 sm + 1 equals rho (1 - u_x) by
+// mass and x-momentum of the rebuilt state, Zou-He).  Velocity form: u = u_in.
+// Pressure form: rho = rho_in and up = (rho_in - 1 - s0 - 2 sm) / rho_in; when
+// u_cap > 0 and up exceeds it, the node takes the velocity form at u_cap (the
+// two forms agree at up = u_cap).  up is what the adjoint needs to know which
+// form ran, so the recorded primal keeps it.
+template <typename Real>
+__device__ __forceinline__ bool inlet_state(const Params<Real>& p, Real s0, Real sm, Real& u, Real& drho, Real& up) {
+  if (p.inlet_mode == IN_PRESSURE) {
+    up = (p.drho_in - (s0 + Real(2) * sm)) / (Real(1) + p.drho_in);
+    if (!(p.u_cap > Real(0) && up > p.u_cap)) {
+      u = up;
+      drho = p.drho_in;
+      return true;  // pressure form
+    }
+    u = p.u_cap;
+  } else {
+    u = p.u_in;
+    up = u;
+  }
+  drho = (s0 + Real(2) * sm + u) / (Real(1) - u);
+  return false;  // velocity form
 }
 
 // Switching function G(w) and its derivative (Darcy/Brinkman, Section 3.2).
@@ -237,10 +268,11 @@ __device__ __forceinline__ void collide_wall(const Params<Real>& p, Real (&f)[Q]
   }
 }
 
-// Inlet (x = 0): Zou-He velocity u = (u_in, 0, 0); the e_x = +1 populations
-// are rebuilt from their opposites with the transverse correction
-// N_t = 1/2 sum_{e_x=0} f_k e_kt, then BGK at E(rho, u_in).  The scalar's
-// single unknown (+x) population is set so that sum g = T_in.
+// Inlet (x = 0): Zou-He, velocity u = (u_in, 0, 0) or pressure rho_in with
+// its velocity limit (see inlet_state); the e_x = +1 populations are rebuilt
+// from their opposites with the transverse correction
+// N_t = 1/2 sum_{e_x=0} f_k e_kt, then BGK at E(rho, u).  The scalar's single
+// unknown (+x) population is set so that sum g = T_in.
 template <int Q, int QS, typename Real>
 __device__ __forceinline__ void collide_inlet(const Params<Real>& p, int y, int z, Real (&f)[Q],
                                               Real (&g)[QS > 0 ? QS : 1]) {
@@ -257,8 +289,8 @@ __device__ __forceinline__ void collide_inlet(const Params<Real>& p, int y, int 
       sm += f[j];
     }
   }
-  const Real u = p.u_in;
-  const Real drho = (s0 + Real(2) * sm + u) / (Real(1) - u);
+  Real u, drho, up;
+  inlet_state<Real>(p, s0, sm, u, drho, up);
   const Real rho = Real(1) + drho;
   const Real usq = u * u;
   Real fs[Q];
@@ -348,10 +380,12 @@ __device__ __forceinline__ void collide_outlet(const Params<Real>& p, Real (&f)[
 
 // Moments of a node's pre-collision state that its transposed Jacobian needs:
 // interior nodes (rho, u, and the scalar T = sum g), outlet nodes (u_x of the
-// Zou-He reconstruction and the scalar sum over the known populations); wall
-// and inlet operators are affine and need none.  The primal step records them
-// (Mom::N values per node per step, plane-major) so the adjoint step does not
-// re-read the Qt populations.  The sums follow the operators' order exactly.
+// Zou-He reconstruction and the scalar sum over the known populations),
+// pressure-inlet nodes (the pressure-form velocity up and the inlet scalar
+// value); walls and velocity inlets are affine and need none.  The primal step
+// records them (Mom::N values per node per step, plane-major) so the adjoint
+// step does not re-read the Qt populations.  The sums follow the operators'
+// order exactly.
 template <int Q, int QS>
 struct Mom {
   static constexpr int D = Lat<Q>::D;
@@ -359,8 +393,13 @@ struct Mom {
   static constexpr int T = D + 1;                      // index of the scalar value
 };
 
+template <typename Real>
+__device__ __forceinline__ bool has_moments(const Params<Real>& p, int cls) {
+  return cls == INTERIOR || cls == OUTLET || (cls == INLET && p.inlet_mode == IN_PRESSURE);
+}
+
 template <int Q, int QS, typename Real>
-__device__ __forceinline__ void node_moments(const Params<Real>& p, int cls, const Real (&f)[Q],
+__device__ __forceinline__ void node_moments(const Params<Real>& p, int cls, int y, int z, const Real (&f)[Q],
                                              const Real (&g)[QS > 0 ? QS : 1], Real (&m)[Mom<Q, QS>::N]) {
   using L = Lat<Q>;
   using M = Mom<Q, QS>;
@@ -403,6 +442,17 @@ __device__ __forceinline__ void node_moments(const Params<Real>& p, int cls, con
         if (i != kMX) rest += g[i];
       m[M::T] = rest;
     }
+  } else if (cls == INLET && p.inlet_mode == IN_PRESSURE) {
+    Real s0 = 0, sm = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      if (L::ex(j) == 0) s0 += f[j];
+      else if (L::ex(j) == -1) sm += f[j];
+    }
+    Real u, drho, up;
+    inlet_state<Real>(p, s0, sm, u, drho, up);
+    m[1] = up;
+    if constexpr (QS > 0) m[M::T] = inlet_value<Real>(p, y, z);
   }
 }
 
@@ -420,9 +470,9 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* _
   pull_state<Q, QS, Real>(src, b, f, g);
   const int cls = node_class(p, x, y, z, is3d);
   if constexpr (MOM) {
-    if (cls == INTERIOR || cls == OUTLET) {  // the only classes whose transposes read them
+    if (has_moments(p, cls)) {  // the only classes whose transposes read them
       Real m[Mom<Q, QS>::N];
-      node_moments<Q, QS, Real>(p, cls, f, g, m);
+      node_moments<Q, QS, Real>(p, cls, y, z, f, g, m);
 #pragma unroll
       for (int k = 0; k < Mom<Q, QS>::N; ++k) put<NT>(mom + (size_t)k * p.N + n, m[k]);
     }
@@ -453,11 +503,11 @@ __global__ __launch_bounds__(256) void k_primal(Params<Real> p, const Real* __re
 
 // ------------------------------------------------------------ objective
 // Boundary sums ("Globals") of the pre-collision state pulled from src, and
-// J = c_dp*dp + c_hf*HF + c_var*Var.  Stage 1: kObjBlocks blocks each reduce a
-// fixed strided subset of the inlet/outlet nodes in LDS (fixed tree order) and
-// write kNG partial sums; stage 2: one thread adds the partials in block order.
-// out[0..7] = sums (see lbm_objective), out[8] = J.
-constexpr int kNG = 8;
+// J = c_dp*dp + c_hf*HF + c_var*Var + c_mix*Mix.  Stage 1: kObjBlocks blocks
+// each reduce a fixed strided subset of the inlet/outlet nodes in LDS (fixed
+// tree order) and write kNG partial sums; stage 2: one thread adds the partials
+// in block order.  out[0..8] = sums (see lbm_objective), out[9] = J.
+constexpr int kNG = 9;
 constexpr int kObjThreads = 256;
 constexpr int kObjBlocks = 64;
 
@@ -483,13 +533,21 @@ __global__ __launch_bounds__(kObjThreads) void k_objective_partial(Params<Real> 
       Real f[Q], g[QS > 0 ? QS : 1];
       pull_state<Q, QS, Real>(src, b, f, g);
       double s0 = 0, sk = 0;
+      Real s0r = 0, skr = 0;
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
-        if (L::ex(j) == 0) s0 += (double)f[j];
-        else if (L::ex(j) == (side ? 1 : -1)) sk += (double)f[j];
+        if (L::ex(j) == 0) {
+          s0 += (double)f[j];
+          s0r += f[j];
+        } else if (L::ex(j) == (side ? 1 : -1)) {
+          sk += (double)f[j];
+          skr += f[j];
+        }
       }
       if (side == 0) {
-        acc[0] += (1.0 + s0 + 2.0 * sk) / (1.0 - (double)p.u_in);
+        Real u, drho, up;  // which inlet form runs is decided exactly as in the step
+        const bool pressure = inlet_state<Real>(p, s0r, skr, u, drho, up);
+        acc[0] += pressure ? p.rho_in : (1.0 + s0 + 2.0 * sk) / (1.0 - (double)u);
         acc[1] += 1.0;
       } else {
         const double ro = (double)p.rho_out;
@@ -507,6 +565,7 @@ __global__ __launch_bounds__(kObjThreads) void k_objective_partial(Params<Real> 
           acc[4] += ux * T;
           acc[5] += T;
           acc[6] += T * T;
+          acc[8] += ux * T * T;
         }
       }
     }
@@ -540,7 +599,7 @@ __global__ __launch_bounds__(64) void k_objective_final(Params<Real> p, const do
   if (!p.periodic && G[1] > 0 && G[3] > 0) {
     const double dp = L::cs2() * (G[0] / G[1] - G[2] / G[3]);
     const double mean = G[5] / G[3];
-    J = p.c_dp * dp + p.c_hf * G[4] + p.c_var * (G[6] / G[3] - mean * mean);
+    J = p.c_dp * dp + p.c_hf * G[4] + p.c_var * (G[6] / G[3] - mean * mean) + p.c_mix * (G[7] - G[8]);
   }
 #pragma unroll
   for (int k = 0; k < kNG; ++k) out[k] = G[k];
@@ -561,8 +620,17 @@ __device__ __forceinline__ void seed_values(const Params<Real>& p, int cls, cons
 #pragma unroll
   for (int i = 0; i < (QS > 0 ? QS : 1); ++i) lg[i] = 0.0;
   if (cls == INLET && glob[1] > 0) {
+    // inlet rho: P / (1 - u) in the velocity form, the constant rho_in in the pressure form
+    Real s0 = 0, sm = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      if (L::ex(j) == 0) s0 += f[j];
+      else if (L::ex(j) == -1) sm += f[j];
+    }
+    Real u, drho, up;
+    const bool pressure = inlet_state<Real>(p, s0, sm, u, drho, up);
     const double dG0 = p.c_dp * L::cs2() / glob[1];
-    const double c = dG0 / (1.0 - (double)p.u_in);
+    const double c = pressure ? 0.0 : dG0 / (1.0 - (double)u);
 #pragma unroll
     for (int j = 0; j < Q; ++j) lf[j] = (L::ex(j) == 0) ? c : (L::ex(j) == -1 ? 2.0 * c : 0.0);
   }
@@ -583,8 +651,9 @@ __device__ __forceinline__ void seed_values(const Params<Real>& p, int cls, cons
       const double ux = (1.0 + s0 + 2.0 * sp) / ro - 1.0;
       const double a = S::w(kMX) * (1.0 - ux / S::c2());
       const double T = rest / (1.0 - a);
-      const double dT = A4 * ux + A5 + 2.0 * A6 * T;        // dJ/dT*
-      const double dux = A4 * T + dT * (-T * S::w(kMX) / (S::c2() * (1.0 - a)));
+      const double Am = p.c_mix;
+      const double dT = A4 * ux + A5 + 2.0 * A6 * T - 2.0 * Am * ux * T;  // dJ/dT*
+      const double dux = A4 * T + Am * (1.0 - T * T) + dT * (-T * S::w(kMX) / (S::c2() * (1.0 - a)));
 #pragma unroll
       for (int j = 0; j < Q; ++j) lf[j] = (L::ex(j) == 0) ? dux / ro : (L::ex(j) == 1 ? 2.0 * dux / ro : 0.0);
 #pragma unroll
@@ -604,7 +673,7 @@ __device__ __forceinline__ void seed_node(const Params<Real>& p, const Real* __r
   const Nbr b = make_nbr(p, x, y, z);
   const int cls = node_class(p, x, y, z, is3d);
   Real f[Q], g[QS > 0 ? QS : 1];
-  if (QS > 0 && cls == OUTLET) {
+  if ((QS > 0 && cls == OUTLET) || (cls == INLET && p.inlet_mode == IN_PRESSURE)) {
     pull_state<Q, QS, Real>(src, b, f, g);
   } else {
 #pragma unroll
@@ -633,8 +702,8 @@ __global__ __launch_bounds__(256) void k_seed(Params<Real> p, const Real* __rest
 // node's pre-collision state (see Mom), its design value wn and the cotangents
 // (mu, nu) of its post-collision populations, returns lambda =
 // (dW/d(f,g))^T (mu, nu) and gw = (dW/dw)^T (mu, nu) (zero except at interior
-// nodes).  Wall and inlet operators are affine in (f, g): their products do
-// not read m.  Hand-derived from the operators above.
+// nodes).  Wall and velocity-inlet operators are affine in (f, g): their
+// products do not read m.  Hand-derived from the operators above.
 template <int Q, int QS, typename Real>
 __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, const Real (&m)[Mom<Q, QS>::N],
                                             Real wn, const Real (&mu)[Q], const Real (&nu)[QS > 0 ? QS : 1],
@@ -651,27 +720,68 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
 #pragma unroll
     for (int i = 0; i < QS; ++i) lg[i] = (p.scalar_wall == S_DIRICHLET) ? Real(0) : nu[S::opp(i)];
   } else if (cls == INLET) {
-    // h = (1-omega) f* + omega E(rho, u_in): affine in f, no primal needed.
-    const Real u = p.u_in, usq = u * u;
-    Real B = 0, drho = 0, dNy = 0, dNz = 0;
-#pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const Real eu = Real(L::ex(j)) * u;
-      B += mu[j] * Real(L::w(j)) * (Real(1) + Real(3) * eu + Real(4.5) * eu * eu - Real(1.5) * usq);
-      if (L::ex(j) == 1) {
-        drho += om1 * mu[j] * Real(6.0 * L::w(j)) * u;
-        if (L::ey(j)) dNy -= om1 * mu[j] * Real(L::ey(j));
-        if (L::ez(j)) dNz -= om1 * mu[j] * Real(L::ez(j));
-      }
+    // Velocity form (u_in, or u_cap where the pressure form was limited):
+    // h = (1-omega) f* + omega E(rho, u) is affine in f.  Pressure form: rho is
+    // fixed and u = (rho_in - P) / rho_in, so the product runs through u; which
+    // form ran is read from the recorded pressure-form velocity m[1].
+    bool pressure = false;
+    Real u = p.u_in;
+    if (p.inlet_mode == IN_PRESSURE) {
+      const Real up = m[1];
+      pressure = !(p.u_cap > Real(0) && up > p.u_cap);
+      u = pressure ? up : p.u_cap;
     }
-    drho += p.om * B;
-    const Real c = drho / (Real(1) - u);
+    if (!pressure) {
+      const Real usq = u * u;
+      Real B = 0, drho = 0, dNy = 0, dNz = 0;
 #pragma unroll
-    for (int k = 0; k < Q; ++k) {
-      Real v = 0;
-      if (L::ex(k) == 0) v = om1 * mu[k] + c + Real(0.5) * (Real(L::ey(k)) * dNy + Real(L::ez(k)) * dNz);
-      if (L::ex(k) == -1) v = om1 * (mu[k] + mu[L::opp(k)]) + Real(2) * c;
-      lf[k] = v;
+      for (int j = 0; j < Q; ++j) {
+        const Real eu = Real(L::ex(j)) * u;
+        B += mu[j] * Real(L::w(j)) * (Real(1) + Real(3) * eu + Real(4.5) * eu * eu - Real(1.5) * usq);
+        if (L::ex(j) == 1) {
+          drho += om1 * mu[j] * Real(6.0 * L::w(j)) * u;
+          if (L::ey(j)) dNy -= om1 * mu[j] * Real(L::ey(j));
+          if (L::ez(j)) dNz -= om1 * mu[j] * Real(L::ez(j));
+        }
+      }
+      drho += p.om * B;
+      const Real c = drho / (Real(1) - u);
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        Real v = 0;
+        if (L::ex(k) == 0) v = om1 * mu[k] + c + Real(0.5) * (Real(L::ey(k)) * dNy + Real(L::ez(k)) * dNz);
+        if (L::ex(k) == -1) v = om1 * (mu[k] + mu[L::opp(k)]) + Real(2) * c;
+        lf[k] = v;
+      }
+    } else {
+      const Real ro = Real(1) + p.drho_in;
+      Real dux = 0, dNy = 0, dNz = 0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const Real ex = Real(L::ex(j));
+        dux += p.om * ro * mu[j] * Real(L::w(j)) * (Real(3) * ex + Real(9) * ex * ex * u - Real(3) * u);
+        if (L::ex(j) == 1) {
+          dux += om1 * mu[j] * Real(6.0 * L::w(j)) * ro;
+          if (L::ey(j)) dNy -= om1 * mu[j] * Real(L::ey(j));
+          if (L::ez(j)) dNz -= om1 * mu[j] * Real(L::ez(j));
+        }
+      }
+      if constexpr (QS > 0) {
+        // the scalar equilibrium at the fixed inlet value T_in (m[T]) moves with u
+        Real N1x = 0;
+#pragma unroll
+        for (int i = 0; i < QS; ++i)
+          if (S::ex(i)) N1x += Real(S::ex(i)) * nu[i] * Real(S::w(i));
+        dux += p.oms * m[M::T] * N1x * Real(1.0 / S::c2());
+      }
+      const Real c = -dux / ro;
+#pragma unroll
+      for (int k = 0; k < Q; ++k) {
+        Real v = 0;
+        if (L::ex(k) == 0) v = om1 * mu[k] + c + Real(0.5) * (Real(L::ey(k)) * dNy + Real(L::ez(k)) * dNz);
+        if (L::ex(k) == -1) v = om1 * (mu[k] + mu[L::opp(k)]) + Real(2) * c;
+        lf[k] = v;
+      }
     }
     if constexpr (QS > 0) {
 #pragma unroll
@@ -813,7 +923,7 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
   Real m[Mom<Q, QS>::N], lf[Q], lg[QSA], gw;
 #pragma unroll
   for (int k = 0; k < Mom<Q, QS>::N; ++k) m[k] = Real(0);
-  if (cls == INTERIOR || cls == OUTLET) {
+  if (has_moments(p, cls)) {
 #pragma unroll
     for (int k = 0; k < Mom<Q, QS>::N; ++k) m[k] = mom[(size_t)k * p.N + n];
   }
@@ -871,14 +981,26 @@ __global__ __launch_bounds__(256) void k_fields(Params<Real> p, const Real* __re
     if (QS > 0 && p.scalar_wall == S_DIRICHLET) T = (double)p.s_wall;
   } else {
     double s0 = 0, sk = 0;
+    Real s0r = 0, skr = 0;
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      if (L::ex(j) == 0) s0 += (double)f[j];
-      else if (L::ex(j) == (cls == INLET ? -1 : 1)) sk += (double)f[j];
+      if (L::ex(j) == 0) {
+        s0 += (double)f[j];
+        s0r += f[j];
+      } else if (L::ex(j) == (cls == INLET ? -1 : 1)) {
+        sk += (double)f[j];
+        skr += f[j];
+      }
     }
     if (cls == INLET) {
-      r = (1.0 + s0 + 2.0 * sk) / (1.0 - (double)p.u_in);
-      ox = (double)p.u_in;
+      Real uu, drho, up;
+      if (inlet_state<Real>(p, s0r, skr, uu, drho, up)) {
+        r = p.rho_in;
+        ox = (p.rho_in - 1.0 - s0 - 2.0 * sk) / p.rho_in;
+      } else {
+        r = (1.0 + s0 + 2.0 * sk) / (1.0 - (double)uu);
+        ox = (double)uu;
+      }
       if (QS > 0) T = (double)inlet_value<Real>(p, y, z);
     } else {
       r = (double)p.rho_out;
@@ -1003,7 +1125,7 @@ __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __r
   for (int i = 0; i < QS; ++i) nu[i] = lam_in[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
   Real m[Mom<Q, QS>::N], lf[Q], lg[QSA], gw;
-  node_moments<Q, QS, Real>(p, cls, f, g, m);
+  node_moments<Q, QS, Real>(p, cls, y, z, f, g, m);
   adjoint_vjp<Q, QS, Real>(p, cls, m, wn, mu, nu, lf, lg, gw);
   if (cls == INLET || cls == OUTLET) {
     double sf[Q], sg[QSA];

@@ -136,7 +136,10 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
   if (c->switch_fn != LBM_G_POWER && c->switch_fn != LBM_G_RAMP) return bad("bad switch_fn");
   if (c->switch_fn == LBM_G_RAMP && !(c->switch_param > 0.0)) return bad("RAMP needs q > 0");
   if (c->switch_fn == LBM_G_POWER && !(c->switch_param >= 0.0)) return bad("POWER needs theta >= 0");
-  if (c->reserved0 != 0) return bad("reserved0 must be 0");
+  if (c->reserved0 != 0 || c->reserved1 != 0) return bad("reserved0 and reserved1 must be 0");
+  if (c->inlet != LBM_INLET_VELOCITY && c->inlet != LBM_INLET_PRESSURE) return bad("bad inlet");
+  if (c->inlet == LBM_INLET_PRESSURE && !(c->rho_in > 0.0 && c->u_cap >= 0.0 && c->u_cap < 1.0))
+    return bad("pressure inlet needs rho_in > 0 and 0 <= u_cap < 1");
   if (c->nsteps < 0 || c->checkpoint_interval < 0) return bad("nsteps and checkpoint_interval must be >= 0");
   const int64_t N = (int64_t)c->nx * c->ny * c->nz;
   const int QT = c->flow + c->scalar;
@@ -224,9 +227,14 @@ Params<Real> make_params(const lbm_config& c, int64_t N) {
   p.s_in_lo = (Real)c.s_in_lo;
   p.s_in_hi = (Real)c.s_in_hi;
   p.sw_param = (Real)c.switch_param;
+  p.inlet_mode = (c.inlet == LBM_INLET_PRESSURE) ? IN_PRESSURE : IN_VELOCITY;
+  p.drho_in = (Real)(c.rho_in - 1.0);
+  p.u_cap = (Real)c.u_cap;
+  p.rho_in = c.rho_in;
   p.c_dp = c.c_dp;
   p.c_hf = c.c_hf;
   p.c_var = c.c_var;
+  p.c_mix = c.c_mix;
   return p;
 }
 

@@ -65,6 +65,16 @@ WORKLOADS = {
     "d3q19_channel_256x128x128": dict(
         _CHANNEL, flow=19, scalar=0, nx=256, ny=128, nz=128, u_in=0.02, c_dp=1.0, c_hf=0.0, c_var=0.0,
         steps=2000, precision="fp32", filter=5, seed=0, checkpoint_interval=0, hbm_budget_gb=160),
+    # The paper's mixing duct without obstacles (Section 4, table of settings):
+    # 450x50x50, pressure drop 0.016666 (rho_in = 1 + 3 dp) with the inlet velocity
+    # limited to 0.05, nu = 0.02 (tau = 3 nu + 1/2), scalar diffusivity 0.003
+    # (D3Q7, c^2 = 1/4: tau_s = 0.003/0.25 + 1/2), inlet scalar -1 below y = 25
+    # and 1 from there on, adiabatic walls, J = outlet mixing flux; w = 1 (all fluid).
+    "d3q19_d3q7_mixer_empty_450x50x50": dict(
+        _CHANNEL, flow=19, scalar=7, nx=450, ny=50, nz=50, tau=0.56, tau_s=0.512, inlet="pressure",
+        rho_in=1.0 + 3 * 0.016666, u_cap=0.05, u_in=0.0, scalar_wall="adiabatic", s_in_lo=-1.0, s_in_hi=1.0,
+        s_split_axis=1, c_dp=0.0, c_hf=0.0, c_var=0.0, c_mix=1.0, steps=40000, precision="fp32", design="fluid",
+        seed=0, checkpoint_interval=0),
 }
 
 # Request sizes of the serving stream (drawn uniformly).
@@ -75,7 +85,7 @@ SERVE_SIZES = (
     dict(_CHANNEL, flow=19, scalar=0, nx=192, ny=96, nz=96, u_in=0.02, filter=5),
 )
 
-RUN_KEYS = ("steps", "precision", "filter", "seed", "checkpoint_interval", "hbm_budget_gb")
+RUN_KEYS = ("steps", "precision", "filter", "seed", "checkpoint_interval", "hbm_budget_gb", "design")
 
 
 def model_params(workload: dict) -> dict:
@@ -90,9 +100,12 @@ def workload(name: str, **overrides) -> dict:
 
 
 def design_for(wl: dict, dtype=None) -> np.ndarray:
-    """The seeded design field of a workload, in its run precision."""
+    """The seeded design field of a workload, in its run precision ("design":
+    "fluid" is the empty channel, w = 1 everywhere)."""
     if dtype is None:
         dtype = np.float32 if wl.get("precision", "fp64") == "fp32" else np.float64
+    if wl.get("design") == "fluid":
+        return np.ones(wl["nx"] * wl["ny"] * wl["nz"], dtype)
     return porosity(wl["nx"], wl["ny"], wl["nz"], wl.get("seed", 0), wl.get("filter", 3), dtype)
 
 

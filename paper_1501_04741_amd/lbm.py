@@ -70,13 +70,22 @@ class LbmConfig(ctypes.Structure):
         ("nsteps", ctypes.c_int64),
         ("checkpoint_interval", ctypes.c_int64),
         ("hbm_budget_bytes", ctypes.c_uint64),
+        ("inlet", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
+        ("rho_in", ctypes.c_double),
+        ("u_cap", ctypes.c_double),
+        ("c_mix", ctypes.c_double),
     ]
+
+NG = 9  # boundary sums ("globals") lbm_objective returns
+_INLET = {"velocity": 0, "pressure": 1}
 
 
 MODEL_DEFAULTS = dict(
     flow=9, scalar=0, nx=16, ny=8, nz=1, periodic=0, tau=0.8, tau_s=0.6, u_in=0.01, rho_out=1.0,
     scalar_wall="adiabatic", s_split_axis=0, s_wall=1.0, s_in_lo=0.0, s_in_hi=0.0,
     switch_fn="power", switch_param=3.0, c_dp=1.0, c_hf=0.0, c_var=0.0,
+    inlet="velocity", rho_in=1.0, u_cap=0.0, c_mix=0.0,
 )
 
 
@@ -89,6 +98,7 @@ def make_config(params: dict, nsteps: int, precision: str = "fp32", checkpoint_i
     p.update(params)
     sw = _WALL[p["scalar_wall"]] if isinstance(p["scalar_wall"], str) else int(p["scalar_wall"])
     fn = _SWITCH[p["switch_fn"]] if isinstance(p["switch_fn"], str) else int(p["switch_fn"])
+    im = _INLET[p["inlet"]] if isinstance(p["inlet"], str) else int(p["inlet"])
     return LbmConfig(
         struct_size=ctypes.sizeof(LbmConfig), flow=int(p["flow"]), scalar=int(p["scalar"]),
         precision=_PREC[precision], nx=int(p["nx"]), ny=int(p["ny"]), nz=int(p["nz"]),
@@ -97,7 +107,8 @@ def make_config(params: dict, nsteps: int, precision: str = "fp32", checkpoint_i
         s_wall=float(p["s_wall"]), s_in_lo=float(p["s_in_lo"]), s_in_hi=float(p["s_in_hi"]),
         switch_fn=fn, reserved0=0, switch_param=float(p["switch_param"]), c_dp=float(p["c_dp"]),
         c_hf=float(p["c_hf"]), c_var=float(p["c_var"]), nsteps=int(nsteps),
-        checkpoint_interval=int(checkpoint_interval), hbm_budget_bytes=int(hbm_budget_bytes))
+        checkpoint_interval=int(checkpoint_interval), hbm_budget_bytes=int(hbm_budget_bytes), inlet=im,
+        reserved1=0, rho_in=float(p["rho_in"]), u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]))
 
 
 _lock = threading.Lock()
@@ -203,7 +214,7 @@ def lbm_primal_steps(ctx, nsteps: int, record: bool = False):
 
 def lbm_objective(ctx):
     J = ctypes.c_double()
-    G = (ctypes.c_double * 8)()
+    G = (ctypes.c_double * NG)()
     st = library().lbm_objective(ctx, ctypes.byref(J), G)
     if st == LBM_ENONFINITE:
         raise LbmError(st, "lbm_objective", "non-finite objective")

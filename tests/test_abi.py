@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_config_struct_size_matches(lib):
     cfg = lbm.make_config(dict(flow=9, nx=16, ny=8), 10)
-    assert cfg.struct_size == ctypes.sizeof(lbm.LbmConfig) == 160
+    assert cfg.struct_size == ctypes.sizeof(lbm.LbmConfig) == 192
     bad = lbm.make_config(dict(flow=9, nx=16, ny=8), 10)
     bad.struct_size = 150
     out = ctypes.c_uint64()
@@ -52,6 +52,12 @@ def test_config_struct_size_matches(lib):
     (dict(flow=9, nx=16, ny=8, switch_fn="ramp", switch_param=0.0), False),
     (dict(flow=9, nx=16, ny=8, u_in=1.0), False),
     (dict(flow=19, scalar=7, nx=16, ny=8, nz=6), True),
+    (dict(flow=9, nx=16, ny=8, inlet="pressure", rho_in=1.05, u_cap=0.05), True),
+    (dict(flow=9, nx=16, ny=8, inlet="pressure", rho_in=1.05), True),        # no limit
+    (dict(flow=9, nx=16, ny=8, inlet="pressure", rho_in=0.0), False),
+    (dict(flow=9, nx=16, ny=8, inlet="pressure", rho_in=1.05, u_cap=1.0), False),
+    (dict(flow=9, nx=16, ny=8, inlet="pressure", rho_in=1.05, u_cap=-0.1), False),
+    (dict(flow=9, nx=16, ny=8, inlet=2), False),
 ])
 def test_config_validation(lib, params, ok):
     cfg = lbm.make_config(params, 10)
