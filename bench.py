@@ -34,11 +34,11 @@ HBM_PEAK_GBS = 8000.0
 # and compile flags whose SHA-256 prefix is given (kernels.hpp, lattice.hpp, build.py in that
 # order) and are reported only while those files still match.
 COUNTER_TRAFFIC = {
-    "sources_sha256_16": "6e1e49e2bf17905c",
+    "sources_sha256_16": "4c325be8b3a0df12",
     "workload": "d3q19_channel_256x128x128",
-    "k_primal": 718949807,
-    "k_adjoint": 751735607,
-    "k_oneshot": 1324817792,
+    "k_primal": 718954797,
+    "k_adjoint": 751734068,
+    "k_oneshot": 1324587779,
 }
 _COUNTER_SOURCES = ("paper_1501_04741_amd/csrc/kernels.hpp", "paper_1501_04741_amd/csrc/lattice.hpp",
                     "paper_1501_04741_amd/build.py")
@@ -74,21 +74,33 @@ def moment_values(p):
     return (3 if p["flow"] == 19 else 2) + 1 + (1 if p.get("scalar", 0) else 0)
 
 
+def primal_bytes(p, precision, recorded=True):
+    """Bytes one primal launch must move, by node class: interior 2*Qt*s + s (pull Qt,
+    store Qt, read w), other classes 2*Qt*s; a recorded launch also writes the M
+    moments the adjoint needs at interior, outlet and pressure-inlet nodes."""
+    s = 4 if precision == "fp32" else 8
+    qt = p["flow"] + p.get("scalar", 0)
+    m = moment_values(p) if recorded else 0
+    m_in = m if p.get("inlet") == "pressure" else 0
+    ni, nw, nin, nout = _class_counts(p)
+    return ni * (2 * qt * s + s + m * s) + nout * (2 * qt * s + m * s) + nin * (2 * qt * s + m_in * s) + nw * 2 * qt * s
+
+
 def algorithmic_bytes(p, precision):
     """Bytes one recorded primal launch and one adjoint launch must move, by node class.
 
-    primal (recorded): interior 2*Qt*s + s + M*s (pull Qt, store Qt, read w, write
-             the M moments the adjoint needs); outlet 2*Qt*s + M*s; wall/inlet 2*Qt*s
+    primal (recorded): see primal_bytes.
     adjoint: interior 2*Qt*s + M*s + 3s (cotangent pull, store, moments, w, grad
-             read+write); outlet 2*Qt*s + M*s; inlet and wall 2*Qt*s (their transposed
-             Jacobians do not depend on the primal state)."""
+             read+write); outlet and pressure inlet 2*Qt*s + M*s; velocity inlet and
+             wall 2*Qt*s (their transposed Jacobians do not depend on the primal state)."""
     s = 4 if precision == "fp32" else 8
     qt = p["flow"] + p.get("scalar", 0)
     m = moment_values(p)
+    m_in = m if p.get("inlet") == "pressure" else 0
     ni, nw, nin, nout = _class_counts(p)
-    primal = ni * (2 * qt * s + s + m * s) + nout * (2 * qt * s + m * s) + (nw + nin) * 2 * qt * s
-    adjoint = ni * (2 * qt * s + m * s + 3 * s) + nout * (2 * qt * s + m * s) + (nw + nin) * 2 * qt * s
-    return primal, adjoint
+    adjoint = ni * (2 * qt * s + m * s + 3 * s) + nout * (2 * qt * s + m * s) + nin * (2 * qt * s + m_in * s) + \
+        nw * 2 * qt * s
+    return primal_bytes(p, precision, True), adjoint
 
 
 def oneshot_bytes(p, precision):
@@ -99,6 +111,50 @@ def oneshot_bytes(p, precision):
     qt = p["flow"] + p.get("scalar", 0)
     ni, nw, nin, nout = _class_counts(p)
     return ni * (4 * qt * s + 3 * s) + (nw + nin + nout) * (4 * qt * s + s)
+
+
+def mixer_leg(dev, steps=4000, os_iters=400):
+    """Forward steps and one-shot iterations on the paper's mixing duct (450x50x50
+    D3Q19 + D3Q7, pressure inlet with velocity limit, mixing objective), FP32."""
+    import torch
+
+    from paper_1501_04741_amd import inputs
+    from paper_1501_04741_amd.lbm import Lbm
+
+    wl = inputs.workload("d3q19_d3q7_mixer_empty_450x50x50")
+    p = inputs.model_params(wl)
+    w = torch.from_numpy(inputs.design_for(wl)).to(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    P = Lbm(p, nsteps=0, precision="fp32", device=dev)
+    P.set_design(w)
+    P.reset()
+    P.primal_steps(200)
+    ev[0].record()
+    P.primal_steps(steps)
+    ev[1].record()
+    torch.cuda.synchronize()
+    P.close()
+    O = Lbm(p, nsteps=0, precision="fp32", device=dev)
+    O.set_design(w)
+    O.reset()
+    O.oneshot_steps(20, 0.0, 0.0)
+    ev[2].record()
+    O.oneshot_steps(os_iters, 0.0, 0.0)
+    ev[3].record()
+    torch.cuda.synchronize()
+    O.close()
+    nodes = p["nx"] * p["ny"] * p["nz"]
+    prim_us = ev[0].elapsed_time(ev[1]) * 1e3 / steps
+    os_us = ev[2].elapsed_time(ev[3]) * 1e3 / os_iters
+    pb, ob = primal_bytes(p, "fp32", recorded=False), oneshot_bytes(p, "fp32")
+    roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
+    return {"workload": "d3q19_d3q7_mixer_empty_450x50x50", "nodes": nodes,
+            "primal": {"kernel": "k_primal<19,7,float>", "steps_timed": steps, "mlups": nodes / prim_us,
+                       "roofline": roof(pb, prim_us)},
+            "oneshot": {"kernel": "k_oneshot<19,7,float>", "iterations_timed": os_iters, "mlups": nodes / os_us,
+                        "roofline": roof(ob, os_us)},
+            "note": "two primal states (234 MB) fit the 256 MB last-level cache; the one-shot's four do not"}
 
 
 def cpu_baseline(p, w64, steps):
@@ -189,6 +245,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="d3q19_channel_256x128x128")
     ap.add_argument("--lbm-steps", type=int, default=None, help="override the primal horizon N")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixer", action="store_true", help="skip the mixing-duct forward/one-shot leg")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run one device copy of MB megabytes (counter calibration for profiles)")
@@ -350,6 +407,9 @@ def main(argv=None):
                                  "traffic": _measured_traffic(args.workload, "k_oneshot"), "bytes_per_launch": ob,
                                  "avg_launch_us": os_launch_ms * 1e3}},
     }
+    if not args.no_mixer:
+        print("[bench] mixing duct leg", file=sys.stderr, flush=True)
+        rec["mixer"] = mixer_leg(dev)
     if not args.no_cpu_baseline:
         print("[bench] GPU timing done; timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(p, w_np.astype(np.float64), args.cpu_steps)
