@@ -53,13 +53,20 @@ constexpr uint64_t kGlobBytes = (kGlobSlots + kObjBlocks * kNG) * sizeof(double)
 
 uint64_t align_up(uint64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+// Row length of the workspace arrays: nx rounded up to whole 128-byte lines.
+int64_t row_pitch(int32_t nx, int32_t precision) {
+  const int64_t per_line = 128 / (precision == LBM_FP32 ? 4 : 8);
+  return ((int64_t)nx + per_line - 1) / per_line * per_line;
+}
+
 struct Plan {
   int Q = 0, QS = 0, QT = 0;
   int64_t N = 0;             // nodes
+  int64_t pitch = 0, Np = 0; // padded row length, pitch*ny*nz
   uint64_t rs = 0;           // bytes per value
   uint64_t state_bytes = 0;  // aligned
   uint64_t mom_bytes = 0;    // aligned, one moment set
-  uint64_t node_bytes = 0;   // aligned N x Real
+  uint64_t node_bytes = 0;   // aligned Np x Real
   int64_t C = 1, S = 1;      // checkpoint interval and slots
   uint64_t total = 0;
 };
@@ -141,9 +148,9 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
   if (c->inlet == LBM_INLET_PRESSURE && !(c->rho_in > 0.0 && c->u_cap >= 0.0 && c->u_cap < 1.0))
     return bad("pressure inlet needs rho_in > 0 and 0 <= u_cap < 1");
   if (c->nsteps < 0 || c->checkpoint_interval < 0) return bad("nsteps and checkpoint_interval must be >= 0");
-  const int64_t N = (int64_t)c->nx * c->ny * c->nz;
+  const int64_t Np = row_pitch(c->nx, c->precision) * c->ny * c->nz;
   const int QT = c->flow + c->scalar;
-  if ((int64_t)QT * N >= (int64_t(1) << 31)) return bad("lattice too large: Qt*N must be < 2^31");
+  if ((int64_t)QT * Np >= (int64_t(1) << 31)) return bad("lattice too large: Qt*N (rows padded) must be < 2^31");
   return LBM_OK;
 }
 
@@ -165,10 +172,12 @@ lbm_status make_plan(const lbm_config* c, Plan* p, std::string* why) {
   p->QS = c->scalar;
   p->QT = p->Q + p->QS;
   p->N = (int64_t)c->nx * c->ny * c->nz;
+  p->pitch = row_pitch(c->nx, c->precision);
+  p->Np = p->pitch * c->ny * c->nz;
   p->rs = (c->precision == LBM_FP32) ? 4 : 8;
-  p->state_bytes = align_up((uint64_t)p->QT * p->N * p->rs);
-  p->mom_bytes = align_up((uint64_t)mom_values(c) * p->N * p->rs);
-  p->node_bytes = align_up((uint64_t)p->N * p->rs);
+  p->state_bytes = align_up((uint64_t)p->QT * p->Np * p->rs);
+  p->mom_bytes = align_up((uint64_t)mom_values(c) * p->Np * p->rs);
+  p->node_bytes = align_up((uint64_t)p->Np * p->rs);
   const int64_t Nst = std::max<int64_t>(c->nsteps, 1);
   int64_t C;
   if (c->checkpoint_interval > 0) {
@@ -214,6 +223,8 @@ Params<Real> make_params(const lbm_config& c, int64_t N) {
   p.nz = c.nz;
   p.periodic = c.periodic ? 1 : 0;
   p.N = (int)N;
+  p.pitch = (int)row_pitch(c.nx, c.precision);
+  p.Np = p.pitch * c.ny * c.nz;
   p.scalar_wall = c.scalar_wall;
   p.split_axis = c.s_split_axis;
   p.switch_fn = c.switch_fn;
@@ -368,6 +379,15 @@ struct Ops {
   static void copy(lbm_ctx* c, const void* a, void* b, size_t n) {
     hipLaunchKernelGGL((k_copy<Real>), flat_grid(n), dim3(256), 0, c->stream, (const Real*)a, (Real*)b, n);
   }
+  // node array: compact ABI layout -> padded workspace layout, and back
+  static void node_in(lbm_ctx* c, const void* a, void* b) {
+    Geo g = node_geometry(c->cfg);
+    hipLaunchKernelGGL((k_node_in<Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)a, (Real*)b);
+  }
+  static void node_out(lbm_ctx* c, const void* a, void* b) {
+    Geo g = node_geometry(c->cfg);
+    hipLaunchKernelGGL((k_node_out<Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)a, (Real*)b);
+  }
 };
 
 // Calls F::template run<Ops<...>>(args) for the context's lattice/precision.
@@ -442,7 +462,7 @@ void start_adjoint(lbm_ctx* c) {
   const int64_t C = c->plan.C;
   O::objective(c, c->cur, c->glob);
   O::seed(c, c->cur, c->lam[0]);
-  O::fill(c, c->grad, (size_t)c->plan.N);
+  O::fill(c, c->grad, (size_t)c->plan.Np);
   c->lam_cur = 0;
   c->t_adj = c->rec_len;
   c->mom_seg = c->rec_len > 0 ? (c->rec_len - 1) / C : -1;
@@ -469,7 +489,7 @@ struct RunAdjoint {
 template <class O>
 struct RunReset {
   static lbm_status run(lbm_ctx* c) {
-    O::fill(c, ckpt_slot(c, 0), (size_t)c->plan.QT * c->plan.N);
+    O::fill(c, ckpt_slot(c, 0), (size_t)c->plan.QT * c->plan.Np);
     return launch_check(c, "reset");
   }
 };
@@ -485,7 +505,7 @@ struct RunSetState {
 template <class O>
 struct RunGradient {
   static lbm_status run(lbm_ctx* c, void* out) {
-    O::copy(c, c->grad, out, (size_t)c->plan.N);
+    O::node_out(c, c->grad, out);
     return launch_check(c, "gradient");
   }
 };
@@ -525,7 +545,7 @@ struct RunMaps {
 template <class O>
 struct RunSetDesign {
   static lbm_status run(lbm_ctx* c, const void* w) {
-    O::copy(c, w, c->w, (size_t)c->plan.N);
+    O::node_in(c, w, c->w);
     return launch_check(c, "set_design");
   }
 };
@@ -536,7 +556,7 @@ template <class O>
 struct RunOneshot {
   static lbm_status run(lbm_ctx* c, int64_t nsteps, double zeta, double pen) {
     if (!c->os_active) {
-      O::fill(c, c->lam[0], (size_t)c->plan.QT * c->plan.N);
+      O::fill(c, c->lam[0], (size_t)c->plan.QT * c->plan.Np);
       c->lam_cur = 0;
       O::objective(c, c->cur, c->glob);
       c->os_active = true;
@@ -559,7 +579,7 @@ struct RunOneshot {
 template <class O>
 struct RunGetDesign {
   static lbm_status run(lbm_ctx* c, void* out) {
-    O::copy(c, c->w, out, (size_t)c->plan.N);
+    O::node_out(c, c->w, out);
     return launch_check(c, "get_design");
   }
 };
