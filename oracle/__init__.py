@@ -57,6 +57,9 @@ class Config(ctypes.Structure):
         ("rho_in", ctypes.c_double),
         ("u_cap", ctypes.c_double),
         ("c_mix", ctypes.c_double),
+        ("collision", ctypes.c_int32),
+        ("reserved3", ctypes.c_int32),
+        ("mrt_s", ctypes.c_double * 5),
     ]
 
 NG = 9  # boundary sums ("globals") the objective is built from
@@ -67,6 +70,7 @@ DEFAULTS = dict(
     scalar_wall="adiabatic", s_split_axis=0, s_wall=1.0, s_in_lo=0.0, s_in_hi=0.0,
     switch_fn="power", switch_param=3.0, c_dp=1.0, c_hf=0.0, c_var=0.0,
     inlet="velocity", rho_in=1.0, u_cap=0.0, c_mix=0.0,
+    collision="bgk", mrt_rates=(1.19, 1.4, 1.2, 1.4, 1.98),
 )
 CONFIG_KEYS = tuple(DEFAULTS)
 
@@ -96,6 +100,7 @@ def _load():
     sig = {
         "lbmo_threads": (ctypes.c_int, [ctypes.c_int]),
         "lbmo_lattice": (ctypes.c_int, [ctypes.c_int, P(ctypes.c_int32), d, P(ctypes.c_int32), d]),
+        "lbmo_mrt": (ctypes.c_int, [c, d, d, d]),
         "lbmo_mask": (ctypes.c_int, [c, P(ctypes.c_uint8)]),
         "lbmo_src_map": (ctypes.c_int, [c, P(ctypes.c_int64)]),
         "lbmo_node_op": (ctypes.c_int, [c, ctypes.c_int, ctypes.c_int, ctypes.c_int, d, d, ctypes.c_double, d, d]),
@@ -132,6 +137,7 @@ def make_config(params: dict) -> Config:
     sw = {"adiabatic": 0, "dirichlet": 1}[p["scalar_wall"]] if isinstance(p["scalar_wall"], str) else int(p["scalar_wall"])
     fn = {"power": 0, "ramp": 1}[p["switch_fn"]] if isinstance(p["switch_fn"], str) else int(p["switch_fn"])
     im = {"velocity": 0, "pressure": 1}[p["inlet"]] if isinstance(p["inlet"], str) else int(p["inlet"])
+    co = {"bgk": 0, "mrt": 1}[p["collision"]] if isinstance(p["collision"], str) else int(p["collision"])
     return Config(
         flow_q=int(p["flow"]), scalar_q=int(p["scalar"]), nx=int(p["nx"]), ny=int(p["ny"]), nz=int(p["nz"]),
         periodic=int(p["periodic"]), tau=float(p["tau"]), tau_s=float(p["tau_s"]), u_in=float(p["u_in"]),
@@ -139,7 +145,8 @@ def make_config(params: dict) -> Config:
         s_wall=float(p["s_wall"]), s_in_lo=float(p["s_in_lo"]), s_in_hi=float(p["s_in_hi"]),
         switch_fn=fn, reserved=0, switch_param=float(p["switch_param"]), c_dp=float(p["c_dp"]),
         c_hf=float(p["c_hf"]), c_var=float(p["c_var"]), inlet_mode=im, reserved2=0, rho_in=float(p["rho_in"]),
-        u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]),
+        u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]), collision=co, reserved3=0,
+        mrt_s=(ctypes.c_double * 5)(*[float(v) for v in p["mrt_rates"]]),
     )
 
 
@@ -178,6 +185,16 @@ def lattice(q: int):
     _check(lib.lbmo_lattice(q, e.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(wt),
                             opp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(cs2)), "lattice")
     return e.reshape(q, 3), wt, opp, cs2.value
+
+
+def mrt(params):
+    """(U[19,19], rates[19], K[19,19]) of the D3Q19 MRT collision of a configuration."""
+    cfg = _cfg(dict(params, collision="mrt"))
+    U = np.zeros(361)
+    r = np.zeros(19)
+    K = np.zeros(361)
+    _check(_load().lbmo_mrt(ctypes.byref(cfg), _dp(U), _dp(r), _dp(K)), "mrt")
+    return U.reshape(19, 19), r, K.reshape(19, 19)
 
 
 def mask(params):

@@ -11,9 +11,11 @@
 //    (Sf)_j(x+e_j) = f_j(x)                         -- Section 2.1
 //  * one step of the local scheme f^{n+1}_j(x+e_j) = W^x_j(f^n(x), w)
 //                                                   -- Section 2.1, eq. (normal:iteration)
-//  * node operators W^x: interior BGK (eq. SRT) with the exact-difference
-//    forcing of Section 3.1 carrying the Darcy/Brinkman velocity switch
-//    u_post = G(w) u_pre of Section 3.2; Zou-He inlet/outlet and bounce-back
+//  * node operators W^x: interior BGK (eq. SRT) or, in 3D, the forced
+//    multiple-relaxation-time collision (Section 3.1, the FMRT form with
+//    d'Humieres' D3Q19 moment basis) with the exact-difference forcing carrying
+//    the Darcy/Brinkman velocity switch u_post = G(w) u_pre of Section 3.2
+//    (inlet/outlet nodes collide by BGK after their Zou-He reconstruction); Zou-He inlet/outlet and bounce-back
 //    walls (Section 3, node classes); a passive scalar on the first 5/7
 //    velocities relaxed by BGK (Section 3, heat-transfer lattice)
 //  * objective F = sum over nodes of node functions (eq. objective:function),
@@ -54,6 +56,7 @@
 #include <cstdint>
 #include <cstring>
 #include <cmath>
+#include <utility>
 #include <vector>
 #include <omp.h>
 
@@ -115,6 +118,7 @@ enum { INTERIOR = 0, WALL = 1, INLET = 2, OUTLET = 3 };
 enum { G_POWER = 0, G_RAMP = 1 };
 enum { S_ADIABATIC = 0, S_DIRICHLET = 1 };
 enum { IN_VELOCITY = 0, IN_PRESSURE = 1 };
+enum { COLL_BGK = 0, COLL_MRT = 1 };
 
 }  // namespace
 
@@ -139,6 +143,9 @@ struct lbmo_cfg {
   double rho_in;         // inlet density of the pressure form
   double u_cap;          // pressure form: largest inlet velocity (0: no limit)
   double c_mix;          // weight of the mixing flux sum_outlet u_x (1 - T^2)
+  int32_t collision;     // 0 BGK, 1 MRT (D3Q19 only)
+  int32_t reserved3;
+  double mrt_s[5];       // MRT rates of the moments e, eps, q, pi, m (viscous moments relax at 1/tau)
 };
 }
 
@@ -149,7 +156,67 @@ struct Model {
   Lattice F, S;        // flow and scalar lattices (S.q == 0 when absent)
   int64_t n = 0;       // number of nodes
   int qt = 0;          // flow + scalar populations per node
+  // MRT: K = U^{-1} (I - T) U, the map of the non-equilibrium part
+  double K[19][19] = {};
 };
+
+// d'Humieres' D3Q19 moment basis (the matrix the paper cites for its 3D MRT),
+// each row a polynomial in the velocity c: density; energy 19|c|^2 - 30;
+// energy square (21|c|^4 - 53|c|^2 + 24)/2; momentum c_a and energy flux
+// (5|c|^2 - 9) c_a for a = x, y, z; stresses 3c_x^2 - |c|^2 and c_y^2 - c_z^2
+// with their fourth-order partners (3|c|^2 - 5) times each; off-diagonal
+// stresses c_x c_y, c_y c_z, c_x c_z; third-order moments (c_y^2 - c_z^2) c_x,
+// (c_z^2 - c_x^2) c_y, (c_x^2 - c_y^2) c_z.  rate[k] is the relaxation rate of
+// row k: the viscous stresses (and the conserved rows, whose non-equilibrium
+// part is zero) relax at omega = 1/tau, the others at the configured rates.
+void mrt_basis(const Lattice& L, const lbmo_cfg& c, double U[19][19], double rate[19]) {
+  for (int j = 0; j < 19; ++j) {
+    const double x = L.e[j][0], y = L.e[j][1], z = L.e[j][2];
+    const double c2 = x * x + y * y + z * z;
+    const double row[19] = {1.0,
+                            19 * c2 - 30,
+                            (21 * c2 * c2 - 53 * c2 + 24) / 2,
+                            x, (5 * c2 - 9) * x,
+                            y, (5 * c2 - 9) * y,
+                            z, (5 * c2 - 9) * z,
+                            3 * x * x - c2, (3 * c2 - 5) * (3 * x * x - c2),
+                            y * y - z * z, (3 * c2 - 5) * (y * y - z * z),
+                            x * y, y * z, x * z,
+                            (y * y - z * z) * x, (z * z - x * x) * y, (x * x - y * y) * z};
+    for (int k = 0; k < 19; ++k) U[k][j] = row[k];
+  }
+  const double om = 1.0 / c.tau;
+  const double* s = c.mrt_s;  // e, eps, q, pi, m
+  const double r[19] = {om, s[0], s[1], om, s[2], om, s[2], om, s[2], om, s[3], om, s[3], om, om, om, s[4], s[4], s[4]};
+  for (int k = 0; k < 19; ++k) rate[k] = r[k];
+}
+
+// K = U^{-1} diag(1 - rate) U, with U^{-1} from Gauss-Jordan elimination.
+void mrt_matrix(const Lattice& L, const lbmo_cfg& c, double K[19][19]) {
+  double U[19][19], rate[19], A[19][38];
+  mrt_basis(L, c, U, rate);
+  for (int i = 0; i < 19; ++i)
+    for (int j = 0; j < 38; ++j) A[i][j] = (j < 19) ? U[i][j] : (j - 19 == i ? 1.0 : 0.0);
+  for (int col = 0; col < 19; ++col) {
+    int piv = col;
+    for (int i = col + 1; i < 19; ++i)
+      if (std::fabs(A[i][col]) > std::fabs(A[piv][col])) piv = i;
+    for (int j = 0; j < 38; ++j) std::swap(A[col][j], A[piv][j]);
+    const double d = A[col][col];
+    for (int j = 0; j < 38; ++j) A[col][j] /= d;
+    for (int i = 0; i < 19; ++i)
+      if (i != col) {
+        const double m = A[i][col];
+        for (int j = 0; j < 38; ++j) A[i][j] -= m * A[col][j];
+      }
+  }
+  for (int i = 0; i < 19; ++i)
+    for (int j = 0; j < 19; ++j) {
+      double v = 0;
+      for (int k = 0; k < 19; ++k) v += A[i][19 + k] * (1.0 - rate[k]) * U[k][j];
+      K[i][j] = v;
+    }
+}
 
 bool make_model(const lbmo_cfg* c, Model* m) {
   if (!c) return false;
@@ -160,6 +227,8 @@ bool make_model(const lbmo_cfg* c, Model* m) {
   if (c->scalar_q != 0 && !((c->flow_q == 9 && c->scalar_q == 5) || (c->flow_q == 19 && c->scalar_q == 7)))
     return false;
   if (c->inlet_mode != IN_VELOCITY && c->inlet_mode != IN_PRESSURE) return false;
+  if (c->collision != COLL_BGK && c->collision != COLL_MRT) return false;
+  if (c->collision == COLL_MRT && c->flow_q != 19) return false;
   if (c->inlet_mode == IN_PRESSURE && !(c->rho_in > 0.0 && c->u_cap >= 0.0 && c->u_cap < 1.0)) return false;
   m->c = *c;
   m->F = make_lattice(c->flow_q);
@@ -167,6 +236,7 @@ bool make_model(const lbmo_cfg* c, Model* m) {
   if (c->scalar_q) m->S = make_lattice(c->scalar_q);
   m->n = (int64_t)c->nx * c->ny * c->nz;
   m->qt = c->flow_q + c->scalar_q;
+  if (c->collision == COLL_MRT) mrt_matrix(m->F, *c, m->K);
   return true;
 }
 
@@ -277,7 +347,18 @@ void node_op(const Model& M, int cls, int y, int z, const T* f, const T* g, cons
       v[a] = G * u[a];  // u_post = G(w) u_pre
     }
     // exact-difference form with T = omega I: h = E(rho,u_post) + (1-omega)(f - E(rho,u_pre))
-    for (int j = 0; j < F.q; ++j) h[j] = feq(F, j, rho, v) + (1.0 - om) * (f[j] - feq(F, j, rho, u));
+    if (c.collision == COLL_MRT) {
+      // FMRT: h = E(rho, u_post) + U^{-1}(I - T)U (f - E(rho, u_pre))
+      T d[19];
+      for (int j = 0; j < F.q; ++j) d[j] = f[j] - feq(F, j, rho, u);
+      for (int j = 0; j < F.q; ++j) {
+        T r = T(0.0);
+        for (int k = 0; k < F.q; ++k) r += M.K[j][k] * d[k];
+        h[j] = feq(F, j, rho, v) + r;
+      }
+    } else {
+      for (int j = 0; j < F.q; ++j) h[j] = feq(F, j, rho, v) + (1.0 - om) * (f[j] - feq(F, j, rho, u));
+    }
     if (S.q) {
       T s = T(0.0);
       for (int i = 0; i < S.q; ++i) s += g[i];
@@ -327,6 +408,10 @@ void node_op(const Model& M, int cls, int y, int z, const T* f, const T* g, cons
       fs[j] = f[j];
     }
   }
+  // BGK after the reconstruction, whatever the interior collision (the paper
+  // gives FMRT for interior nodes and Zou-He for the inlet/outlet; MRT there
+  // lets the third-order moments of the rebuilt state ring when their rate
+  // nears 2)
   for (int j = 0; j < F.q; ++j) h[j] = fs[j] + om * (feq(F, j, rho, u) - fs[j]);
   if (!S.q) return;
   T gs[7];
@@ -597,6 +682,24 @@ int lbmo_lattice(int q, int32_t* e, double* wt, int32_t* opp, double* cs2) {
     opp[j] = L.opp[j];
   }
   *cs2 = L.cs2;
+  return 0;
+}
+
+// The MRT moment basis U (19 x 19, row k = moment k), the rates of its rows
+// and K = U^{-1}(I - T)U for a D3Q19 configuration.
+int lbmo_mrt(const lbmo_cfg* cfg, double* U, double* rate, double* K) {
+  Model M;
+  if (!make_model(cfg, &M) || M.F.q != 19) return -1;
+  double Ub[19][19], r[19], Kb[19][19];
+  mrt_basis(M.F, M.c, Ub, r);
+  mrt_matrix(M.F, M.c, Kb);
+  for (int i = 0; i < 19; ++i) {
+    rate[i] = r[i];
+    for (int j = 0; j < 19; ++j) {
+      U[19 * i + j] = Ub[i][j];
+      K[19 * i + j] = Kb[i][j];
+    }
+  }
   return 0;
 }
 
