@@ -157,6 +157,42 @@ def mixer_leg(dev, steps=4000, os_iters=400):
             "note": "two primal states (234 MB) fit the 256 MB last-level cache; the one-shot's four do not"}
 
 
+def mrt_leg(dev, steps=200):
+    """Recorded primal and adjoint launches of the 256x128x128 D3Q19 channel with
+    the forced MRT interior collision (d'Humieres rates), FP32, all moments held."""
+    import torch
+
+    from paper_1501_04741_amd import inputs
+    from paper_1501_04741_amd.lbm import Lbm
+
+    wl = inputs.workload("d3q19_channel_256x128x128")
+    p = dict(inputs.model_params(wl), collision="mrt")
+    w = torch.from_numpy(inputs.design_for(wl)).to(dev)
+    L = Lbm(p, nsteps=steps, precision="fp32", checkpoint_interval=steps, device=dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for rep_ in range(2):  # the second pass is timed
+        L.set_design(w)
+        L.reset()
+        ev[0].record()
+        L.primal_steps(steps, record=True)
+        ev[1].record()
+        L.adjoint_steps(1)
+        ev[2].record()
+        L.adjoint_steps(steps - 1)
+        ev[3].record()
+    torch.cuda.synchronize()
+    L.close()
+    prim_us = ev[0].elapsed_time(ev[1]) * 1e3 / steps
+    adj_us = ev[2].elapsed_time(ev[3]) * 1e3 / (steps - 1)
+    pb, ab = algorithmic_bytes(p, "fp32")
+    nodes = p["nx"] * p["ny"] * p["nz"]
+    roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
+    return {"workload": "d3q19_channel_256x128x128 with MRT collision", "steps_timed": steps,
+            "primal": {"kernel": "k_primal<19,0,float,MRT>", "mlups": nodes / prim_us, "roofline": roof(pb, prim_us)},
+            "adjoint": {"kernel": "k_adjoint<19,0,float,MRT>", "mlups": nodes / adj_us, "roofline": roof(ab, adj_us)}}
+
+
 def cpu_baseline(p, w64, steps):
     import oracle
     cores = oracle.threads()
@@ -245,7 +281,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="d3q19_channel_256x128x128")
     ap.add_argument("--lbm-steps", type=int, default=None, help="override the primal horizon N")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixer", action="store_true", help="skip the mixing-duct forward/one-shot leg")
+    ap.add_argument("--no-mixer", action="store_true", help="skip the mixing-duct and MRT legs")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run one device copy of MB megabytes (counter calibration for profiles)")
@@ -410,6 +446,8 @@ def main(argv=None):
     if not args.no_mixer:
         print("[bench] mixing duct leg", file=sys.stderr, flush=True)
         rec["mixer"] = mixer_leg(dev)
+        print("[bench] MRT leg", file=sys.stderr, flush=True)
+        rec["mrt"] = mrt_leg(dev)
     if not args.no_cpu_baseline:
         print("[bench] GPU timing done; timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(p, w_np.astype(np.float64), args.cpu_steps)

@@ -5,7 +5,7 @@
  * lattice-Boltzmann topology-optimisation method:
  *   1. the fused primal collide+stream step  f^{n+1}_j(x+e_j) = W^x_j(f^n(x), w)
  *      (Section 2.1, eq. normal:iteration), with the node operators W^x of
- *      Section 3: BGK (eq. SRT) with exact-difference forcing (Section 3.1)
+ *      Section 3: BGK (eq. SRT) or forced MRT, with exact-difference forcing (Section 3.1)
  *      carrying the Brinkman velocity switch u_post = G(w) u_pre (Section 3.2),
  *      Zou-He inlet (velocity, or pressure with a velocity limit as in the
  *      channel setup of Section 4) and outlet, bounce-back walls, and an
@@ -70,6 +70,7 @@ enum { LBM_FP32 = 4, LBM_FP64 = 8 };
 enum { LBM_WALL_ADIABATIC = 0, LBM_WALL_DIRICHLET = 1 };
 enum { LBM_G_POWER = 0, LBM_G_RAMP = 1 };
 enum { LBM_INLET_VELOCITY = 0, LBM_INLET_PRESSURE = 1 };
+enum { LBM_COLL_BGK = 0, LBM_COLL_MRT = 1 };
 
 /* Model and run configuration (the paper's "Settings", Section 3.4). */
 typedef struct lbm_config {
@@ -114,6 +115,16 @@ typedef struct lbm_config {
   double u_cap;          /* pressure inlet velocity limit, 0 <= u_cap < 1;   *
                           * 0 = no limit                                     */
   double c_mix;          /* weight of the mixing flux Mix (see c_dp)         */
+  int32_t collision;     /* interior collision: LBM_COLL_BGK (eq. SRT) or     *
+                          * LBM_COLL_MRT, the forced multiple-relaxation-time *
+                          * collision of Section 3.1 with d'Humieres' D3Q19   *
+                          * moment basis (D3Q19 only); inlet/outlet nodes     *
+                          * use BGK after their Zou-He reconstruction        */
+  int32_t reserved2;     /* must be 0                                        */
+  double mrt_rates[5];   /* MRT rates in (0, 2) of the energy, energy-square, *
+                          * energy-flux, fourth-order-stress and third-order *
+                          * moments; density, momentum and the viscous       *
+                          * stresses relax at 1/tau                          */
 } lbm_config;
 
 /* Workspace size for cfg (cfg->nsteps and the checkpoint plan included).

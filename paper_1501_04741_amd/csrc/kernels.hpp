@@ -56,6 +56,7 @@ struct Params {
   Real u_cap;               // pressure inlet velocity limit (0: none)
   double rho_in;            // pressure inlet density, for the objective sums
   double c_dp, c_hf, c_var, c_mix;  // objective weights
+  Real mrt_k[19];           // MRT: (1 - rate_k) / |U row k|^2 (interior collision U^T diag(mrt_k) U)
 };
 
 template <typename P>
@@ -205,7 +206,38 @@ __device__ __forceinline__ void pull_state(const Real* __restrict__ src, const N
 // Interior: h = E(rho, G u) + (1 - omega)(f - E(rho, u))   (Section 3.1 with
 // T = omega I, Section 3.2 for u_post = G(w) u_pre); scalar BGK toward the
 // linear equilibrium at u_post.
-template <int Q, int QS, typename Real>
+// MRT relaxation map K = U^{-1} diag(1 - rate) U = U^T diag(mrt_k) U applied to
+// a population vector (D3Q19; K is symmetric because U's rows are orthogonal).
+template <typename Real>
+__device__ __forceinline__ void mrt_apply(const Params<Real>& p, const Real (&d)[19], Real (&out)[19]) {
+  Real m[19];
+#pragma unroll
+  for (int k = 0; k < 19; ++k) {
+    Real s = 0;
+#pragma unroll
+    for (int j = 0; j < 19; ++j) {
+      const int c = Mrt19::u(k, j);
+      if (c == 1) s += d[j];
+      else if (c == -1) s -= d[j];
+      else if (c != 0) s += Real(c) * d[j];
+    }
+    m[k] = s * p.mrt_k[k];
+  }
+#pragma unroll
+  for (int j = 0; j < 19; ++j) {
+    Real s = 0;
+#pragma unroll
+    for (int k = 0; k < 19; ++k) {
+      const int c = Mrt19::u(k, j);
+      if (c == 1) s += m[k];
+      else if (c == -1) s -= m[k];
+      else if (c != 0) s += Real(c) * m[k];
+    }
+    out[j] = s;
+  }
+}
+
+template <int Q, int QS, typename Real, bool MRT = false>
 __device__ __forceinline__ void collide_interior(const Params<Real>& p, Real wn, Real (&f)[Q],
                                                  Real (&g)[QS > 0 ? QS : 1]) {
   using L = Lat<Q>;
@@ -224,18 +256,38 @@ __device__ __forceinline__ void collide_interior(const Params<Real>& p, Real wn,
   Real G, dG;
   switch_fn(p, wn, G, dG);
   const Real usq = ux * ux + uy * uy + uz * uz;
-  const Real om1 = Real(1) - p.om;
   const Real G2 = G * G;
-  const Real a0 = p.om * drho;
+  if constexpr (MRT) {
+    // FMRT (Section 3.1): h = E(rho, G u) + U^{-1}(I - T)U (f - E(rho, u))
+    static_assert(Q == 19, "MRT is D3Q19 only");
+    Real d[19];
 #pragma unroll
-  for (int j = 0; j < Q; ++j) {
-    const Real eu = Real(L::ex(j)) * ux + Real(L::ey(j)) * uy + Real(L::ez(j)) * uz;
-    // P(u) = 3 e.u + 4.5 (e.u)^2 - 1.5 u^2 (c_s^2 = 1/3), P(Gu) = G P1 + G^2 P2
-    const Real P1 = Real(3) * eu;
-    const Real P2 = Real(4.5) * eu * eu - Real(1.5) * usq;
-    const Real Pu = P1 + P2;
-    const Real Pv = G * P1 + G2 * P2;
-    f[j] = om1 * f[j] + Real(L::w(j)) * (a0 + rho * (Pv - om1 * Pu));
+    for (int j = 0; j < Q; ++j) {
+      const Real eu = Real(L::ex(j)) * ux + Real(L::ey(j)) * uy + Real(L::ez(j)) * uz;
+      const Real Pu = Real(3) * eu + Real(4.5) * eu * eu - Real(1.5) * usq;
+      d[j] = f[j] - Real(L::w(j)) * (drho + rho * Pu);  // shifted f minus shifted E(rho, u)
+    }
+    Real r[19];
+    mrt_apply<Real>(p, d, r);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const Real eu = Real(L::ex(j)) * ux + Real(L::ey(j)) * uy + Real(L::ez(j)) * uz;
+      const Real Pv = G * Real(3) * eu + G2 * (Real(4.5) * eu * eu - Real(1.5) * usq);
+      f[j] = Real(L::w(j)) * (drho + rho * Pv) + r[j];
+    }
+  } else {
+    const Real om1 = Real(1) - p.om;
+    const Real a0 = p.om * drho;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const Real eu = Real(L::ex(j)) * ux + Real(L::ey(j)) * uy + Real(L::ez(j)) * uz;
+      // P(u) = 3 e.u + 4.5 (e.u)^2 - 1.5 u^2 (c_s^2 = 1/3), P(Gu) = G P1 + G^2 P2
+      const Real P1 = Real(3) * eu;
+      const Real P2 = Real(4.5) * eu * eu - Real(1.5) * usq;
+      const Real Pu = P1 + P2;
+      const Real Pv = G * P1 + G2 * P2;
+      f[j] = om1 * f[j] + Real(L::w(j)) * (a0 + rho * (Pv - om1 * Pu));
+    }
   }
   if constexpr (QS > 0) {
     Real T = 0;
@@ -467,7 +519,7 @@ __device__ __forceinline__ void node_moments(const Params<Real>& p, int cls, int
 
 // One primal node update: pull, collide by node class, store (coalesced).
 // With MOM, also records the node's pre-collision moments (see Mom).
-template <int Q, int QS, typename Real, bool NT, bool MOM>
+template <int Q, int QS, typename Real, bool NT, bool MOM, bool MRT>
 __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* __restrict__ src,
                                             Real* __restrict__ dst, const Real* __restrict__ w,
                                             Real* __restrict__ mom, int x, int y, int z) {
@@ -487,7 +539,7 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* _
     }
   }
   if (cls == INTERIOR) {
-    collide_interior<Q, QS, Real>(p, w[n], f, g);
+    collide_interior<Q, QS, Real, MRT>(p, w[n], f, g);
   } else if (cls == WALL) {
     collide_wall<Q, QS, Real>(p, f, g);
   } else if (cls == INLET) {
@@ -501,13 +553,13 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* _
   for (int i = 0; i < QS; ++i) put<NT>(dst + own_addr<QT>(b, Q + i), g[i]);
 }
 
-template <int Q, int QS, typename Real, bool NT, bool MOM>
+template <int Q, int QS, typename Real, bool NT, bool MOM, bool MRT>
 __global__ __launch_bounds__(256) void k_primal(Params<Real> p, const Real* __restrict__ src,
                                                 Real* __restrict__ dst, const Real* __restrict__ w,
                                                 Real* __restrict__ mom) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
-  primal_node<Q, QS, Real, NT, MOM>(p, src, dst, w, mom, x, blockIdx.y, blockIdx.z);
+  primal_node<Q, QS, Real, NT, MOM, MRT>(p, src, dst, w, mom, x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------------ objective
@@ -713,7 +765,7 @@ __global__ __launch_bounds__(256) void k_seed(Params<Real> p, const Real* __rest
 // (dW/d(f,g))^T (mu, nu) and gw = (dW/dw)^T (mu, nu) (zero except at interior
 // nodes).  Wall and velocity-inlet operators are affine in (f, g): their
 // products do not read m.  Hand-derived from the operators above.
-template <int Q, int QS, typename Real>
+template <int Q, int QS, typename Real, bool MRT = false>
 __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, const Real (&m)[Mom<Q, QS>::N],
                                             Real wn, const Real (&mu)[Q], const Real (&nu)[QS > 0 ? QS : 1],
                                             Real (&lf)[Q], Real (&lg)[QS > 0 ? QS : 1], Real& gw) {
@@ -821,13 +873,39 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
       }
       const Real Mu = M1x * ux + M1y * uy + M1z * uz;
       const Real Pu = Px * ux + Py * uy + Pz * uz;
-      // d/drho at fixed u of A(rho, G u) - (1-omega) A(rho, u), A = sum mu_j E_j
-      const Real dL_drho = M0 * (Real(1) - om1) + Real(3) * (G - om1) * Mu + Real(4.5) * (G2 - om1) * Pu -
-                           Real(1.5) * (G2 - om1) * M0 * usq;
-      const Real c1 = Real(3) * (G - om1), c2 = Real(9) * (G2 - om1), c3 = Real(3) * (G2 - om1) * M0;
-      Real dux = rho * (c1 * M1x + c2 * Px - c3 * ux);
-      Real duy = rho * (c1 * M1y + c2 * Py - c3 * uy);
-      Real duz = rho * (c1 * M1z + c2 * Pz - c3 * uz);
+      Real dL_drho, dux, duy, duz;
+      Real kap[Q];  // MRT: the relaxed cotangent K mu (K symmetric); BGK uses (1 - omega) mu
+      if constexpr (MRT) {
+        // h = E(rho, G u) + K (f - E(rho, u)):  lambda = K mu + (dE(rho,Gu)/df)^T mu - (dE(rho,u)/df)^T K mu
+        mrt_apply<Real>(p, mu, kap);
+        Real K0 = 0, K1x = 0, K1y = 0, K1z = 0, KPx = 0, KPy = 0, KPz = 0;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+          const Real a = kap[j] * Real(L::w(j));
+          const Real eu = Real(L::ex(j)) * ux + Real(L::ey(j)) * uy + Real(L::ez(j)) * uz;
+          const Real be = a * eu;
+          K0 += a;
+          if (L::ex(j)) { K1x += Real(L::ex(j)) * a; KPx += Real(L::ex(j)) * be; }
+          if (L::ey(j)) { K1y += Real(L::ey(j)) * a; KPy += Real(L::ey(j)) * be; }
+          if (L::ez(j)) { K1z += Real(L::ez(j)) * a; KPz += Real(L::ez(j)) * be; }
+        }
+        const Real Ku = K1x * ux + K1y * uy + K1z * uz;
+        const Real KPu = KPx * ux + KPy * uy + KPz * uz;
+        dL_drho = (M0 + Real(3) * G * Mu + Real(4.5) * G2 * Pu - Real(1.5) * G2 * M0 * usq) -
+                  (K0 + Real(3) * Ku + Real(4.5) * KPu - Real(1.5) * K0 * usq);
+        const Real g1 = Real(3) * G, g2 = Real(9) * G2, g3 = Real(3) * G2 * M0, k3 = Real(3) * K0;
+        dux = rho * ((g1 * M1x + g2 * Px - g3 * ux) - (Real(3) * K1x + Real(9) * KPx - k3 * ux));
+        duy = rho * ((g1 * M1y + g2 * Py - g3 * uy) - (Real(3) * K1y + Real(9) * KPy - k3 * uy));
+        duz = rho * ((g1 * M1z + g2 * Pz - g3 * uz) - (Real(3) * K1z + Real(9) * KPz - k3 * uz));
+      } else {
+        // d/drho at fixed u of A(rho, G u) - (1-omega) A(rho, u), A = sum mu_j E_j
+        dL_drho = M0 * (Real(1) - om1) + Real(3) * (G - om1) * Mu + Real(4.5) * (G2 - om1) * Pu -
+                  Real(1.5) * (G2 - om1) * M0 * usq;
+        const Real c1 = Real(3) * (G - om1), c2 = Real(9) * (G2 - om1), c3 = Real(3) * (G2 - om1) * M0;
+        dux = rho * (c1 * M1x + c2 * Px - c3 * ux);
+        duy = rho * (c1 * M1y + c2 * Py - c3 * uy);
+        duz = rho * (c1 * M1z + c2 * Pz - c3 * uz);
+      }
       Real dLdG = rho * (Real(3) * Mu + Real(9) * G * Pu - Real(3) * G * M0 * usq);
       if constexpr (QS > 0) {
         const Real T = m[M::T];
@@ -855,7 +933,9 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
       const Real drt = dL_drho - (dux * ux + duy * uy + duz * uz) * inv;
 #pragma unroll
       for (int k = 0; k < Q; ++k) {
-        Real v = om1 * mu[k] + drt;
+        Real v;
+        if constexpr (MRT) v = kap[k] + drt;
+        else v = om1 * mu[k] + drt;
         if (L::ex(k)) v += Real(L::ex(k)) * dmx;
         if (L::ey(k)) v += Real(L::ey(k)) * dmy;
         if (L::ez(k)) v += Real(L::ez(k)) * dmz;
@@ -911,7 +991,7 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
 // lambda^n(x) = (dW^x/df)^T(f^n(x)) mu(x),  mu_j(x) = lambda^{n+1}_j(x + e_j)
 // grad(x)    += (dW^x/dw)^T mu(x)            (interior nodes only)
 // The vector-Jacobian products below are hand-derived from the operators above.
-template <int Q, int QS, typename Real, bool NT>
+template <int Q, int QS, typename Real, bool NT, bool MRT>
 __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* __restrict__ mom,
                                              const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
                                              const Real* __restrict__ w, Real* __restrict__ grad, int x, int y,
@@ -937,7 +1017,7 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
     for (int k = 0; k < Mom<Q, QS>::N; ++k) m[k] = mom[(size_t)k * p.Np + n];
   }
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
-  adjoint_vjp<Q, QS, Real>(p, cls, m, wn, mu, nu, lf, lg, gw);
+  adjoint_vjp<Q, QS, Real, MRT>(p, cls, m, wn, mu, nu, lf, lg, gw);
   if (cls == INTERIOR) grad[n] += gw;
 #pragma unroll
   for (int j = 0; j < Q; ++j) put<NT>(lam_out + own_addr<QT>(b, j), lf[j]);
@@ -945,13 +1025,13 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
   for (int i = 0; i < QS; ++i) put<NT>(lam_out + own_addr<QT>(b, Q + i), lg[i]);
 }
 
-template <int Q, int QS, typename Real, bool NT>
+template <int Q, int QS, typename Real, bool NT, bool MRT>
 __global__ __launch_bounds__(256) void k_adjoint(Params<Real> p, const Real* __restrict__ mom,
                                                  const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
                                                  const Real* __restrict__ w, Real* __restrict__ grad) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
-  adjoint_node<Q, QS, Real, NT>(p, mom, lam_in, lam_out, w, grad, x, blockIdx.y, blockIdx.z);
+  adjoint_node<Q, QS, Real, NT, MRT>(p, mom, lam_in, lam_out, w, grad, x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------ inspection kernels
@@ -1109,7 +1189,7 @@ __global__ __launch_bounds__(256) void k_get_adjoint(Params<Real> p, const Real*
 //   w(x)           <- clip(w + zeta (g + c_pen (1 - 2w)), 0, 1) (interior nodes; eq. P)
 // with mu_j(x) = lambda^n_j(x + e_j).  Each node owns its w, so the in-place
 // update races with nothing.
-template <int Q, int QS, typename Real, bool NT>
+template <int Q, int QS, typename Real, bool NT, bool MRT>
 __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __restrict__ prim_in,
                                                  Real* __restrict__ prim_out, const Real* __restrict__ lam_in,
                                                  Real* __restrict__ lam_out, Real* __restrict__ w,
@@ -1135,7 +1215,7 @@ __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __r
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
   Real m[Mom<Q, QS>::N], lf[Q], lg[QSA], gw;
   node_moments<Q, QS, Real>(p, cls, y, z, f, g, m);
-  adjoint_vjp<Q, QS, Real>(p, cls, m, wn, mu, nu, lf, lg, gw);
+  adjoint_vjp<Q, QS, Real, MRT>(p, cls, m, wn, mu, nu, lf, lg, gw);
   if (cls == INLET || cls == OUTLET) {
     double sf[Q], sg[QSA];
     seed_values<Q, QS, Real>(p, cls, f, g, glob, sf, sg);
@@ -1145,7 +1225,7 @@ __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __r
     for (int i = 0; i < QS; ++i) lg[i] += (Real)sg[i];
   }
   if (cls == INTERIOR) {
-    collide_interior<Q, QS, Real>(p, wn, f, g);
+    collide_interior<Q, QS, Real, MRT>(p, wn, f, g);
   } else if (cls == WALL) {
     collide_wall<Q, QS, Real>(p, f, g);
   } else if (cls == INLET) {
@@ -1213,7 +1293,7 @@ __device__ __forceinline__ int batch_find(const BatchArgs<Real>& A, int blk) {
   return k;
 }
 
-template <int Q, int QS, typename Real>
+template <int Q, int QS, typename Real, bool MRT>
 __global__ __launch_bounds__(kBatchBX) void k_primal_batch(BatchArgs<Real> A) {
   const int blk = blockIdx.x;
   const int k = batch_find(A, blk);
@@ -1225,18 +1305,18 @@ __global__ __launch_bounds__(kBatchBX) void k_primal_batch(BatchArgs<Real> A) {
   const int y = row % S.p.ny, z = row / S.p.ny;
   if (S.nt) {
     if (A.m[k])
-      primal_node<Q, QS, Real, true, true>(S.p, A.a[k], A.c[k], S.w, A.m[k], x, y, z);
+      primal_node<Q, QS, Real, true, true, MRT>(S.p, A.a[k], A.c[k], S.w, A.m[k], x, y, z);
     else
-      primal_node<Q, QS, Real, true, false>(S.p, A.a[k], A.c[k], S.w, nullptr, x, y, z);
+      primal_node<Q, QS, Real, true, false, MRT>(S.p, A.a[k], A.c[k], S.w, nullptr, x, y, z);
   } else {
     if (A.m[k])
-      primal_node<Q, QS, Real, false, true>(S.p, A.a[k], A.c[k], S.w, A.m[k], x, y, z);
+      primal_node<Q, QS, Real, false, true, MRT>(S.p, A.a[k], A.c[k], S.w, A.m[k], x, y, z);
     else
-      primal_node<Q, QS, Real, false, false>(S.p, A.a[k], A.c[k], S.w, nullptr, x, y, z);
+      primal_node<Q, QS, Real, false, false, MRT>(S.p, A.a[k], A.c[k], S.w, nullptr, x, y, z);
   }
 }
 
-template <int Q, int QS, typename Real>
+template <int Q, int QS, typename Real, bool MRT>
 __global__ __launch_bounds__(kBatchBX) void k_adjoint_batch(BatchArgs<Real> A) {
   const int blk = blockIdx.x;
   const int k = batch_find(A, blk);
@@ -1247,9 +1327,9 @@ __global__ __launch_bounds__(kBatchBX) void k_adjoint_batch(BatchArgs<Real> A) {
   if (x >= S.p.nx) return;
   const int y = row % S.p.ny, z = row / S.p.ny;
   if (S.nt)
-    adjoint_node<Q, QS, Real, true>(S.p, A.a[k], A.b[k], A.c[k], S.w, S.grad, x, y, z);
+    adjoint_node<Q, QS, Real, true, MRT>(S.p, A.a[k], A.b[k], A.c[k], S.w, S.grad, x, y, z);
   else
-    adjoint_node<Q, QS, Real, false>(S.p, A.a[k], A.b[k], A.c[k], S.w, S.grad, x, y, z);
+    adjoint_node<Q, QS, Real, false, MRT>(S.p, A.a[k], A.b[k], A.c[k], S.w, S.grad, x, y, z);
 }
 
 // ------------------------------------------------------- small helpers

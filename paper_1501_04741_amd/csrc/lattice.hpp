@@ -96,6 +96,53 @@ struct SLat<7> {
   __host__ __device__ static constexpr double c2() { return 1.0 / 4.0; }
 };
 
+// Moment basis of the D3Q19 multiple-relaxation-time collision (d'Humieres et
+// al., the matrix Section 3.1 cites): row k of U evaluated on velocity j.  Rows:
+// density; energy 19|c|^2 - 30; energy square (21|c|^4 - 53|c|^2 + 24)/2;
+// momentum c_a and energy flux (5|c|^2 - 9) c_a for a = x, y, z; stresses
+// 3c_x^2 - |c|^2, c_y^2 - c_z^2 and their partners times (3|c|^2 - 5);
+// off-diagonal stresses c_x c_y, c_y c_z, c_x c_z; third-order moments
+// (c_y^2 - c_z^2) c_x, (c_z^2 - c_x^2) c_y, (c_x^2 - c_y^2) c_z.  The rows are
+// mutually orthogonal, so U^{-1} = U^T diag(1 / |row|^2).
+struct Mrt19 {
+  __host__ __device__ static constexpr int u(int k, int j) {
+    const int x = Lat<19>::ex(j), y = Lat<19>::ey(j), z = Lat<19>::ez(j);
+    const int c2 = x * x + y * y + z * z;
+    switch (k) {
+      case 0: return 1;
+      case 1: return 19 * c2 - 30;
+      case 2: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+      case 3: return x;
+      case 4: return (5 * c2 - 9) * x;
+      case 5: return y;
+      case 6: return (5 * c2 - 9) * y;
+      case 7: return z;
+      case 8: return (5 * c2 - 9) * z;
+      case 9: return 3 * x * x - c2;
+      case 10: return (3 * c2 - 5) * (3 * x * x - c2);
+      case 11: return y * y - z * z;
+      case 12: return (3 * c2 - 5) * (y * y - z * z);
+      case 13: return x * y;
+      case 14: return y * z;
+      case 15: return x * z;
+      case 16: return (y * y - z * z) * x;
+      case 17: return (z * z - x * x) * y;
+      default: return (x * x - y * y) * z;
+    }
+  }
+  __host__ __device__ static constexpr int norm2(int k) {
+    int s = 0;
+    for (int j = 0; j < 19; ++j) s += u(k, j) * u(k, j);
+    return s;
+  }
+  // rate group of row k: 0 = 1/tau (conserved and viscous rows), 1 energy,
+  // 2 energy square, 3 energy flux, 4 fourth-order stresses, 5 third-order
+  __host__ __device__ static constexpr int group(int k) {
+    constexpr int t[19] = {0, 1, 2, 0, 3, 0, 3, 0, 3, 0, 4, 0, 4, 0, 0, 0, 5, 5, 5};
+    return t[k];
+  }
+};
+
 // Velocity indices of +x and -x (paper's e_2 and e_3) in every lattice.
 constexpr int kPX = 1;
 constexpr int kMX = 2;

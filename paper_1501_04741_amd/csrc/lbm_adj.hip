@@ -145,6 +145,13 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
   if (c->switch_fn == LBM_G_POWER && !(c->switch_param >= 0.0)) return bad("POWER needs theta >= 0");
   if (c->reserved0 != 0 || c->reserved1 != 0) return bad("reserved0 and reserved1 must be 0");
   if (c->inlet != LBM_INLET_VELOCITY && c->inlet != LBM_INLET_PRESSURE) return bad("bad inlet");
+  if (c->collision != LBM_COLL_BGK && c->collision != LBM_COLL_MRT) return bad("bad collision");
+  if (c->collision == LBM_COLL_MRT) {
+    if (c->flow != LBM_D3Q19) return bad("MRT collision is D3Q19 only");
+    for (int k = 0; k < 5; ++k)
+      if (!(c->mrt_rates[k] > 0.0 && c->mrt_rates[k] < 2.0)) return bad("MRT rates must lie in (0, 2)");
+  }
+  if (c->reserved2 != 0) return bad("reserved2 must be 0");
   if (c->inlet == LBM_INLET_PRESSURE && !(c->rho_in > 0.0 && c->u_cap >= 0.0 && c->u_cap < 1.0))
     return bad("pressure inlet needs rho_in > 0 and 0 <= u_cap < 1");
   if (c->nsteps < 0 || c->checkpoint_interval < 0) return bad("nsteps and checkpoint_interval must be >= 0");
@@ -246,6 +253,12 @@ Params<Real> make_params(const lbm_config& c, int64_t N) {
   p.c_hf = c.c_hf;
   p.c_var = c.c_var;
   p.c_mix = c.c_mix;
+  // MRT row scales (1 - rate) / |row|^2; rows of group 0 relax at 1/tau
+  for (int k = 0; k < 19; ++k) {
+    const int gr = Mrt19::group(k);
+    const double rate = (gr == 0) ? 1.0 / c.tau : c.mrt_rates[gr - 1];
+    p.mrt_k[k] = (Real)((1.0 - rate) / Mrt19::norm2(k));
+  }
   return p;
 }
 
@@ -273,7 +286,7 @@ lbm_status launch_check(lbm_ctx* c, const char* what) {
 }
 
 // Typed operations on one context.
-template <int Q, int QS, typename Real>
+template <int Q, int QS, typename Real, bool MRT = false>
 struct Ops {
   using RealT = Real;
   static constexpr int kQ = Q, kQS = QS;
@@ -282,10 +295,10 @@ struct Ops {
     return (c->cfg.nx + kBatchBX - 1) / kBatchBX * c->cfg.ny * c->cfg.nz;
   }
   static void primal_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks) {
-    hipLaunchKernelGGL((k_primal_batch<Q, QS, Real>), dim3(blocks), dim3(kBatchBX), 0, st, A);
+    hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, MRT>), dim3(blocks), dim3(kBatchBX), 0, st, A);
   }
   static void adjoint_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks) {
-    hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real>), dim3(blocks), dim3(kBatchBX), 0, st, A);
+    hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, MRT>), dim3(blocks), dim3(kBatchBX), 0, st, A);
   }
 
   static bool nt(lbm_ctx* c) { return 2 * c->plan.state_bytes > kLastLevelCacheBytes; }
@@ -310,14 +323,14 @@ struct Ops {
     Real* m = (Real*)mom;
     if (nt(c)) {
       if (m)
-        hipLaunchKernelGGL((k_primal<Q, QS, Real, true, true>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+        hipLaunchKernelGGL((k_primal<Q, QS, Real, true, true, MRT>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
       else
-        hipLaunchKernelGGL((k_primal<Q, QS, Real, true, false>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+        hipLaunchKernelGGL((k_primal<Q, QS, Real, true, false, MRT>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
     } else {
       if (m)
-        hipLaunchKernelGGL((k_primal<Q, QS, Real, false, true>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+        hipLaunchKernelGGL((k_primal<Q, QS, Real, false, true, MRT>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
       else
-        hipLaunchKernelGGL((k_primal<Q, QS, Real, false, false>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+        hipLaunchKernelGGL((k_primal<Q, QS, Real, false, false, MRT>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
     }
   }
   static void objective(lbm_ctx* c, const void* src, double* out) {
@@ -335,21 +348,21 @@ struct Ops {
   static void adjoint(lbm_ctx* c, const void* mom, const void* lin, void* lout) {
     Geo g = node_geometry(c->cfg);
     if (nt(c))
-      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true, MRT>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
                          (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
     else
-      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false, MRT>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
                          (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
   }
   static void oneshot(lbm_ctx* c, const void* src, void* dst, const void* lin, void* lout, double zeta,
                       double pen) {
     Geo g = node_geometry(c->cfg);
     if (nt(c))
-      hipLaunchKernelGGL((k_oneshot<Q, QS, Real, true>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
+      hipLaunchKernelGGL((k_oneshot<Q, QS, Real, true, MRT>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
                          (Real*)dst, (const Real*)lin, (Real*)lout, (Real*)c->w, (Real*)c->grad,
                          (const double*)c->glob, (Real)zeta, (Real)pen);
     else
-      hipLaunchKernelGGL((k_oneshot<Q, QS, Real, false>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
+      hipLaunchKernelGGL((k_oneshot<Q, QS, Real, false, MRT>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
                          (Real*)dst, (const Real*)lin, (Real*)lout, (Real*)c->w, (Real*)c->grad,
                          (const double*)c->glob, (Real)zeta, (Real)pen);
   }
@@ -397,8 +410,12 @@ lbm_status dispatch(lbm_ctx* c, A&&... a) {
   const bool f32 = k.precision == LBM_FP32;
   if (k.flow == 9 && k.scalar == 0) return f32 ? F<Ops<9, 0, float>>::run(c, a...) : F<Ops<9, 0, double>>::run(c, a...);
   if (k.flow == 9 && k.scalar == 5) return f32 ? F<Ops<9, 5, float>>::run(c, a...) : F<Ops<9, 5, double>>::run(c, a...);
-  if (k.flow == 19 && k.scalar == 0)
+  const bool mrt = k.collision == LBM_COLL_MRT;
+  if (k.flow == 19 && k.scalar == 0) {
+    if (mrt) return f32 ? F<Ops<19, 0, float, true>>::run(c, a...) : F<Ops<19, 0, double, true>>::run(c, a...);
     return f32 ? F<Ops<19, 0, float>>::run(c, a...) : F<Ops<19, 0, double>>::run(c, a...);
+  }
+  if (mrt) return f32 ? F<Ops<19, 7, float, true>>::run(c, a...) : F<Ops<19, 7, double, true>>::run(c, a...);
   return f32 ? F<Ops<19, 7, float>>::run(c, a...) : F<Ops<19, 7, double>>::run(c, a...);
 }
 

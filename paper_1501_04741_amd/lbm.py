@@ -75,10 +75,14 @@ class LbmConfig(ctypes.Structure):
         ("rho_in", ctypes.c_double),
         ("u_cap", ctypes.c_double),
         ("c_mix", ctypes.c_double),
+        ("collision", ctypes.c_int32),
+        ("reserved2", ctypes.c_int32),
+        ("mrt_rates", ctypes.c_double * 5),
     ]
 
 NG = 9  # boundary sums ("globals") lbm_objective returns
 _INLET = {"velocity": 0, "pressure": 1}
+_COLL = {"bgk": 0, "mrt": 1}
 
 
 MODEL_DEFAULTS = dict(
@@ -86,6 +90,7 @@ MODEL_DEFAULTS = dict(
     scalar_wall="adiabatic", s_split_axis=0, s_wall=1.0, s_in_lo=0.0, s_in_hi=0.0,
     switch_fn="power", switch_param=3.0, c_dp=1.0, c_hf=0.0, c_var=0.0,
     inlet="velocity", rho_in=1.0, u_cap=0.0, c_mix=0.0,
+    collision="bgk", mrt_rates=(1.19, 1.4, 1.2, 1.4, 1.98),
 )
 
 
@@ -99,6 +104,7 @@ def make_config(params: dict, nsteps: int, precision: str = "fp32", checkpoint_i
     sw = _WALL[p["scalar_wall"]] if isinstance(p["scalar_wall"], str) else int(p["scalar_wall"])
     fn = _SWITCH[p["switch_fn"]] if isinstance(p["switch_fn"], str) else int(p["switch_fn"])
     im = _INLET[p["inlet"]] if isinstance(p["inlet"], str) else int(p["inlet"])
+    co = _COLL[p["collision"]] if isinstance(p["collision"], str) else int(p["collision"])
     return LbmConfig(
         struct_size=ctypes.sizeof(LbmConfig), flow=int(p["flow"]), scalar=int(p["scalar"]),
         precision=_PREC[precision], nx=int(p["nx"]), ny=int(p["ny"]), nz=int(p["nz"]),
@@ -108,7 +114,8 @@ def make_config(params: dict, nsteps: int, precision: str = "fp32", checkpoint_i
         switch_fn=fn, reserved0=0, switch_param=float(p["switch_param"]), c_dp=float(p["c_dp"]),
         c_hf=float(p["c_hf"]), c_var=float(p["c_var"]), nsteps=int(nsteps),
         checkpoint_interval=int(checkpoint_interval), hbm_budget_bytes=int(hbm_budget_bytes), inlet=im,
-        reserved1=0, rho_in=float(p["rho_in"]), u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]))
+        reserved1=0, rho_in=float(p["rho_in"]), u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]), collision=co,
+        reserved2=0, mrt_rates=(ctypes.c_double * 5)(*[float(v) for v in p["mrt_rates"]]))
 
 
 _lock = threading.Lock()

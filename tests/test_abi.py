@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_config_struct_size_matches(lib):
     cfg = lbm.make_config(dict(flow=9, nx=16, ny=8), 10)
-    assert cfg.struct_size == ctypes.sizeof(lbm.LbmConfig) == 192
+    assert cfg.struct_size == ctypes.sizeof(lbm.LbmConfig) == 240
     bad = lbm.make_config(dict(flow=9, nx=16, ny=8), 10)
     bad.struct_size = 150
     out = ctypes.c_uint64()
@@ -58,6 +58,10 @@ def test_config_struct_size_matches(lib):
     (dict(flow=9, nx=16, ny=8, inlet="pressure", rho_in=1.05, u_cap=1.0), False),
     (dict(flow=9, nx=16, ny=8, inlet="pressure", rho_in=1.05, u_cap=-0.1), False),
     (dict(flow=9, nx=16, ny=8, inlet=2), False),
+    (dict(flow=19, nx=16, ny=8, nz=6, collision="mrt"), True),
+    (dict(flow=9, nx=16, ny=8, collision="mrt"), False),                     # MRT is D3Q19 only
+    (dict(flow=19, nx=16, ny=8, nz=6, collision="mrt", mrt_rates=(1.19, 1.4, 1.2, 1.4, 2.0)), False),
+    (dict(flow=19, nx=16, ny=8, nz=6, collision=2), False),
 ])
 def test_config_validation(lib, params, ok):
     cfg = lbm.make_config(params, 10)
