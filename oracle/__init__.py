@@ -60,6 +60,7 @@ class Config(ctypes.Structure):
         ("collision", ctypes.c_int32),
         ("reserved3", ctypes.c_int32),
         ("mrt_s", ctypes.c_double * 5),
+        ("tau_s_solid", ctypes.c_double),
     ]
 
 NG = 9  # boundary sums ("globals") the objective is built from
@@ -70,7 +71,7 @@ DEFAULTS = dict(
     scalar_wall="adiabatic", s_split_axis=0, s_wall=1.0, s_in_lo=0.0, s_in_hi=0.0,
     switch_fn="power", switch_param=3.0, c_dp=1.0, c_hf=0.0, c_var=0.0,
     inlet="velocity", rho_in=1.0, u_cap=0.0, c_mix=0.0,
-    collision="bgk", mrt_rates=(1.19, 1.4, 1.2, 1.4, 1.98),
+    collision="bgk", mrt_rates=(1.19, 1.4, 1.2, 1.4, 1.98), tau_s_solid=0.0,
 )
 CONFIG_KEYS = tuple(DEFAULTS)
 
@@ -146,7 +147,7 @@ def make_config(params: dict) -> Config:
         switch_fn=fn, reserved=0, switch_param=float(p["switch_param"]), c_dp=float(p["c_dp"]),
         c_hf=float(p["c_hf"]), c_var=float(p["c_var"]), inlet_mode=im, reserved2=0, rho_in=float(p["rho_in"]),
         u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]), collision=co, reserved3=0,
-        mrt_s=(ctypes.c_double * 5)(*[float(v) for v in p["mrt_rates"]]),
+        mrt_s=(ctypes.c_double * 5)(*[float(v) for v in p["mrt_rates"]]), tau_s_solid=float(p["tau_s_solid"]),
     )
 
 

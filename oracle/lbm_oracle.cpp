@@ -15,7 +15,10 @@
 //    multiple-relaxation-time collision (Section 3.1, the FMRT form with
 //    d'Humieres' D3Q19 moment basis) with the exact-difference forcing carrying
 //    the Darcy/Brinkman velocity switch u_post = G(w) u_pre of Section 3.2
-//    (inlet/outlet nodes collide by BGK after their Zou-He reconstruction); Zou-He inlet/outlet and bounce-back
+//    (inlet/outlet nodes collide by BGK after their Zou-He reconstruction);
+//    the scalar diffusivity interpolates linearly between fluid and solid,
+//    alpha(w) = w alpha_fluid + (1-w) alpha_solid (Section 3.2), i.e.
+//    tau_s(w) = w tau_s + (1-w) tau_s_solid at interior nodes; Zou-He inlet/outlet and bounce-back
 //    walls (Section 3, node classes); a passive scalar on the first 5/7
 //    velocities relaxed by BGK (Section 3, heat-transfer lattice)
 //  * objective F = sum over nodes of node functions (eq. objective:function),
@@ -146,6 +149,7 @@ struct lbmo_cfg {
   int32_t collision;     // 0 BGK, 1 MRT (D3Q19 only)
   int32_t reserved3;
   double mrt_s[5];       // MRT rates of the moments e, eps, q, pi, m (viscous moments relax at 1/tau)
+  double tau_s_solid;    // scalar relaxation time at w = 0 (0: tau_s everywhere)
 };
 }
 
@@ -229,6 +233,7 @@ bool make_model(const lbmo_cfg* c, Model* m) {
   if (c->inlet_mode != IN_VELOCITY && c->inlet_mode != IN_PRESSURE) return false;
   if (c->collision != COLL_BGK && c->collision != COLL_MRT) return false;
   if (c->collision == COLL_MRT && c->flow_q != 19) return false;
+  if (c->tau_s_solid != 0.0 && !(c->tau_s_solid > 0.5)) return false;
   if (c->inlet_mode == IN_PRESSURE && !(c->rho_in > 0.0 && c->u_cap >= 0.0 && c->u_cap < 1.0)) return false;
   m->c = *c;
   m->F = make_lattice(c->flow_q);
@@ -362,7 +367,13 @@ void node_op(const Model& M, int cls, int y, int z, const T* f, const T* g, cons
     if (S.q) {
       T s = T(0.0);
       for (int i = 0; i < S.q; ++i) s += g[i];
-      for (int i = 0; i < S.q; ++i) gp[i] = g[i] + oms * (seq(S, i, s, v) - g[i]);
+      if (c.tau_s_solid != 0.0) {
+        // diffusivity interpolated between solid and fluid: tau_s(w) = w tau_s + (1 - w) tau_s_solid
+        const T omw = 1.0 / (w * c.tau_s + (1.0 - w) * c.tau_s_solid);
+        for (int i = 0; i < S.q; ++i) gp[i] = g[i] + omw * (seq(S, i, s, v) - g[i]);
+      } else {
+        for (int i = 0; i < S.q; ++i) gp[i] = g[i] + oms * (seq(S, i, s, v) - g[i]);
+      }
     }
     return;
   }
