@@ -70,8 +70,11 @@ def _class_counts(p):
 
 
 def moment_values(p):
-    """Values per node the recorded primal keeps for the adjoint (rho, u[, scalar])."""
-    return (3 if p["flow"] == 19 else 2) + 1 + (1 if p.get("scalar", 0) else 0)
+    """Values per node the recorded primal keeps for the adjoint: rho, u and the
+    scalar sum, or all scalar populations when the diffusivity is blended."""
+    qs = p.get("scalar", 0)
+    blended = qs and p.get("tau_s_solid", 0.0) not in (0.0, p.get("tau_s", 0.6))
+    return (3 if p["flow"] == 19 else 2) + 1 + ((qs if blended else 1) if qs else 0)
 
 
 def primal_bytes(p, precision, recorded=True):

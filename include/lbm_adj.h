@@ -125,6 +125,10 @@ typedef struct lbm_config {
                           * energy-flux, fourth-order-stress and third-order *
                           * moments; density, momentum and the viscous       *
                           * stresses relax at 1/tau                          */
+  double tau_s_solid;    /* scalar relaxation time at w = 0; the diffusivity *
+                          * blends linearly with the design field (Section   *
+                          * 3.2): tau_s(w) = w tau_s + (1-w) tau_s_solid at  *
+                          * interior nodes.  0 = tau_s everywhere            */
 } lbm_config;
 
 /* Workspace size for cfg (cfg->nsteps and the checkpoint plan included).

@@ -37,6 +37,9 @@ enum : int { INTERIOR = 0, WALL = 1, INLET = 2, OUTLET = 3 };
 enum : int { G_POWER = 0, G_RAMP = 1 };
 enum : int { S_ADIABATIC = 0, S_DIRICHLET = 1 };
 enum : int { IN_VELOCITY = 0, IN_PRESSURE = 1 };
+// Kernel variants (template mask V): forced MRT interior collision; scalar
+// diffusivity blended with the design field.
+enum : int { kVarMRT = 1, kVarVD = 2 };
 
 // Per-context parameters, passed by value to every kernel.
 template <typename Real>
@@ -57,6 +60,7 @@ struct Params {
   double rho_in;            // pressure inlet density, for the objective sums
   double c_dp, c_hf, c_var, c_mix;  // objective weights
   Real mrt_k[19];           // MRT: (1 - rate_k) / |U row k|^2 (interior collision U^T diag(mrt_k) U)
+  Real taus_f, taus_s;      // scalar relaxation time of fluid (w = 1) and solid (w = 0), blended variant
 };
 
 template <typename P>
@@ -237,11 +241,13 @@ __device__ __forceinline__ void mrt_apply(const Params<Real>& p, const Real (&d)
   }
 }
 
-template <int Q, int QS, typename Real, bool MRT = false>
+template <int Q, int QS, typename Real, int V = 0>
 __device__ __forceinline__ void collide_interior(const Params<Real>& p, Real wn, Real (&f)[Q],
                                                  Real (&g)[QS > 0 ? QS : 1]) {
   using L = Lat<Q>;
   using S = SLat<QS>;
+  constexpr bool MRT = (V & kVarMRT) != 0;
+  constexpr bool VD = (V & kVarVD) != 0;
   Real drho = 0, mx = 0, my = 0, mz = 0;
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
@@ -294,12 +300,14 @@ __device__ __forceinline__ void collide_interior(const Params<Real>& p, Real wn,
 #pragma unroll
     for (int i = 0; i < QS; ++i) T += g[i];
     const Real vx = G * ux, vy = G * uy, vz = G * uz;
-    const Real oms1 = Real(1) - p.oms;
+    // blended diffusivity: tau_s(w) = w tau_fluid + (1 - w) tau_solid (Section 3.2)
+    const Real oms = VD ? Real(1) / (wn * p.taus_f + (Real(1) - wn) * p.taus_s) : p.oms;
+    const Real oms1 = Real(1) - oms;
     const Real ic2 = Real(1.0 / S::c2());
 #pragma unroll
     for (int i = 0; i < QS; ++i) {
       const Real ev = Real(S::ex(i)) * vx + Real(S::ey(i)) * vy + Real(S::ez(i)) * vz;
-      g[i] = oms1 * g[i] + p.oms * Real(S::w(i)) * T * (Real(1) + ev * ic2);
+      g[i] = oms1 * g[i] + oms * Real(S::w(i)) * T * (Real(1) + ev * ic2);
     }
   }
 }
@@ -447,11 +455,14 @@ __device__ __forceinline__ void collide_outlet(const Params<Real>& p, Real (&f)[
 // records them (Mom::N values per node per step, plane-major) so the adjoint
 // step does not re-read the Qt populations.  The sums follow the operators'
 // order exactly.
-template <int Q, int QS>
+template <int Q, int QS, int V = 0>
 struct Mom {
   static constexpr int D = Lat<Q>::D;
-  static constexpr int N = D + 1 + (QS > 0 ? 1 : 0);  // values per node
-  static constexpr int T = D + 1;                      // index of the scalar value
+  static constexpr bool VD = (V & kVarVD) != 0;
+  // values per node: rho, u and the scalar sum T, or (blended diffusivity) the
+  // QS scalar populations themselves, whose non-equilibrium part the w-derivative needs
+  static constexpr int N = D + 1 + (QS > 0 ? (VD ? QS : 1) : 0);
+  static constexpr int T = D + 1;  // index of the (first) scalar value
 };
 
 template <typename Real>
@@ -459,11 +470,11 @@ __device__ __forceinline__ bool has_moments(const Params<Real>& p, int cls) {
   return cls == INTERIOR || cls == OUTLET || (cls == INLET && p.inlet_mode == IN_PRESSURE);
 }
 
-template <int Q, int QS, typename Real>
+template <int Q, int QS, typename Real, int V = 0>
 __device__ __forceinline__ void node_moments(const Params<Real>& p, int cls, int y, int z, const Real (&f)[Q],
-                                             const Real (&g)[QS > 0 ? QS : 1], Real (&m)[Mom<Q, QS>::N]) {
+                                             const Real (&g)[QS > 0 ? QS : 1], Real (&m)[Mom<Q, QS, V>::N]) {
   using L = Lat<Q>;
-  using M = Mom<Q, QS>;
+  using M = Mom<Q, QS, V>;
 #pragma unroll
   for (int k = 0; k < M::N; ++k) m[k] = Real(0);
   if (cls == INTERIOR) {
@@ -482,10 +493,15 @@ __device__ __forceinline__ void node_moments(const Params<Real>& p, int cls, int
     m[2] = my * inv;
     if constexpr (M::D == 3) m[3] = mz * inv;
     if constexpr (QS > 0) {
-      Real T = 0;
+      if constexpr (M::VD) {
 #pragma unroll
-      for (int i = 0; i < QS; ++i) T += g[i];
-      m[M::T] = T;
+        for (int i = 0; i < QS; ++i) m[M::T + i] = g[i];
+      } else {
+        Real T = 0;
+#pragma unroll
+        for (int i = 0; i < QS; ++i) T += g[i];
+        m[M::T] = T;
+      }
     }
   } else if (cls == OUTLET) {
     Real s0 = 0, sp = 0;
@@ -519,7 +535,7 @@ __device__ __forceinline__ void node_moments(const Params<Real>& p, int cls, int
 
 // One primal node update: pull, collide by node class, store (coalesced).
 // With MOM, also records the node's pre-collision moments (see Mom).
-template <int Q, int QS, typename Real, bool NT, bool MOM, bool MRT>
+template <int Q, int QS, typename Real, bool NT, bool MOM, int V>
 __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* __restrict__ src,
                                             Real* __restrict__ dst, const Real* __restrict__ w,
                                             Real* __restrict__ mom, int x, int y, int z) {
@@ -532,14 +548,14 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* _
   const int cls = node_class(p, x, y, z, is3d);
   if constexpr (MOM) {
     if (has_moments(p, cls)) {  // the only classes whose transposes read them
-      Real m[Mom<Q, QS>::N];
-      node_moments<Q, QS, Real>(p, cls, y, z, f, g, m);
+      Real m[Mom<Q, QS, V>::N];
+      node_moments<Q, QS, Real, V>(p, cls, y, z, f, g, m);
 #pragma unroll
-      for (int k = 0; k < Mom<Q, QS>::N; ++k) put<NT>(mom + (size_t)k * p.Np + n, m[k]);
+      for (int k = 0; k < Mom<Q, QS, V>::N; ++k) put<NT>(mom + (size_t)k * p.Np + n, m[k]);
     }
   }
   if (cls == INTERIOR) {
-    collide_interior<Q, QS, Real, MRT>(p, w[n], f, g);
+    collide_interior<Q, QS, Real, V>(p, w[n], f, g);
   } else if (cls == WALL) {
     collide_wall<Q, QS, Real>(p, f, g);
   } else if (cls == INLET) {
@@ -553,13 +569,13 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* _
   for (int i = 0; i < QS; ++i) put<NT>(dst + own_addr<QT>(b, Q + i), g[i]);
 }
 
-template <int Q, int QS, typename Real, bool NT, bool MOM, bool MRT>
+template <int Q, int QS, typename Real, bool NT, bool MOM, int V>
 __global__ __launch_bounds__(256) void k_primal(Params<Real> p, const Real* __restrict__ src,
                                                 Real* __restrict__ dst, const Real* __restrict__ w,
                                                 Real* __restrict__ mom) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
-  primal_node<Q, QS, Real, NT, MOM, MRT>(p, src, dst, w, mom, x, blockIdx.y, blockIdx.z);
+  primal_node<Q, QS, Real, NT, MOM, V>(p, src, dst, w, mom, x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------------ objective
@@ -765,13 +781,15 @@ __global__ __launch_bounds__(256) void k_seed(Params<Real> p, const Real* __rest
 // (dW/d(f,g))^T (mu, nu) and gw = (dW/dw)^T (mu, nu) (zero except at interior
 // nodes).  Wall and velocity-inlet operators are affine in (f, g): their
 // products do not read m.  Hand-derived from the operators above.
-template <int Q, int QS, typename Real, bool MRT = false>
-__device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, const Real (&m)[Mom<Q, QS>::N],
+template <int Q, int QS, typename Real, int V = 0>
+__device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, const Real (&m)[Mom<Q, QS, V>::N],
                                             Real wn, const Real (&mu)[Q], const Real (&nu)[QS > 0 ? QS : 1],
                                             Real (&lf)[Q], Real (&lg)[QS > 0 ? QS : 1], Real& gw) {
   using L = Lat<Q>;
   using S = SLat<QS>;
-  using M = Mom<Q, QS>;
+  using M = Mom<Q, QS, V>;
+  constexpr bool MRT = (V & kVarMRT) != 0;
+  constexpr bool VD = (V & kVarVD) != 0;
   gw = Real(0);
   const Real om1 = Real(1) - p.om;
   const Real oms1 = Real(1) - p.oms;
@@ -907,8 +925,16 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
         duz = rho * (c1 * M1z + c2 * Pz - c3 * uz);
       }
       Real dLdG = rho * (Real(3) * Mu + Real(9) * G * Pu - Real(3) * G * M0 * usq);
+      Real gws = 0;  // blended diffusivity: d omega_s / dw times the scalar's non-equilibrium product
       if constexpr (QS > 0) {
-        const Real T = m[M::T];
+        Real T;
+        if constexpr (VD) {
+          T = 0;
+#pragma unroll
+          for (int i = 0; i < QS; ++i) T += m[M::T + i];
+        } else {
+          T = m[M::T];
+        }
         Real N0 = 0, N1x = 0, N1y = 0, N1z = 0;
 #pragma unroll
         for (int i = 0; i < QS; ++i) {
@@ -920,14 +946,26 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
         }
         const Real ic2 = Real(1.0 / S::c2());
         const Real N1u = N1x * ux + N1y * uy + N1z * uz;
-        const Real k = p.oms * T * G * ic2;
+        Real oms = p.oms;
+        if constexpr (VD) {
+          // g' = g + omega(w) (E^s - g), omega(w) = 1 / (w tau_f + (1 - w) tau_s):
+          // the w-derivative adds omega'(w) sum_i nu_i (E^s_i - g_i)
+          const Real tw = wn * p.taus_f + (Real(1) - wn) * p.taus_s;
+          oms = Real(1) / tw;
+          Real nug = 0;
+#pragma unroll
+          for (int i = 0; i < QS; ++i) nug += nu[i] * m[M::T + i];
+          gws = -(p.taus_f - p.taus_s) * oms * oms * (T * (N0 + G * N1u * ic2) - nug);
+        }
+        const Real k = oms * T * G * ic2;
         dux += k * N1x;
         duy += k * N1y;
         duz += k * N1z;
-        dLdG += p.oms * T * N1u * ic2;
-        const Real dT = p.oms * (N0 + G * N1u * ic2);
+        dLdG += oms * T * N1u * ic2;
+        const Real dT = oms * (N0 + G * N1u * ic2);
+        const Real oms1w = Real(1) - oms;
 #pragma unroll
-        for (int i = 0; i < QS; ++i) lg[i] = oms1 * nu[i] + dT;
+        for (int i = 0; i < QS; ++i) lg[i] = oms1w * nu[i] + dT;
       }
       const Real dmx = dux * inv, dmy = duy * inv, dmz = duz * inv;
       const Real drt = dL_drho - (dux * ux + duy * uy + duz * uz) * inv;
@@ -941,7 +979,7 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
         if (L::ez(k)) v += Real(L::ez(k)) * dmz;
         lf[k] = v;
       }
-      gw = dG * dLdG;
+      gw = dG * dLdG + gws;
     } else {  // OUTLET
       const Real ro = p.rho_out;
       const Real ux = m[1];
@@ -991,7 +1029,7 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
 // lambda^n(x) = (dW^x/df)^T(f^n(x)) mu(x),  mu_j(x) = lambda^{n+1}_j(x + e_j)
 // grad(x)    += (dW^x/dw)^T mu(x)            (interior nodes only)
 // The vector-Jacobian products below are hand-derived from the operators above.
-template <int Q, int QS, typename Real, bool NT, bool MRT>
+template <int Q, int QS, typename Real, bool NT, int V>
 __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* __restrict__ mom,
                                              const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
                                              const Real* __restrict__ w, Real* __restrict__ grad, int x, int y,
@@ -1009,15 +1047,15 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
 #pragma unroll
   for (int i = 0; i < QS; ++i) nu[i] = lam_in[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
   const int cls = node_class(p, x, y, z, is3d);
-  Real m[Mom<Q, QS>::N], lf[Q], lg[QSA], gw;
+  Real m[Mom<Q, QS, V>::N], lf[Q], lg[QSA], gw;
 #pragma unroll
-  for (int k = 0; k < Mom<Q, QS>::N; ++k) m[k] = Real(0);
+  for (int k = 0; k < Mom<Q, QS, V>::N; ++k) m[k] = Real(0);
   if (has_moments(p, cls)) {
 #pragma unroll
-    for (int k = 0; k < Mom<Q, QS>::N; ++k) m[k] = mom[(size_t)k * p.Np + n];
+    for (int k = 0; k < Mom<Q, QS, V>::N; ++k) m[k] = mom[(size_t)k * p.Np + n];
   }
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
-  adjoint_vjp<Q, QS, Real, MRT>(p, cls, m, wn, mu, nu, lf, lg, gw);
+  adjoint_vjp<Q, QS, Real, V>(p, cls, m, wn, mu, nu, lf, lg, gw);
   if (cls == INTERIOR) grad[n] += gw;
 #pragma unroll
   for (int j = 0; j < Q; ++j) put<NT>(lam_out + own_addr<QT>(b, j), lf[j]);
@@ -1025,13 +1063,13 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
   for (int i = 0; i < QS; ++i) put<NT>(lam_out + own_addr<QT>(b, Q + i), lg[i]);
 }
 
-template <int Q, int QS, typename Real, bool NT, bool MRT>
+template <int Q, int QS, typename Real, bool NT, int V>
 __global__ __launch_bounds__(256) void k_adjoint(Params<Real> p, const Real* __restrict__ mom,
                                                  const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
                                                  const Real* __restrict__ w, Real* __restrict__ grad) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
-  adjoint_node<Q, QS, Real, NT, MRT>(p, mom, lam_in, lam_out, w, grad, x, blockIdx.y, blockIdx.z);
+  adjoint_node<Q, QS, Real, NT, V>(p, mom, lam_in, lam_out, w, grad, x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------ inspection kernels
@@ -1189,7 +1227,7 @@ __global__ __launch_bounds__(256) void k_get_adjoint(Params<Real> p, const Real*
 //   w(x)           <- clip(w + zeta (g + c_pen (1 - 2w)), 0, 1) (interior nodes; eq. P)
 // with mu_j(x) = lambda^n_j(x + e_j).  Each node owns its w, so the in-place
 // update races with nothing.
-template <int Q, int QS, typename Real, bool NT, bool MRT>
+template <int Q, int QS, typename Real, bool NT, int V>
 __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __restrict__ prim_in,
                                                  Real* __restrict__ prim_out, const Real* __restrict__ lam_in,
                                                  Real* __restrict__ lam_out, Real* __restrict__ w,
@@ -1213,9 +1251,9 @@ __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __r
 #pragma unroll
   for (int i = 0; i < QS; ++i) nu[i] = lam_in[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
-  Real m[Mom<Q, QS>::N], lf[Q], lg[QSA], gw;
-  node_moments<Q, QS, Real>(p, cls, y, z, f, g, m);
-  adjoint_vjp<Q, QS, Real, MRT>(p, cls, m, wn, mu, nu, lf, lg, gw);
+  Real m[Mom<Q, QS, V>::N], lf[Q], lg[QSA], gw;
+  node_moments<Q, QS, Real, V>(p, cls, y, z, f, g, m);
+  adjoint_vjp<Q, QS, Real, V>(p, cls, m, wn, mu, nu, lf, lg, gw);
   if (cls == INLET || cls == OUTLET) {
     double sf[Q], sg[QSA];
     seed_values<Q, QS, Real>(p, cls, f, g, glob, sf, sg);
@@ -1225,7 +1263,7 @@ __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __r
     for (int i = 0; i < QS; ++i) lg[i] += (Real)sg[i];
   }
   if (cls == INTERIOR) {
-    collide_interior<Q, QS, Real, MRT>(p, wn, f, g);
+    collide_interior<Q, QS, Real, V>(p, wn, f, g);
   } else if (cls == WALL) {
     collide_wall<Q, QS, Real>(p, f, g);
   } else if (cls == INLET) {
@@ -1293,7 +1331,7 @@ __device__ __forceinline__ int batch_find(const BatchArgs<Real>& A, int blk) {
   return k;
 }
 
-template <int Q, int QS, typename Real, bool MRT>
+template <int Q, int QS, typename Real, int V>
 __global__ __launch_bounds__(kBatchBX) void k_primal_batch(BatchArgs<Real> A) {
   const int blk = blockIdx.x;
   const int k = batch_find(A, blk);
@@ -1305,18 +1343,18 @@ __global__ __launch_bounds__(kBatchBX) void k_primal_batch(BatchArgs<Real> A) {
   const int y = row % S.p.ny, z = row / S.p.ny;
   if (S.nt) {
     if (A.m[k])
-      primal_node<Q, QS, Real, true, true, MRT>(S.p, A.a[k], A.c[k], S.w, A.m[k], x, y, z);
+      primal_node<Q, QS, Real, true, true, V>(S.p, A.a[k], A.c[k], S.w, A.m[k], x, y, z);
     else
-      primal_node<Q, QS, Real, true, false, MRT>(S.p, A.a[k], A.c[k], S.w, nullptr, x, y, z);
+      primal_node<Q, QS, Real, true, false, V>(S.p, A.a[k], A.c[k], S.w, nullptr, x, y, z);
   } else {
     if (A.m[k])
-      primal_node<Q, QS, Real, false, true, MRT>(S.p, A.a[k], A.c[k], S.w, A.m[k], x, y, z);
+      primal_node<Q, QS, Real, false, true, V>(S.p, A.a[k], A.c[k], S.w, A.m[k], x, y, z);
     else
-      primal_node<Q, QS, Real, false, false, MRT>(S.p, A.a[k], A.c[k], S.w, nullptr, x, y, z);
+      primal_node<Q, QS, Real, false, false, V>(S.p, A.a[k], A.c[k], S.w, nullptr, x, y, z);
   }
 }
 
-template <int Q, int QS, typename Real, bool MRT>
+template <int Q, int QS, typename Real, int V>
 __global__ __launch_bounds__(kBatchBX) void k_adjoint_batch(BatchArgs<Real> A) {
   const int blk = blockIdx.x;
   const int k = batch_find(A, blk);
@@ -1327,9 +1365,9 @@ __global__ __launch_bounds__(kBatchBX) void k_adjoint_batch(BatchArgs<Real> A) {
   if (x >= S.p.nx) return;
   const int y = row % S.p.ny, z = row / S.p.ny;
   if (S.nt)
-    adjoint_node<Q, QS, Real, true, MRT>(S.p, A.a[k], A.b[k], A.c[k], S.w, S.grad, x, y, z);
+    adjoint_node<Q, QS, Real, true, V>(S.p, A.a[k], A.b[k], A.c[k], S.w, S.grad, x, y, z);
   else
-    adjoint_node<Q, QS, Real, false, MRT>(S.p, A.a[k], A.b[k], A.c[k], S.w, S.grad, x, y, z);
+    adjoint_node<Q, QS, Real, false, V>(S.p, A.a[k], A.b[k], A.c[k], S.w, S.grad, x, y, z);
 }
 
 // ------------------------------------------------------- small helpers

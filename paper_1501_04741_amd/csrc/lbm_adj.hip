@@ -152,6 +152,7 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
       if (!(c->mrt_rates[k] > 0.0 && c->mrt_rates[k] < 2.0)) return bad("MRT rates must lie in (0, 2)");
   }
   if (c->reserved2 != 0) return bad("reserved2 must be 0");
+  if (c->tau_s_solid != 0.0 && !(c->tau_s_solid > 0.5)) return bad("tau_s_solid must be 0 or exceed 1/2");
   if (c->inlet == LBM_INLET_PRESSURE && !(c->rho_in > 0.0 && c->u_cap >= 0.0 && c->u_cap < 1.0))
     return bad("pressure inlet needs rho_in > 0 and 0 <= u_cap < 1");
   if (c->nsteps < 0 || c->checkpoint_interval < 0) return bad("nsteps and checkpoint_interval must be >= 0");
@@ -168,8 +169,13 @@ uint64_t plan_total(const Plan& p, int64_t C, int64_t S) {
 }
 
 // Values per node in one moment set (must equal Mom<Q,QS>::N of the kernels).
+// Blended (design-dependent) scalar diffusivity in use.
+bool blended_diffusivity(const lbm_config* c) {
+  return c->scalar != 0 && c->tau_s_solid != 0.0 && c->tau_s_solid != c->tau_s;
+}
+
 int mom_values(const lbm_config* c) {
-  return (c->flow == LBM_D3Q19 ? 3 : 2) + 1 + (c->scalar ? 1 : 0);
+  return (c->flow == LBM_D3Q19 ? 3 : 2) + 1 + (c->scalar ? (blended_diffusivity(c) ? c->scalar : 1) : 0);
 }
 
 lbm_status make_plan(const lbm_config* c, Plan* p, std::string* why) {
@@ -253,6 +259,8 @@ Params<Real> make_params(const lbm_config& c, int64_t N) {
   p.c_hf = c.c_hf;
   p.c_var = c.c_var;
   p.c_mix = c.c_mix;
+  p.taus_f = (Real)c.tau_s;
+  p.taus_s = (Real)(c.tau_s_solid != 0.0 ? c.tau_s_solid : c.tau_s);
   // MRT row scales (1 - rate) / |row|^2; rows of group 0 relax at 1/tau
   for (int k = 0; k < 19; ++k) {
     const int gr = Mrt19::group(k);
@@ -286,7 +294,7 @@ lbm_status launch_check(lbm_ctx* c, const char* what) {
 }
 
 // Typed operations on one context.
-template <int Q, int QS, typename Real, bool MRT = false>
+template <int Q, int QS, typename Real, int V = 0>
 struct Ops {
   using RealT = Real;
   static constexpr int kQ = Q, kQS = QS;
@@ -295,10 +303,10 @@ struct Ops {
     return (c->cfg.nx + kBatchBX - 1) / kBatchBX * c->cfg.ny * c->cfg.nz;
   }
   static void primal_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks) {
-    hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, MRT>), dim3(blocks), dim3(kBatchBX), 0, st, A);
+    hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V>), dim3(blocks), dim3(kBatchBX), 0, st, A);
   }
   static void adjoint_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks) {
-    hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, MRT>), dim3(blocks), dim3(kBatchBX), 0, st, A);
+    hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V>), dim3(blocks), dim3(kBatchBX), 0, st, A);
   }
 
   static bool nt(lbm_ctx* c) { return 2 * c->plan.state_bytes > kLastLevelCacheBytes; }
@@ -313,7 +321,8 @@ struct Ops {
     hipLaunchKernelGGL((k_write_desc<Real>), dim3(1), dim3(64), 0, c->stream, h, (BatchStatic<Real>*)c->desc);
     return launch_check(c, "descriptor upload");
   }
-  static_assert(Mom<Q, QS>::N == (Q == 19 ? 3 : 2) + 1 + (QS > 0 ? 1 : 0), "moment count mismatch");
+  static_assert(Mom<Q, QS, V>::N == (Q == 19 ? 3 : 2) + 1 + (QS > 0 ? ((V & kVarVD) ? QS : 1) : 0),
+                "moment count mismatch");
   // One primal step; records the moments of the pulled state when mom != null.
   static void primal(lbm_ctx* c, const void* src, void* dst, void* mom = nullptr) {
     Geo g = node_geometry(c->cfg);
@@ -323,14 +332,14 @@ struct Ops {
     Real* m = (Real*)mom;
     if (nt(c)) {
       if (m)
-        hipLaunchKernelGGL((k_primal<Q, QS, Real, true, true, MRT>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+        hipLaunchKernelGGL((k_primal<Q, QS, Real, true, true, V>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
       else
-        hipLaunchKernelGGL((k_primal<Q, QS, Real, true, false, MRT>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+        hipLaunchKernelGGL((k_primal<Q, QS, Real, true, false, V>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
     } else {
       if (m)
-        hipLaunchKernelGGL((k_primal<Q, QS, Real, false, true, MRT>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+        hipLaunchKernelGGL((k_primal<Q, QS, Real, false, true, V>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
       else
-        hipLaunchKernelGGL((k_primal<Q, QS, Real, false, false, MRT>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+        hipLaunchKernelGGL((k_primal<Q, QS, Real, false, false, V>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
     }
   }
   static void objective(lbm_ctx* c, const void* src, double* out) {
@@ -348,21 +357,21 @@ struct Ops {
   static void adjoint(lbm_ctx* c, const void* mom, const void* lin, void* lout) {
     Geo g = node_geometry(c->cfg);
     if (nt(c))
-      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true, MRT>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true, V>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
                          (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
     else
-      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false, MRT>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false, V>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
                          (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
   }
   static void oneshot(lbm_ctx* c, const void* src, void* dst, const void* lin, void* lout, double zeta,
                       double pen) {
     Geo g = node_geometry(c->cfg);
     if (nt(c))
-      hipLaunchKernelGGL((k_oneshot<Q, QS, Real, true, MRT>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
+      hipLaunchKernelGGL((k_oneshot<Q, QS, Real, true, V>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
                          (Real*)dst, (const Real*)lin, (Real*)lout, (Real*)c->w, (Real*)c->grad,
                          (const double*)c->glob, (Real)zeta, (Real)pen);
     else
-      hipLaunchKernelGGL((k_oneshot<Q, QS, Real, false, MRT>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
+      hipLaunchKernelGGL((k_oneshot<Q, QS, Real, false, V>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
                          (Real*)dst, (const Real*)lin, (Real*)lout, (Real*)c->w, (Real*)c->grad,
                          (const double*)c->glob, (Real)zeta, (Real)pen);
   }
@@ -408,14 +417,24 @@ template <template <class> class F, class... A>
 lbm_status dispatch(lbm_ctx* c, A&&... a) {
   const lbm_config& k = c->cfg;
   const bool f32 = k.precision == LBM_FP32;
-  if (k.flow == 9 && k.scalar == 0) return f32 ? F<Ops<9, 0, float>>::run(c, a...) : F<Ops<9, 0, double>>::run(c, a...);
-  if (k.flow == 9 && k.scalar == 5) return f32 ? F<Ops<9, 5, float>>::run(c, a...) : F<Ops<9, 5, double>>::run(c, a...);
   const bool mrt = k.collision == LBM_COLL_MRT;
+  const bool vd = blended_diffusivity(&k);
+  if (k.flow == 9 && k.scalar == 0) return f32 ? F<Ops<9, 0, float>>::run(c, a...) : F<Ops<9, 0, double>>::run(c, a...);
+  if (k.flow == 9 && k.scalar == 5) {
+    if (vd) return f32 ? F<Ops<9, 5, float, kVarVD>>::run(c, a...) : F<Ops<9, 5, double, kVarVD>>::run(c, a...);
+    return f32 ? F<Ops<9, 5, float>>::run(c, a...) : F<Ops<9, 5, double>>::run(c, a...);
+  }
   if (k.flow == 19 && k.scalar == 0) {
-    if (mrt) return f32 ? F<Ops<19, 0, float, true>>::run(c, a...) : F<Ops<19, 0, double, true>>::run(c, a...);
+    if (mrt)
+      return f32 ? F<Ops<19, 0, float, kVarMRT>>::run(c, a...) : F<Ops<19, 0, double, kVarMRT>>::run(c, a...);
     return f32 ? F<Ops<19, 0, float>>::run(c, a...) : F<Ops<19, 0, double>>::run(c, a...);
   }
-  if (mrt) return f32 ? F<Ops<19, 7, float, true>>::run(c, a...) : F<Ops<19, 7, double, true>>::run(c, a...);
+  if (mrt && vd) {
+    constexpr int V = kVarMRT | kVarVD;
+    return f32 ? F<Ops<19, 7, float, V>>::run(c, a...) : F<Ops<19, 7, double, V>>::run(c, a...);
+  }
+  if (mrt) return f32 ? F<Ops<19, 7, float, kVarMRT>>::run(c, a...) : F<Ops<19, 7, double, kVarMRT>>::run(c, a...);
+  if (vd) return f32 ? F<Ops<19, 7, float, kVarVD>>::run(c, a...) : F<Ops<19, 7, double, kVarVD>>::run(c, a...);
   return f32 ? F<Ops<19, 7, float>>::run(c, a...) : F<Ops<19, 7, double>>::run(c, a...);
 }
 

@@ -78,6 +78,7 @@ class LbmConfig(ctypes.Structure):
         ("collision", ctypes.c_int32),
         ("reserved2", ctypes.c_int32),
         ("mrt_rates", ctypes.c_double * 5),
+        ("tau_s_solid", ctypes.c_double),
     ]
 
 NG = 9  # boundary sums ("globals") lbm_objective returns
@@ -90,7 +91,7 @@ MODEL_DEFAULTS = dict(
     scalar_wall="adiabatic", s_split_axis=0, s_wall=1.0, s_in_lo=0.0, s_in_hi=0.0,
     switch_fn="power", switch_param=3.0, c_dp=1.0, c_hf=0.0, c_var=0.0,
     inlet="velocity", rho_in=1.0, u_cap=0.0, c_mix=0.0,
-    collision="bgk", mrt_rates=(1.19, 1.4, 1.2, 1.4, 1.98),
+    collision="bgk", mrt_rates=(1.19, 1.4, 1.2, 1.4, 1.98), tau_s_solid=0.0,
 )
 
 
@@ -115,7 +116,8 @@ def make_config(params: dict, nsteps: int, precision: str = "fp32", checkpoint_i
         c_hf=float(p["c_hf"]), c_var=float(p["c_var"]), nsteps=int(nsteps),
         checkpoint_interval=int(checkpoint_interval), hbm_budget_bytes=int(hbm_budget_bytes), inlet=im,
         reserved1=0, rho_in=float(p["rho_in"]), u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]), collision=co,
-        reserved2=0, mrt_rates=(ctypes.c_double * 5)(*[float(v) for v in p["mrt_rates"]]))
+        reserved2=0, mrt_rates=(ctypes.c_double * 5)(*[float(v) for v in p["mrt_rates"]]),
+        tau_s_solid=float(p["tau_s_solid"]))
 
 
 _lock = threading.Lock()

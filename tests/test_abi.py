@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_config_struct_size_matches(lib):
     cfg = lbm.make_config(dict(flow=9, nx=16, ny=8), 10)
-    assert cfg.struct_size == ctypes.sizeof(lbm.LbmConfig) == 240
+    assert cfg.struct_size == ctypes.sizeof(lbm.LbmConfig) == 248
     bad = lbm.make_config(dict(flow=9, nx=16, ny=8), 10)
     bad.struct_size = 150
     out = ctypes.c_uint64()
@@ -62,6 +62,8 @@ def test_config_struct_size_matches(lib):
     (dict(flow=9, nx=16, ny=8, collision="mrt"), False),                     # MRT is D3Q19 only
     (dict(flow=19, nx=16, ny=8, nz=6, collision="mrt", mrt_rates=(1.19, 1.4, 1.2, 1.4, 2.0)), False),
     (dict(flow=19, nx=16, ny=8, nz=6, collision=2), False),
+    (dict(flow=9, scalar=5, nx=16, ny=8, tau_s_solid=4.5), True),
+    (dict(flow=9, scalar=5, nx=16, ny=8, tau_s_solid=0.4), False),
 ])
 def test_config_validation(lib, params, ok):
     cfg = lbm.make_config(params, 10)
