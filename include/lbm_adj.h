@@ -129,6 +129,14 @@ typedef struct lbm_config {
                           * blends linearly with the design field (Section   *
                           * 3.2): tau_s(w) = w tau_s + (1-w) tau_s_solid at  *
                           * interior nodes.  0 = tau_s everywhere            */
+  int32_t inplace;       /* 1: one buffer per state, streamed in place       *
+                          * (alternating even/odd access patterns); halves  *
+                          * the state memory of unrecorded runs and of the  *
+                          * one-shot iteration.  Requires nsteps = 0: such  *
+                          * a context neither records nor runs the unsteady *
+                          * adjoint nor joins batched launches (LBM_ESTATE / *
+                          * LBM_EINVAL)                                      */
+  int32_t reserved3;     /* must be 0                                        */
 } lbm_config;
 
 /* Workspace size for cfg (cfg->nsteps and the checkpoint plan included).

@@ -203,6 +203,121 @@ __device__ __forceinline__ void pull_state(const Real* __restrict__ src, const N
   for (int i = 0; i < QS; ++i) g[i] = src[pull_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
 }
 
+// In-place streaming (one buffer per state, the "AA" access pattern).  The
+// ping-pong form (ACC_PP) keeps post-collision states and pulls.  In place, a
+// buffer alternates between two phases: after an even number of steps slot j
+// of node x holds the pre-collision f_j(x) (phase E); an even step reads its
+// own slots and writes h_j(x) into its own slot opp(j) (phase O); an odd step
+// reads f_j(x) = h_j(x - e_j) from slot opp(j) of x - e_j and writes h_j(x)
+// into slot j of x + e_j (phase E again).  Each slot is read and written by
+// one node only, so no step races.  The adjoint cotangent streams the other
+// way (mu_j(x) = lambda_j(x + e_j)) and mirrors the pattern with e -> -e.
+enum : int { ACC_PP = 0, ACC_EVEN = 1, ACC_ODD = 2 };
+
+template <int Q, int QS, typename Real, int ACC>
+__device__ __forceinline__ void load_state(const Real* a, const Nbr& b, Real (&f)[Q], Real (&g)[QS > 0 ? QS : 1]) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  constexpr int QT = Q + QS;
+  if constexpr (ACC == ACC_PP) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) f[j] = a[pull_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))];
+#pragma unroll
+    for (int i = 0; i < QS; ++i) g[i] = a[pull_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
+  } else if constexpr (ACC == ACC_EVEN) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) f[j] = a[own_addr<QT>(b, j)];
+#pragma unroll
+    for (int i = 0; i < QS; ++i) g[i] = a[own_addr<QT>(b, Q + i)];
+  } else {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) f[j] = a[pull_addr<QT>(b, L::opp(j), L::ex(j), L::ey(j), L::ez(j))];
+#pragma unroll
+    for (int i = 0; i < QS; ++i) g[i] = a[pull_addr<QT>(b, Q + S::opp(i), S::ex(i), S::ey(i), S::ez(i))];
+  }
+}
+
+template <int Q, int QS, typename Real, bool NT, int ACC>
+__device__ __forceinline__ void store_state(Real* a, const Nbr& b, const Real (&f)[Q], const Real (&g)[QS > 0 ? QS : 1]) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  constexpr int QT = Q + QS;
+  if constexpr (ACC == ACC_PP) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) put<NT>(a + own_addr<QT>(b, j), f[j]);
+#pragma unroll
+    for (int i = 0; i < QS; ++i) put<NT>(a + own_addr<QT>(b, Q + i), g[i]);
+  } else if constexpr (ACC == ACC_EVEN) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) put<NT>(a + own_addr<QT>(b, L::opp(j)), f[j]);
+#pragma unroll
+    for (int i = 0; i < QS; ++i) put<NT>(a + own_addr<QT>(b, Q + S::opp(i)), g[i]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) put<NT>(a + push_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j)), f[j]);
+#pragma unroll
+    for (int i = 0; i < QS; ++i) put<NT>(a + push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i)), g[i]);
+  }
+}
+
+// Cotangent of the post-collision populations, mu_j(x) = lambda_j(x + e_j),
+// and the store of the new lambda(x), for the three access patterns.
+template <int Q, int QS, typename Real, int ACC>
+__device__ __forceinline__ void load_cot(const Real* a, const Nbr& b, Real (&mu)[Q], Real (&nu)[QS > 0 ? QS : 1]) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  constexpr int QT = Q + QS;
+  if constexpr (ACC == ACC_PP) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) mu[j] = a[push_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))];
+#pragma unroll
+    for (int i = 0; i < QS; ++i) nu[i] = a[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
+  } else if constexpr (ACC == ACC_EVEN) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) mu[j] = a[own_addr<QT>(b, j)];
+#pragma unroll
+    for (int i = 0; i < QS; ++i) nu[i] = a[own_addr<QT>(b, Q + i)];
+  } else {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) mu[j] = a[push_addr<QT>(b, L::opp(j), L::ex(j), L::ey(j), L::ez(j))];
+#pragma unroll
+    for (int i = 0; i < QS; ++i) nu[i] = a[push_addr<QT>(b, Q + S::opp(i), S::ex(i), S::ey(i), S::ez(i))];
+  }
+}
+
+template <int Q, int QS, typename Real, bool NT, int ACC>
+__device__ __forceinline__ void store_cot(Real* a, const Nbr& b, const Real (&lf)[Q], const Real (&lg)[QS > 0 ? QS : 1]) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  constexpr int QT = Q + QS;
+  if constexpr (ACC == ACC_PP) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) put<NT>(a + own_addr<QT>(b, j), lf[j]);
+#pragma unroll
+    for (int i = 0; i < QS; ++i) put<NT>(a + own_addr<QT>(b, Q + i), lg[i]);
+  } else if constexpr (ACC == ACC_EVEN) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) put<NT>(a + own_addr<QT>(b, L::opp(j)), lf[j]);
+#pragma unroll
+    for (int i = 0; i < QS; ++i) put<NT>(a + own_addr<QT>(b, Q + S::opp(i)), lg[i]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) put<NT>(a + pull_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j)), lf[j]);
+#pragma unroll
+    for (int i = 0; i < QS; ++i) put<NT>(a + pull_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i)), lg[i]);
+  }
+}
+
+// Pre-collision state of a node for the inspection and objective kernels: the
+// access pattern of the buffer is a run-time argument there.
+template <int Q, int QS, typename Real>
+__device__ __forceinline__ void load_state_rt(const Real* a, const Nbr& b, int acc, Real (&f)[Q],
+                                              Real (&g)[QS > 0 ? QS : 1]) {
+  if (acc == ACC_EVEN) load_state<Q, QS, Real, ACC_EVEN>(a, b, f, g);
+  else if (acc == ACC_ODD) load_state<Q, QS, Real, ACC_ODD>(a, b, f, g);
+  else load_state<Q, QS, Real, ACC_PP>(a, b, f, g);
+}
+
 // ------------------------------------------------------- node operators
 // All operators map the shifted pre-collision populations f~ (and scalar g)
 // of one node to its shifted post-collision values in place.
@@ -535,16 +650,18 @@ __device__ __forceinline__ void node_moments(const Params<Real>& p, int cls, int
 
 // One primal node update: pull, collide by node class, store (coalesced).
 // With MOM, also records the node's pre-collision moments (see Mom).
-template <int Q, int QS, typename Real, bool NT, bool MOM, int V>
-__device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* __restrict__ src,
-                                            Real* __restrict__ dst, const Real* __restrict__ w,
-                                            Real* __restrict__ mom, int x, int y, int z) {
+// src and dst are the same buffer for the in-place patterns, so they carry no
+// restrict qualifier here (the ping-pong kernels declare theirs).
+template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC = ACC_PP>
+__device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* src, Real* dst,
+                                            const Real* __restrict__ w, Real* __restrict__ mom, int x, int y,
+                                            int z) {
+  static_assert(ACC == ACC_PP || !MOM, "recording uses the ping-pong buffers");
   constexpr bool is3d = (Q == 19);
-  constexpr int QT = Q + QS;
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_inode(b);  // workspace node arrays
   Real f[Q], g[QS > 0 ? QS : 1];
-  pull_state<Q, QS, Real>(src, b, f, g);
+  load_state<Q, QS, Real, ACC>(src, b, f, g);
   const int cls = node_class(p, x, y, z, is3d);
   if constexpr (MOM) {
     if (has_moments(p, cls)) {  // the only classes whose transposes read them
@@ -563,10 +680,7 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* _
   } else {
     collide_outlet<Q, QS, Real>(p, f, g);
   }
-#pragma unroll
-  for (int j = 0; j < Q; ++j) put<NT>(dst + own_addr<QT>(b, j), f[j]);
-#pragma unroll
-  for (int i = 0; i < QS; ++i) put<NT>(dst + own_addr<QT>(b, Q + i), g[i]);
+  store_state<Q, QS, Real, NT, ACC>(dst, b, f, g);
 }
 
 template <int Q, int QS, typename Real, bool NT, bool MOM, int V>
@@ -576,6 +690,14 @@ __global__ __launch_bounds__(256) void k_primal(Params<Real> p, const Real* __re
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
   primal_node<Q, QS, Real, NT, MOM, V>(p, src, dst, w, mom, x, blockIdx.y, blockIdx.z);
+}
+
+// One in-place step (even or odd phase) of an unrecorded run.
+template <int Q, int QS, typename Real, bool NT, int V, int ACC>
+__global__ __launch_bounds__(256) void k_primal_inplace(Params<Real> p, Real* a, const Real* __restrict__ w) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  primal_node<Q, QS, Real, NT, false, V, ACC>(p, a, a, w, nullptr, x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------------ objective
@@ -590,7 +712,7 @@ constexpr int kObjBlocks = 64;
 
 template <int Q, int QS, typename Real>
 __global__ __launch_bounds__(kObjThreads) void k_objective_partial(Params<Real> p, const Real* __restrict__ src,
-                                                                   double* __restrict__ part) {
+                                                                   double* __restrict__ part, int pattern) {
   using L = Lat<Q>;
   using S = SLat<QS>;
   constexpr bool is3d = (Q == 19);
@@ -608,7 +730,7 @@ __global__ __launch_bounds__(kObjThreads) void k_objective_partial(Params<Real> 
       if (node_class(p, x, y, z, is3d) == WALL) continue;
       const Nbr b = make_nbr(p, x, y, z);
       Real f[Q], g[QS > 0 ? QS : 1];
-      pull_state<Q, QS, Real>(src, b, f, g);
+      load_state_rt<Q, QS, Real>(src, b, pattern, f, g);
       double s0 = 0, sk = 0;
       Real s0r = 0, skr = 0;
 #pragma unroll
@@ -1077,7 +1199,7 @@ __global__ __launch_bounds__(256) void k_adjoint(Params<Real> p, const Real* __r
 template <int Q, int QS, typename Real>
 __global__ __launch_bounds__(256) void k_fields(Params<Real> p, const Real* __restrict__ src,
                                                 double* __restrict__ rho, double* __restrict__ u,
-                                                double* __restrict__ s) {
+                                                double* __restrict__ s, int acc) {
   using L = Lat<Q>;
   using S = SLat<QS>;
   constexpr bool is3d = (Q == 19);
@@ -1087,7 +1209,7 @@ __global__ __launch_bounds__(256) void k_fields(Params<Real> p, const Real* __re
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_node(b);
   Real f[Q], g[QS > 0 ? QS : 1];
-  pull_state<Q, QS, Real>(src, b, f, g);
+  load_state_rt<Q, QS, Real>(src, b, acc, f, g);
   const int cls = node_class(p, x, y, z, is3d);
   double dr = 0, mx = 0, my = 0, mz = 0, T = 0;
 #pragma unroll
@@ -1152,14 +1274,14 @@ __global__ __launch_bounds__(256) void k_fields(Params<Real> p, const Real* __re
 // Pre-collision state f^t (un-shifted, double) pulled from src.
 template <int Q, int QS, typename Real>
 __global__ __launch_bounds__(256) void k_get_state(Params<Real> p, const Real* __restrict__ src,
-                                                   double* __restrict__ fo, double* __restrict__ go) {
+                                                   double* __restrict__ fo, double* __restrict__ go, int acc) {
   using L = Lat<Q>;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
   const Nbr b = make_nbr(p, x, blockIdx.y, blockIdx.z);
   const int n = own_node(b);
   Real f[Q], g[QS > 0 ? QS : 1];
-  pull_state<Q, QS, Real>(src, b, f, g);
+  load_state_rt<Q, QS, Real>(src, b, acc, f, g);
 #pragma unroll
   for (int j = 0; j < Q; ++j) fo[(size_t)j * p.N + n] = (double)f[j] + L::w(j);
   if (go) {
@@ -1168,16 +1290,25 @@ __global__ __launch_bounds__(256) void k_get_state(Params<Real> p, const Real* _
   }
 }
 
-// Stored post-collision buffer h^{-1} with S h^{-1} = f0: h_j(x) = f0_j(x + e_j).
+// Ping-pong: the stored post-collision buffer h^{-1} with S h^{-1} = f0,
+// h_j(x) = f0_j(x + e_j).  In place (phase E): slot j of x holds f0_j(x).
 template <int Q, int QS, typename Real>
 __global__ __launch_bounds__(256) void k_set_state(Params<Real> p, const double* __restrict__ f0,
-                                                   const double* __restrict__ g0, Real* __restrict__ dst) {
+                                                   const double* __restrict__ g0, Real* __restrict__ dst, int acc) {
   using L = Lat<Q>;
   using S = SLat<QS>;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
   constexpr int QT = Q + QS;
   const Nbr b = make_nbr(p, x, blockIdx.y, blockIdx.z);
+  if (acc != ACC_PP) {
+    const int n = own_node(b);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) dst[own_addr<QT>(b, j)] = (Real)(f0[(size_t)j * p.N + n] - L::w(j));
+#pragma unroll
+    for (int i = 0; i < QS; ++i) dst[own_addr<QT>(b, Q + i)] = g0 ? (Real)g0[(size_t)i * p.N + n] : Real(0);
+    return;
+  }
 #pragma unroll
   for (int j = 0; j < Q; ++j)
     dst[own_addr<QT>(b, j)] = (Real)(f0[(size_t)j * p.N + push_node(b, L::ex(j), L::ey(j), L::ez(j))] - L::w(j));
@@ -1201,20 +1332,33 @@ __global__ __launch_bounds__(256) void k_maps(Params<Real> p, uint8_t* __restric
   }
 }
 
-// Adjoint state (row-blocked, context precision) to plane-major doubles.
+// Adjoint state lambda(x) (row-blocked, context precision) to plane-major
+// doubles.  Ping-pong: slot j of x.  In place, phase E: slot j of x - e_j
+// (the buffer holds mu_j(x) = lambda_j(x + e_j) at slot j of x); phase O:
+// slot opp(j) of x.
 template <int Q, int QS, typename Real>
 __global__ __launch_bounds__(256) void k_get_adjoint(Params<Real> p, const Real* __restrict__ lam,
-                                                     double* __restrict__ lf, double* __restrict__ lg) {
+                                                     double* __restrict__ lf, double* __restrict__ lg, int acc) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
   constexpr int QT = Q + QS;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
   const Nbr b = make_nbr(p, x, blockIdx.y, blockIdx.z);
   const int n = own_node(b);
 #pragma unroll
-  for (int j = 0; j < Q; ++j) lf[(size_t)j * p.N + n] = (double)lam[own_addr<QT>(b, j)];
+  for (int j = 0; j < Q; ++j) {
+    const int a = acc == ACC_EVEN ? pull_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))
+                                  : (acc == ACC_ODD ? own_addr<QT>(b, L::opp(j)) : own_addr<QT>(b, j));
+    lf[(size_t)j * p.N + n] = (double)lam[a];
+  }
   if (lg) {
 #pragma unroll
-    for (int i = 0; i < QS; ++i) lg[(size_t)i * p.N + n] = (double)lam[own_addr<QT>(b, Q + i)];
+    for (int i = 0; i < QS; ++i) {
+      const int a = acc == ACC_EVEN ? pull_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))
+                                    : (acc == ACC_ODD ? own_addr<QT>(b, Q + S::opp(i)) : own_addr<QT>(b, Q + i));
+      lg[(size_t)i * p.N + n] = (double)lam[a];
+    }
   }
 }
 
@@ -1227,29 +1371,21 @@ __global__ __launch_bounds__(256) void k_get_adjoint(Params<Real> p, const Real*
 //   w(x)           <- clip(w + zeta (g + c_pen (1 - 2w)), 0, 1) (interior nodes; eq. P)
 // with mu_j(x) = lambda^n_j(x + e_j).  Each node owns its w, so the in-place
 // update races with nothing.
-template <int Q, int QS, typename Real, bool NT, int V>
-__global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __restrict__ prim_in,
-                                                 Real* __restrict__ prim_out, const Real* __restrict__ lam_in,
-                                                 Real* __restrict__ lam_out, Real* __restrict__ w,
-                                                 Real* __restrict__ grad, const double* __restrict__ glob, Real zeta,
-                                                 Real c_pen) {
-  using L = Lat<Q>;
-  using S = SLat<QS>;
+// prim_in/prim_out and lam_in/lam_out are the same buffers in place, hence no
+// restrict on them here (the ping-pong kernel declares it).
+template <int Q, int QS, typename Real, bool NT, int V, int ACC>
+__device__ __forceinline__ void oneshot_node(const Params<Real>& p, const Real* prim_in, Real* prim_out,
+                                             const Real* lam_in, Real* lam_out, Real* __restrict__ w,
+                                             Real* __restrict__ grad, const double* __restrict__ glob, Real zeta,
+                                             Real c_pen, int x, int y, int z) {
   constexpr bool is3d = (Q == 19);
   constexpr int QSA = QS > 0 ? QS : 1;
-  constexpr int QT = Q + QS;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= p.nx) return;
-  const int y = blockIdx.y, z = blockIdx.z;
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_inode(b);  // workspace node arrays
   const int cls = node_class(p, x, y, z, is3d);
   Real f[Q], g[QSA], mu[Q], nu[QSA];
-  pull_state<Q, QS, Real>(prim_in, b, f, g);
-#pragma unroll
-  for (int j = 0; j < Q; ++j) mu[j] = lam_in[push_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))];
-#pragma unroll
-  for (int i = 0; i < QS; ++i) nu[i] = lam_in[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
+  load_state<Q, QS, Real, ACC>(prim_in, b, f, g);
+  load_cot<Q, QS, Real, ACC>(lam_in, b, mu, nu);
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
   Real m[Mom<Q, QS, V>::N], lf[Q], lg[QSA], gw;
   node_moments<Q, QS, Real, V>(p, cls, y, z, f, g, m);
@@ -1271,19 +1407,36 @@ __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __r
   } else {
     collide_outlet<Q, QS, Real>(p, f, g);
   }
-#pragma unroll
-  for (int j = 0; j < Q; ++j) put<NT>(prim_out + own_addr<QT>(b, j), f[j]);
-#pragma unroll
-  for (int i = 0; i < QS; ++i) put<NT>(prim_out + own_addr<QT>(b, Q + i), g[i]);
-#pragma unroll
-  for (int j = 0; j < Q; ++j) put<NT>(lam_out + own_addr<QT>(b, j), lf[j]);
-#pragma unroll
-  for (int i = 0; i < QS; ++i) put<NT>(lam_out + own_addr<QT>(b, Q + i), lg[i]);
+  store_state<Q, QS, Real, NT, ACC>(prim_out, b, f, g);
+  store_cot<Q, QS, Real, NT, ACC>(lam_out, b, lf, lg);
   grad[n] = gw;
   if (cls == INTERIOR) {
     const Real v = wn + zeta * (gw + c_pen * (Real(1) - Real(2) * wn));
     w[n] = v < Real(0) ? Real(0) : (v > Real(1) ? Real(1) : v);
   }
+}
+
+template <int Q, int QS, typename Real, bool NT, int V>
+__global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __restrict__ prim_in,
+                                                 Real* __restrict__ prim_out, const Real* __restrict__ lam_in,
+                                                 Real* __restrict__ lam_out, Real* __restrict__ w,
+                                                 Real* __restrict__ grad, const double* __restrict__ glob, Real zeta,
+                                                 Real c_pen) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  oneshot_node<Q, QS, Real, NT, V, ACC_PP>(p, prim_in, prim_out, lam_in, lam_out, w, grad, glob, zeta, c_pen, x,
+                                           blockIdx.y, blockIdx.z);
+}
+
+// One in-place one-shot iteration (even or odd phase): a is the primal buffer,
+// l the adjoint buffer, each read and rewritten in place.
+template <int Q, int QS, typename Real, bool NT, int V, int ACC>
+__global__ __launch_bounds__(256) void k_oneshot_inplace(Params<Real> p, Real* a, Real* l, Real* __restrict__ w,
+                                                         Real* __restrict__ grad, const double* __restrict__ glob,
+                                                         Real zeta, Real c_pen) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  oneshot_node<Q, QS, Real, NT, V, ACC>(p, a, a, l, l, w, grad, glob, zeta, c_pen, x, blockIdx.y, blockIdx.z);
 }
 
 // --------------------------------------------------------- batched launches

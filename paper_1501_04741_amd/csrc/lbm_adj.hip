@@ -68,6 +68,7 @@ struct Plan {
   uint64_t mom_bytes = 0;    // aligned, one moment set
   uint64_t node_bytes = 0;   // aligned Np x Real
   int64_t C = 1, S = 1;      // checkpoint interval and slots
+  bool inplace = false;      // one buffer per state (unrecorded runs and one-shot only)
   uint64_t total = 0;
 };
 
@@ -153,6 +154,9 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
   }
   if (c->reserved2 != 0) return bad("reserved2 must be 0");
   if (c->tau_s_solid != 0.0 && !(c->tau_s_solid > 0.5)) return bad("tau_s_solid must be 0 or exceed 1/2");
+  if (c->inplace != 0 && c->inplace != 1) return bad("inplace must be 0 or 1");
+  if (c->reserved3 != 0) return bad("reserved3 must be 0");
+  if (c->inplace && c->nsteps != 0) return bad("in-place contexts do not record: nsteps must be 0");
   if (c->inlet == LBM_INLET_PRESSURE && !(c->rho_in > 0.0 && c->u_cap >= 0.0 && c->u_cap < 1.0))
     return bad("pressure inlet needs rho_in > 0 and 0 <= u_cap < 1");
   if (c->nsteps < 0 || c->checkpoint_interval < 0) return bad("nsteps and checkpoint_interval must be >= 0");
@@ -191,6 +195,14 @@ lbm_status make_plan(const lbm_config* c, Plan* p, std::string* why) {
   p->state_bytes = align_up((uint64_t)p->QT * p->Np * p->rs);
   p->mom_bytes = align_up((uint64_t)mom_values(c) * p->Np * p->rs);
   p->node_bytes = align_up((uint64_t)p->Np * p->rs);
+  if (c->inplace) {
+    // the state (kept in the first checkpoint slot) and the adjoint state, nothing else
+    p->inplace = true;
+    p->C = 0;
+    p->S = 1;
+    p->total = 2 * p->node_bytes + align_up(kGlobBytes) + align_up(kDescBytes) + 2 * p->state_bytes;
+    return LBM_OK;
+  }
   const int64_t Nst = std::max<int64_t>(c->nsteps, 1);
   int64_t C;
   if (c->checkpoint_interval > 0) {
@@ -309,7 +321,48 @@ struct Ops {
     hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V>), dim3(blocks), dim3(kBatchBX), 0, st, A);
   }
 
-  static bool nt(lbm_ctx* c) { return 2 * c->plan.state_bytes > kLastLevelCacheBytes; }
+  // streaming stores when the states a step touches exceed the last-level cache
+  static bool nt(lbm_ctx* c) { return (c->plan.inplace ? 1 : 2) * c->plan.state_bytes > kLastLevelCacheBytes; }
+  // access pattern of the current state buffer: ping-pong, or the in-place phase of step t
+  static int acc(lbm_ctx* c) { return c->plan.inplace ? ((c->t % 2 == 0) ? ACC_EVEN : ACC_ODD) : ACC_PP; }
+  // One in-place step from the current phase.
+  static void primal_inplace(lbm_ctx* c) {
+    Geo g = node_geometry(c->cfg);
+    Real* a = (Real*)c->cur;
+    const Real* w = (const Real*)c->w;
+    const bool even = (c->t % 2 == 0);
+    if (nt(c)) {
+      if (even)
+        hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, true, V, ACC_EVEN>), g.grid, g.block, 0, c->stream, P(c), a, w);
+      else
+        hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, true, V, ACC_ODD>), g.grid, g.block, 0, c->stream, P(c), a, w);
+    } else {
+      if (even)
+        hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, false, V, ACC_EVEN>), g.grid, g.block, 0, c->stream, P(c), a, w);
+      else
+        hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, false, V, ACC_ODD>), g.grid, g.block, 0, c->stream, P(c), a, w);
+    }
+  }
+  static void oneshot_inplace(lbm_ctx* c, double zeta, double pen) {
+    Geo g = node_geometry(c->cfg);
+    Real* a = (Real*)c->cur;
+    Real* l = (Real*)c->lam[0];
+    Real* w = (Real*)c->w;
+    Real* gr = (Real*)c->grad;
+    const double* gl = (const double*)c->glob;
+    const bool even = (c->t % 2 == 0);
+#define LBM_OS_INPLACE(NTV, ACCV)                                                                         \
+  hipLaunchKernelGGL((k_oneshot_inplace<Q, QS, Real, NTV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), a, l, w, gr, \
+                     gl, (Real)zeta, (Real)pen)
+    if (nt(c)) {
+      if (even) LBM_OS_INPLACE(true, ACC_EVEN);
+      else LBM_OS_INPLACE(true, ACC_ODD);
+    } else {
+      if (even) LBM_OS_INPLACE(false, ACC_EVEN);
+      else LBM_OS_INPLACE(false, ACC_ODD);
+    }
+#undef LBM_OS_INPLACE
+  }
   static lbm_status write_static(lbm_ctx* c) {
     static_assert(sizeof(BatchStatic<Real>) <= kDescBytes, "descriptor region too small");
     BatchStatic<Real> h;
@@ -345,7 +398,7 @@ struct Ops {
   static void objective(lbm_ctx* c, const void* src, double* out) {
     double* part = c->glob + kGlobSlots;
     hipLaunchKernelGGL((k_objective_partial<Q, QS, Real>), dim3(kObjBlocks), dim3(kObjThreads), 0, c->stream, P(c),
-                       (const Real*)src, part);
+                       (const Real*)src, part, acc(c));
     hipLaunchKernelGGL((k_objective_final<Q, QS, Real>), dim3(1), dim3(64), 0, c->stream, P(c),
                        (const double*)part, out);
   }
@@ -377,19 +430,23 @@ struct Ops {
   }
   static void get_adjoint(lbm_ctx* c, const void* lam, double* lf, double* lg) {
     Geo g = node_geometry(c->cfg);
-    hipLaunchKernelGGL((k_get_adjoint<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)lam, lf, lg);
+    hipLaunchKernelGGL((k_get_adjoint<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)lam, lf, lg,
+                       acc(c));
   }
   static void fields(lbm_ctx* c, const void* src, double* rho, double* u, double* s) {
     Geo g = node_geometry(c->cfg);
-    hipLaunchKernelGGL((k_fields<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src, rho, u, s);
+    hipLaunchKernelGGL((k_fields<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src, rho, u, s,
+                       acc(c));
   }
   static void get_state(lbm_ctx* c, const void* src, double* f, double* gg) {
     Geo g = node_geometry(c->cfg);
-    hipLaunchKernelGGL((k_get_state<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src, f, gg);
+    hipLaunchKernelGGL((k_get_state<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src, f, gg,
+                       acc(c));
   }
   static void set_state(lbm_ctx* c, const double* f, const double* gg, void* dst) {
     Geo g = node_geometry(c->cfg);
-    hipLaunchKernelGGL((k_set_state<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), f, gg, (Real*)dst);
+    hipLaunchKernelGGL((k_set_state<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), f, gg, (Real*)dst,
+                       c->plan.inplace ? ACC_EVEN : ACC_PP);
   }
   static void maps(lbm_ctx* c, uint8_t* mask, int64_t* src) {
     Geo g = node_geometry(c->cfg);
@@ -454,6 +511,13 @@ void* rec_dst(lbm_ctx* c, int64_t k) {
 template <class O>
 struct RunPrimal {
   static lbm_status run(lbm_ctx* c, int64_t nsteps, int record) {
+    if (c->plan.inplace) {
+      for (int64_t i = 0; i < nsteps; ++i) {
+        O::primal_inplace(c);
+        ++c->t;
+      }
+      return launch_check(c, "in-place primal step");
+    }
     for (int64_t i = 0; i < nsteps; ++i) {
       void* src = c->cur;
       void* dst = record ? rec_dst(c, c->t) : other_pp(c, c->cur);
@@ -602,6 +666,11 @@ struct RunOneshot {
     const bool state_dependent_seed = (c->cfg.c_var != 0.0);
     for (int64_t i = 0; i < nsteps; ++i) {
       if (state_dependent_seed) O::objective(c, c->cur, c->glob);
+      if (c->plan.inplace) {
+        O::oneshot_inplace(c, zeta, pen);
+        ++c->t;
+        continue;
+      }
       void* dst = (c->cur == c->pp[0]) ? c->pp[1] : c->pp[0];
       O::oneshot(c, c->cur, dst, c->lam[c->lam_cur], c->lam[1 - c->lam_cur], zeta, pen);
       c->cur = dst;
@@ -738,6 +807,7 @@ lbm_status check_batch(lbm_ctx* const* cs, int32_t n) {
     if (!cs[k]) return LBM_EINVAL;
     for (int q = 0; q < k; ++q)
       if (cs[q] == cs[k]) return fail(cs[0], LBM_EINVAL, "batch: context %d appears twice", k);
+    if (cs[k]->plan.inplace) return fail(cs[0], LBM_EINVAL, "batch: context %d streams in place", k);
     const lbm_config &a = cs[0]->cfg, &b = cs[k]->cfg;
     if (a.flow != b.flow || a.scalar != b.scalar || a.precision != b.precision)
       return fail(cs[0], LBM_EINVAL, "batch: context %d has another lattice or precision", k);
@@ -806,13 +876,19 @@ lbm_status lbm_create(const lbm_config* cfg, void* hip_stream, void* workspace_d
   q += align_up(kGlobBytes);
   c->desc = q;
   q += align_up(kDescBytes);
-  for (int i = 0; i < 2; ++i) {
-    c->lam[i] = q;
+  if (p.inplace) {
+    c->lam[0] = c->lam[1] = q;  // one adjoint buffer, rewritten in place
     q += p.state_bytes;
-  }
-  for (int i = 0; i < 2; ++i) {
-    c->pp[i] = q;
-    q += p.state_bytes;
+    c->pp[0] = c->pp[1] = nullptr;
+  } else {
+    for (int i = 0; i < 2; ++i) {
+      c->lam[i] = q;
+      q += p.state_bytes;
+    }
+    for (int i = 0; i < 2; ++i) {
+      c->pp[i] = q;
+      q += p.state_bytes;
+    }
   }
   c->ckpt = q;
   q += (uint64_t)p.S * p.state_bytes;
@@ -870,6 +946,7 @@ lbm_status lbm_primal_steps(lbm_ctx* c, int64_t nsteps, int32_t record) {
   if (!c->design_set) return fail(c, LBM_ESTATE, "primal_steps: no design field set");
   if (c->adj_started) return fail(c, LBM_ESTATE, "primal_steps: adjoint started; call lbm_reset first");
   if (record && c->os_active) return fail(c, LBM_ESTATE, "primal_steps: one-shot running; call lbm_reset first");
+  if (record && c->plan.inplace) return fail(c, LBM_ESTATE, "primal_steps: an in-place context does not record");
   if (record) {
     if (!(c->rec_open && c->t == c->rec_len))
       return fail(c, LBM_ESTATE, "primal_steps: recording must start at t = 0 or continue a recorded run");
@@ -913,6 +990,7 @@ lbm_status lbm_adjoint_steps(lbm_ctx* c, int64_t nsteps) {
   if (!c) return LBM_EINVAL;
   if (nsteps < 0) return fail(c, LBM_EINVAL, "adjoint_steps: negative count");
   if (c->os_active) return fail(c, LBM_ESTATE, "adjoint_steps: one-shot running; call lbm_reset first");
+  if (c->plan.inplace) return fail(c, LBM_ESTATE, "adjoint_steps: an in-place context keeps no trajectory");
   if (!c->adj_started) {
     if (!c->design_set) return fail(c, LBM_ESTATE, "adjoint_steps: no design field set");
     if (!(c->rec_open && c->t == c->rec_len))

@@ -79,6 +79,8 @@ class LbmConfig(ctypes.Structure):
         ("reserved2", ctypes.c_int32),
         ("mrt_rates", ctypes.c_double * 5),
         ("tau_s_solid", ctypes.c_double),
+        ("inplace", ctypes.c_int32),
+        ("reserved3", ctypes.c_int32),
     ]
 
 NG = 9  # boundary sums ("globals") lbm_objective returns
@@ -96,7 +98,7 @@ MODEL_DEFAULTS = dict(
 
 
 def make_config(params: dict, nsteps: int, precision: str = "fp32", checkpoint_interval: int = 0,
-                hbm_budget_bytes: int = 0) -> LbmConfig:
+                hbm_budget_bytes: int = 0, inplace: bool = False) -> LbmConfig:
     p = dict(MODEL_DEFAULTS)
     unknown = set(params) - set(MODEL_DEFAULTS)
     if unknown:
@@ -117,7 +119,7 @@ def make_config(params: dict, nsteps: int, precision: str = "fp32", checkpoint_i
         checkpoint_interval=int(checkpoint_interval), hbm_budget_bytes=int(hbm_budget_bytes), inlet=im,
         reserved1=0, rho_in=float(p["rho_in"]), u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]), collision=co,
         reserved2=0, mrt_rates=(ctypes.c_double * 5)(*[float(v) for v in p["mrt_rates"]]),
-        tau_s_solid=float(p["tau_s_solid"]))
+        tau_s_solid=float(p["tau_s_solid"]), inplace=1 if inplace else 0, reserved3=0)
 
 
 _lock = threading.Lock()
@@ -300,14 +302,16 @@ class Lbm:
     horizon a recorded run may reach.  Device memory comes from torch."""
 
     def __init__(self, params: dict, nsteps: int, precision: str = "fp32", checkpoint_interval: int = 0,
-                 hbm_budget_bytes: int = 0, device=None, stream=None, workspace=None):
+                 hbm_budget_bytes: int = 0, device=None, stream=None, workspace=None, inplace: bool = False):
         """workspace: optional caller-owned uint8 device tensor (256-byte aligned) of at
-        least lbm_required_bytes; by default one is allocated with torch.empty."""
+        least lbm_required_bytes; by default one is allocated with torch.empty.
+        inplace: stream in place (one buffer per state; unrecorded runs and one-shot
+        only, nsteps must be 0)."""
         library()
         self.device = torch.device(device if device is not None else "cuda")
         self.params = dict(params)
         self.precision = precision
-        self.cfg = make_config(params, nsteps, precision, checkpoint_interval, hbm_budget_bytes)
+        self.cfg = make_config(params, nsteps, precision, checkpoint_interval, hbm_budget_bytes, inplace)
         self.dtype = torch.float32 if precision == "fp32" else torch.float64
         self.nx, self.ny, self.nz = self.cfg.nx, self.cfg.ny, self.cfg.nz
         self.N = self.nx * self.ny * self.nz

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_config_struct_size_matches(lib):
     cfg = lbm.make_config(dict(flow=9, nx=16, ny=8), 10)
-    assert cfg.struct_size == ctypes.sizeof(lbm.LbmConfig) == 248
+    assert cfg.struct_size == ctypes.sizeof(lbm.LbmConfig) == 256
     bad = lbm.make_config(dict(flow=9, nx=16, ny=8), 10)
     bad.struct_size = 150
     out = ctypes.c_uint64()
@@ -103,3 +103,16 @@ def test_checkpoint_plan_sizes(lib):
     n2 = 512 * 256
     c500 = _bytes(dict(flow=9, scalar=5, nx=512, ny=256), 20000, checkpoint_interval=500)
     assert abs(c500 - ((4 + 40) * 14 * n2 * 4 + 500 * 4 * n2 * 4)) < 4 * MB
+
+
+def test_inplace_workspace_holds_two_states(lib):
+    """An in-place context keeps one primal and one adjoint buffer: two states
+    fewer than the smallest ping-pong plan of the same lattice, no moments."""
+    p = dict(flow=19, nx=256, ny=128, nz=128)
+    state = 19 * 256 * 128 * 128 * 4
+    small = lbm.lbm_required_bytes(lbm.make_config(p, 0))
+    inpl = lbm.lbm_required_bytes(lbm.make_config(p, 0, inplace=True))
+    assert inpl < 2.2 * state + 64 * 2 ** 20
+    assert small - inpl >= 3 * state      # ping-pong: 4 states + checkpoint + moment set
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_required_bytes(lbm.make_config(p, 10, inplace=True))   # in place does not record

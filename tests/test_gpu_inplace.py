@@ -1,0 +1,143 @@
+"""In-place streaming (one buffer per state, alternating even/odd access
+patterns) against the ping-pong path, bitwise: unrecorded primal runs of odd
+and even length, the one-shot iteration in chunks, state import/export in both
+phases; and the calls an in-place context refuses."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1501_04741_amd import inputs
+from paper_1501_04741_amd import lbm as L
+from paper_1501_04741_amd.lbm import Lbm, LbmError
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return None if t is None else t.detach().cpu().numpy()
+
+
+def _p(flow, scalar, nx, ny, nz, **kw):
+    p = dict(flow=flow, scalar=scalar, nx=nx, ny=ny, nz=nz, tau=0.8, tau_s=0.6, u_in=0.02, switch_fn="ramp",
+             switch_param=0.05, c_dp=1.0)
+    if scalar:
+        p.update(c_hf=0.5, c_var=1.0, s_in_lo=0.0, s_in_hi=1.0, s_split_axis=1)
+    p.update(kw)
+    return p
+
+
+CASES = [
+    ("d2q9_ragged", _p(9, 0, 70, 9, 1)),
+    ("d2q9_d2q5_dirichlet_blended", _p(9, 5, 40, 11, 1, scalar_wall="dirichlet", s_wall=1.0, tau_s_solid=3.0)),
+    ("d3q19", _p(19, 0, 21, 7, 6)),
+    ("d3q19_d3q7_mrt_pressure_mix", _p(19, 7, 24, 6, 5, collision="mrt", inlet="pressure", rho_in=1.02,
+                                       u_cap=0.012, c_mix=1.0, s_in_lo=-1.0)),
+    ("d3q19_d3q7_periodic", _p(19, 7, 9, 6, 5, periodic=1, c_dp=0.0, c_hf=0.0, c_var=0.0)),
+]
+
+
+def _pair(p, prec, seed=0):
+    dt = np.float32 if prec == "fp32" else np.float64
+    w = torch.from_numpy(inputs.porosity(p["nx"], p["ny"], p["nz"], seed, 3, dt))
+    a = Lbm(p, nsteps=0, precision=prec)
+    b = Lbm(p, nsteps=0, precision=prec, inplace=True)
+    for c in (a, b):
+        c.set_design(w)
+        c.reset()
+    return a, b
+
+
+def _same_state(a, b):
+    fa, ga = a.get_state()
+    fb, gb = b.get_state()
+    assert np.array_equal(_np(fa), _np(fb))
+    if ga is not None:
+        assert np.array_equal(_np(ga), _np(gb))
+    for x, y in zip(a.fields(), b.fields()):
+        if x is not None:
+            assert np.array_equal(_np(x), _np(y))
+    assert a.objective() == b.objective()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("name,p", CASES, ids=[c[0] for c in CASES])
+def test_inplace_primal_bitwise_equals_pingpong(name, p, prec):
+    a, b = _pair(p, prec)
+    done = 0
+    for k in (0, 1, 1, 5, 16):          # ends on both phases along the way
+        a.primal_steps(k)
+        b.primal_steps(k)
+        done += k
+        _same_state(a, b)
+    assert done == 23
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("name,p", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_inplace_oneshot_bitwise_equals_pingpong(name, p, prec):
+    a, b = _pair(p, prec, seed=1)
+    for c in (a, b):
+        c.primal_steps(3)                # start the one-shot from an odd phase
+    for k in (1, 4, 7, 2):
+        a.oneshot_steps(k, 0.5, -0.001)
+        b.oneshot_steps(k, 0.5, -0.001)
+        assert np.array_equal(_np(a.design()), _np(b.design()))
+        assert np.array_equal(_np(a.gradient()), _np(b.gradient()))
+        la, lga = a.get_adjoint()
+        lb, lgb = b.get_adjoint()
+        assert np.array_equal(_np(la), _np(lb))
+        if lga is not None:
+            assert np.array_equal(_np(lga), _np(lgb))
+        _same_state(a, b)
+
+
+def test_inplace_oneshot_matches_oracle():
+    p = CASES[3][1]
+    iters, zeta, pen = 45, 2.0, -0.002
+    w0 = inputs.porosity(p["nx"], p["ny"], p["nz"], 1, 3)
+    ctx = Lbm(p, nsteps=0, precision="fp64", inplace=True)
+    ctx.set_design(torch.from_numpy(w0))
+    ctx.reset()
+    for k in (1, 25, iters - 26):
+        ctx.oneshot_steps(k, zeta, pen)
+    ref = oracle.oneshot(p, w0, iters, zeta, pen)
+    f, g = ctx.get_state()
+    lf, lg = ctx.get_adjoint()
+    assert np.max(np.abs(_np(ctx.design()) - ref["w"])) <= 1e-12
+    assert np.max(np.abs(_np(f) - ref["f"])) <= 1e-13
+    scale = max(np.abs(ref["lam_f"]).max(), np.abs(ref["lam_g"]).max())
+    assert np.max(np.abs(_np(lf) - ref["lam_f"])) <= 1e-10 * scale
+    assert np.max(np.abs(_np(lg) - ref["lam_g"])) <= 1e-10 * scale
+
+
+def test_inplace_set_state_round_trip():
+    p = CASES[1][1]
+    n = p["nx"] * p["ny"]
+    rng = np.random.default_rng(5)
+    e, wt, _, _ = oracle.lattice(9)
+    f0 = torch.from_numpy(wt[:, None] * (1 + 0.05 * rng.standard_normal((9, n)))).cuda()
+    g0 = torch.from_numpy(0.3 * rng.random((5, n))).cuda()
+    a, b = _pair(p, "fp64")
+    for c in (a, b):
+        c.set_state(f0, g0)
+    fb, gb = b.get_state()
+    assert torch.equal(fb, f0) and torch.equal(gb, g0)
+    for k in (1, 2):
+        a.primal_steps(k)
+        b.primal_steps(k)
+        _same_state(a, b)
+
+
+def test_inplace_refuses_recording_adjoint_and_batches():
+    p = CASES[0][1]
+    a, b = _pair(p, "fp32")
+    with pytest.raises(LbmError):
+        b.primal_steps(1, record=True)
+    with pytest.raises(LbmError):
+        b.adjoint_steps(1)
+    with pytest.raises(LbmError):
+        L.lbm_primal_steps_batch([b.ctx], 1, record=False)
+    b.primal_steps(2)                    # still usable
+    a.primal_steps(2)
+    _same_state(a, b)
