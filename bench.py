@@ -196,6 +196,47 @@ def mrt_leg(dev, steps=200):
             "adjoint": {"kernel": "k_adjoint<19,0,float,MRT>", "mlups": nodes / adj_us, "roofline": roof(ab, adj_us)}}
 
 
+def inplace_leg(dev, steps=200):
+    """The 256x128x128 channel streamed in place (one buffer per state): an
+    unrecorded forward and the one-shot iteration, FP32, with the workspace of
+    the in-place and the ping-pong one-shot contexts."""
+    import torch
+
+    from paper_1501_04741_amd import inputs
+    from paper_1501_04741_amd.lbm import Lbm
+
+    wl = inputs.workload("d3q19_channel_256x128x128")
+    p = inputs.model_params(wl)
+    w = torch.from_numpy(inputs.design_for(wl)).to(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    c = Lbm(p, nsteps=0, precision="fp32", device=dev, inplace=True)
+    c.set_design(w)
+    c.reset()
+    c.primal_steps(20)
+    ev[0].record()
+    c.primal_steps(steps)
+    ev[1].record()
+    c.reset()
+    c.oneshot_steps(20, 0.0, 0.0)
+    ev[2].record()
+    c.oneshot_steps(steps, 0.0, 0.0)
+    ev[3].record()
+    torch.cuda.synchronize()
+    ws_inplace = c.workspace_bytes
+    c.close()
+    ws_pp = Lbm(p, nsteps=0, precision="fp32", device=dev).workspace_bytes
+    prim_us = ev[0].elapsed_time(ev[1]) * 1e3 / steps
+    os_us = ev[2].elapsed_time(ev[3]) * 1e3 / steps
+    pb, ob = primal_bytes(p, "fp32", recorded=False), oneshot_bytes(p, "fp32")
+    nodes = p["nx"] * p["ny"] * p["nz"]
+    roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
+    return {"workload": "d3q19_channel_256x128x128 streamed in place", "steps_timed": steps,
+            "primal": {"kernel": "k_primal_inplace<19,0,float>", "mlups": nodes / prim_us, "roofline": roof(pb, prim_us)},
+            "oneshot": {"kernel": "k_oneshot_inplace<19,0,float>", "mlups": nodes / os_us, "roofline": roof(ob, os_us)},
+            "workspace_gb": {"inplace": round(ws_inplace / 1e9, 3), "ping_pong": round(ws_pp / 1e9, 3)}}
+
+
 def cpu_baseline(p, w64, steps):
     import oracle
     cores = oracle.threads()
@@ -284,7 +325,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="d3q19_channel_256x128x128")
     ap.add_argument("--lbm-steps", type=int, default=None, help="override the primal horizon N")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixer", action="store_true", help="skip the mixing-duct and MRT legs")
+    ap.add_argument("--no-mixer", action="store_true", help="skip the mixing-duct, MRT and in-place legs")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run one device copy of MB megabytes (counter calibration for profiles)")
@@ -451,6 +492,8 @@ def main(argv=None):
         rec["mixer"] = mixer_leg(dev)
         print("[bench] MRT leg", file=sys.stderr, flush=True)
         rec["mrt"] = mrt_leg(dev)
+        print("[bench] in-place leg", file=sys.stderr, flush=True)
+        rec["inplace"] = inplace_leg(dev)
     if not args.no_cpu_baseline:
         print("[bench] GPU timing done; timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(p, w_np.astype(np.float64), args.cpu_steps)
