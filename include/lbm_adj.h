@@ -130,12 +130,15 @@ typedef struct lbm_config {
                           * 3.2): tau_s(w) = w tau_s + (1-w) tau_s_solid at  *
                           * interior nodes.  0 = tau_s everywhere            */
   int32_t inplace;       /* 1: one buffer per state, streamed in place       *
-                          * (alternating even/odd access patterns); halves  *
-                          * the state memory of unrecorded runs and of the  *
-                          * one-shot iteration.  Requires nsteps = 0: such  *
-                          * a context neither records nor runs the unsteady *
-                          * adjoint nor joins batched launches (LBM_ESTATE / *
-                          * LBM_EINVAL)                                      */
+                          * (alternating even/odd access patterns): one     *
+                          * primal and one adjoint buffer instead of two    *
+                          * each.  A recorded run then keeps the moments of  *
+                          * every step (checkpoint_interval 0 or >= nsteps; *
+                          * LBM_ENOMEM when they exceed the budget), so the *
+                          * adjoint never needs a stored state.  With       *
+                          * nsteps = 0 only unrecorded runs and the one-shot *
+                          * iteration are available.  In-place contexts do  *
+                          * not join batched launches (LBM_EINVAL)          */
   int32_t reserved3;     /* must be 0                                        */
 } lbm_config;
 

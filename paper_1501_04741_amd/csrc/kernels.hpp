@@ -656,7 +656,6 @@ template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC = ACC_
 __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* src, Real* dst,
                                             const Real* __restrict__ w, Real* __restrict__ mom, int x, int y,
                                             int z) {
-  static_assert(ACC == ACC_PP || !MOM, "recording uses the ping-pong buffers");
   constexpr bool is3d = (Q == 19);
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_inode(b);  // workspace node arrays
@@ -692,12 +691,13 @@ __global__ __launch_bounds__(256) void k_primal(Params<Real> p, const Real* __re
   primal_node<Q, QS, Real, NT, MOM, V>(p, src, dst, w, mom, x, blockIdx.y, blockIdx.z);
 }
 
-// One in-place step (even or odd phase) of an unrecorded run.
-template <int Q, int QS, typename Real, bool NT, int V, int ACC>
-__global__ __launch_bounds__(256) void k_primal_inplace(Params<Real> p, Real* a, const Real* __restrict__ w) {
+// One in-place step (even or odd phase); with MOM it also records the moments.
+template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC>
+__global__ __launch_bounds__(256) void k_primal_inplace(Params<Real> p, Real* a, const Real* __restrict__ w,
+                                                        Real* __restrict__ mom) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
-  primal_node<Q, QS, Real, NT, false, V, ACC>(p, a, a, w, nullptr, x, blockIdx.y, blockIdx.z);
+  primal_node<Q, QS, Real, NT, MOM, V, ACC>(p, a, a, w, mom, x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------------ objective
@@ -866,14 +866,16 @@ __device__ __forceinline__ void seed_values(const Params<Real>& p, int cls, cons
 template <int Q, int QS, typename Real>
 __device__ __forceinline__ void seed_node(const Params<Real>& p, const Real* __restrict__ src,
                                           const double* __restrict__ glob, Real* __restrict__ lam, int x, int y,
-                                          int z) {
+                                          int z, int pattern, int inplace_out) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
   constexpr bool is3d = (Q == 19);
   constexpr int QT = Q + QS;
   const Nbr b = make_nbr(p, x, y, z);
   const int cls = node_class(p, x, y, z, is3d);
   Real f[Q], g[QS > 0 ? QS : 1];
   if ((QS > 0 && cls == OUTLET) || (cls == INLET && p.inlet_mode == IN_PRESSURE)) {
-    pull_state<Q, QS, Real>(src, b, f, g);
+    load_state_rt<Q, QS, Real>(src, b, pattern, f, g);
   } else {
 #pragma unroll
     for (int j = 0; j < Q; ++j) f[j] = Real(0);
@@ -882,18 +884,20 @@ __device__ __forceinline__ void seed_node(const Params<Real>& p, const Real* __r
   }
   double lf[Q], lg[QS > 0 ? QS : 1];
   seed_values<Q, QS, Real>(p, cls, f, g, glob, lf, lg);
+  // in place, lambda^N enters as an odd-phase cotangent buffer: lambda_j(x) in slot opp(j) of x
 #pragma unroll
-  for (int j = 0; j < Q; ++j) lam[own_addr<QT>(b, j)] = (Real)lf[j];
+  for (int j = 0; j < Q; ++j) lam[own_addr<QT>(b, inplace_out ? L::opp(j) : j)] = (Real)lf[j];
 #pragma unroll
-  for (int i = 0; i < QS; ++i) lam[own_addr<QT>(b, Q + i)] = (Real)lg[i];
+  for (int i = 0; i < QS; ++i) lam[own_addr<QT>(b, Q + (inplace_out ? S::opp(i) : i))] = (Real)lg[i];
 }
 
 template <int Q, int QS, typename Real>
 __global__ __launch_bounds__(256) void k_seed(Params<Real> p, const Real* __restrict__ src,
-                                              const double* __restrict__ glob, Real* __restrict__ lam) {
+                                              const double* __restrict__ glob, Real* __restrict__ lam, int pattern,
+                                              int inplace_out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
-  seed_node<Q, QS, Real>(p, src, glob, lam, x, blockIdx.y, blockIdx.z);
+  seed_node<Q, QS, Real>(p, src, glob, lam, x, blockIdx.y, blockIdx.z, pattern, inplace_out);
 }
 
 // ------------------------------------------------------------ adjoint step
@@ -1151,23 +1155,17 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
 // lambda^n(x) = (dW^x/df)^T(f^n(x)) mu(x),  mu_j(x) = lambda^{n+1}_j(x + e_j)
 // grad(x)    += (dW^x/dw)^T mu(x)            (interior nodes only)
 // The vector-Jacobian products below are hand-derived from the operators above.
-template <int Q, int QS, typename Real, bool NT, int V>
+// lam_in and lam_out are the same buffer in place, hence no restrict on them.
+template <int Q, int QS, typename Real, bool NT, int V, int ACC = ACC_PP>
 __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* __restrict__ mom,
-                                             const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
-                                             const Real* __restrict__ w, Real* __restrict__ grad, int x, int y,
-                                             int z) {
-  using L = Lat<Q>;
-  using S = SLat<QS>;
+                                             const Real* lam_in, Real* lam_out, const Real* __restrict__ w,
+                                             Real* __restrict__ grad, int x, int y, int z) {
   constexpr bool is3d = (Q == 19);
   constexpr int QSA = QS > 0 ? QS : 1;
-  constexpr int QT = Q + QS;
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_inode(b);  // workspace node arrays
   Real mu[Q], nu[QSA];
-#pragma unroll
-  for (int j = 0; j < Q; ++j) mu[j] = lam_in[push_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))];
-#pragma unroll
-  for (int i = 0; i < QS; ++i) nu[i] = lam_in[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
+  load_cot<Q, QS, Real, ACC>(lam_in, b, mu, nu);
   const int cls = node_class(p, x, y, z, is3d);
   Real m[Mom<Q, QS, V>::N], lf[Q], lg[QSA], gw;
 #pragma unroll
@@ -1179,10 +1177,7 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
   adjoint_vjp<Q, QS, Real, V>(p, cls, m, wn, mu, nu, lf, lg, gw);
   if (cls == INTERIOR) grad[n] += gw;
-#pragma unroll
-  for (int j = 0; j < Q; ++j) put<NT>(lam_out + own_addr<QT>(b, j), lf[j]);
-#pragma unroll
-  for (int i = 0; i < QS; ++i) put<NT>(lam_out + own_addr<QT>(b, Q + i), lg[i]);
+  store_cot<Q, QS, Real, NT, ACC>(lam_out, b, lf, lg);
 }
 
 template <int Q, int QS, typename Real, bool NT, int V>
@@ -1192,6 +1187,15 @@ __global__ __launch_bounds__(256) void k_adjoint(Params<Real> p, const Real* __r
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
   adjoint_node<Q, QS, Real, NT, V>(p, mom, lam_in, lam_out, w, grad, x, blockIdx.y, blockIdx.z);
+}
+
+// One in-place adjoint step (even or odd phase of the cotangent buffer l).
+template <int Q, int QS, typename Real, bool NT, int V, int ACC>
+__global__ __launch_bounds__(256) void k_adjoint_inplace(Params<Real> p, const Real* __restrict__ mom, Real* l,
+                                                         const Real* __restrict__ w, Real* __restrict__ grad) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  adjoint_node<Q, QS, Real, NT, V, ACC>(p, mom, l, l, w, grad, x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------ inspection kernels

@@ -156,7 +156,8 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
   if (c->tau_s_solid != 0.0 && !(c->tau_s_solid > 0.5)) return bad("tau_s_solid must be 0 or exceed 1/2");
   if (c->inplace != 0 && c->inplace != 1) return bad("inplace must be 0 or 1");
   if (c->reserved3 != 0) return bad("reserved3 must be 0");
-  if (c->inplace && c->nsteps != 0) return bad("in-place contexts do not record: nsteps must be 0");
+  if (c->inplace && c->nsteps > 0 && c->checkpoint_interval > 0 && c->checkpoint_interval < c->nsteps)
+    return bad("an in-place context records the moments of every step: checkpoint_interval must be 0 or >= nsteps");
   if (c->inlet == LBM_INLET_PRESSURE && !(c->rho_in > 0.0 && c->u_cap >= 0.0 && c->u_cap < 1.0))
     return bad("pressure inlet needs rho_in > 0 and 0 <= u_cap < 1");
   if (c->nsteps < 0 || c->checkpoint_interval < 0) return bad("nsteps and checkpoint_interval must be >= 0");
@@ -196,11 +197,17 @@ lbm_status make_plan(const lbm_config* c, Plan* p, std::string* why) {
   p->mom_bytes = align_up((uint64_t)mom_values(c) * p->Np * p->rs);
   p->node_bytes = align_up((uint64_t)p->Np * p->rs);
   if (c->inplace) {
-    // the state (kept in the first checkpoint slot) and the adjoint state, nothing else
+    // the state (kept in the first checkpoint slot), the adjoint state and, for a
+    // recorded run, the moments of every step (the adjoint then never needs a state)
     p->inplace = true;
-    p->C = 0;
+    p->C = c->nsteps;
     p->S = 1;
-    p->total = 2 * p->node_bytes + align_up(kGlobBytes) + align_up(kDescBytes) + 2 * p->state_bytes;
+    p->total = 2 * p->node_bytes + align_up(kGlobBytes) + align_up(kDescBytes) + 2 * p->state_bytes +
+               (uint64_t)p->C * p->mom_bytes;
+    if (c->hbm_budget_bytes && p->total > c->hbm_budget_bytes) {
+      if (why) *why = "the moments of every step do not fit hbm_budget_bytes";
+      return LBM_ENOMEM;
+    }
     return LBM_OK;
   }
   const int64_t Nst = std::max<int64_t>(c->nsteps, 1);
@@ -325,23 +332,53 @@ struct Ops {
   static bool nt(lbm_ctx* c) { return (c->plan.inplace ? 1 : 2) * c->plan.state_bytes > kLastLevelCacheBytes; }
   // access pattern of the current state buffer: ping-pong, or the in-place phase of step t
   static int acc(lbm_ctx* c) { return c->plan.inplace ? ((c->t % 2 == 0) ? ACC_EVEN : ACC_ODD) : ACC_PP; }
-  // One in-place step from the current phase.
-  static void primal_inplace(lbm_ctx* c) {
+  // One in-place step from the current phase; records the moments when mom != null.
+  static void primal_inplace(lbm_ctx* c, void* mom) {
     Geo g = node_geometry(c->cfg);
     Real* a = (Real*)c->cur;
     const Real* w = (const Real*)c->w;
+    Real* m = (Real*)mom;
     const bool even = (c->t % 2 == 0);
+#define LBM_PI(NTV, MOMV, ACCV) \
+  hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), a, w, m)
     if (nt(c)) {
-      if (even)
-        hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, true, V, ACC_EVEN>), g.grid, g.block, 0, c->stream, P(c), a, w);
-      else
-        hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, true, V, ACC_ODD>), g.grid, g.block, 0, c->stream, P(c), a, w);
+      if (m) {
+        if (even) LBM_PI(true, true, ACC_EVEN);
+        else LBM_PI(true, true, ACC_ODD);
+      } else {
+        if (even) LBM_PI(true, false, ACC_EVEN);
+        else LBM_PI(true, false, ACC_ODD);
+      }
     } else {
-      if (even)
-        hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, false, V, ACC_EVEN>), g.grid, g.block, 0, c->stream, P(c), a, w);
-      else
-        hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, false, V, ACC_ODD>), g.grid, g.block, 0, c->stream, P(c), a, w);
+      if (m) {
+        if (even) LBM_PI(false, true, ACC_EVEN);
+        else LBM_PI(false, true, ACC_ODD);
+      } else {
+        if (even) LBM_PI(false, false, ACC_EVEN);
+        else LBM_PI(false, false, ACC_ODD);
+      }
     }
+#undef LBM_PI
+  }
+  // One in-place adjoint step: the cotangent buffer is in the odd-phase layout
+  // after an even number of adjoint steps (the seed writes that layout).
+  static void adjoint_inplace(lbm_ctx* c, const void* mom, int64_t steps_done) {
+    Geo g = node_geometry(c->cfg);
+    const Real* m = (const Real*)mom;
+    Real* l = (Real*)c->lam[0];
+    const Real* w = (const Real*)c->w;
+    Real* gr = (Real*)c->grad;
+    const bool odd = (steps_done % 2 == 0);
+#define LBM_AI(NTV, ACCV) \
+  hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, NTV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), m, l, w, gr)
+    if (nt(c)) {
+      if (odd) LBM_AI(true, ACC_ODD);
+      else LBM_AI(true, ACC_EVEN);
+    } else {
+      if (odd) LBM_AI(false, ACC_ODD);
+      else LBM_AI(false, ACC_EVEN);
+    }
+#undef LBM_AI
   }
   static void oneshot_inplace(lbm_ctx* c, double zeta, double pen) {
     Geo g = node_geometry(c->cfg);
@@ -405,7 +442,7 @@ struct Ops {
   static void seed(lbm_ctx* c, const void* src, void* lam) {
     Geo g = node_geometry(c->cfg);
     hipLaunchKernelGGL((k_seed<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
-                       (const double*)c->glob, (Real*)lam);
+                       (const double*)c->glob, (Real*)lam, acc(c), c->plan.inplace ? 1 : 0);
   }
   static void adjoint(lbm_ctx* c, const void* mom, const void* lin, void* lout) {
     Geo g = node_geometry(c->cfg);
@@ -428,10 +465,10 @@ struct Ops {
                          (Real*)dst, (const Real*)lin, (Real*)lout, (Real*)c->w, (Real*)c->grad,
                          (const double*)c->glob, (Real)zeta, (Real)pen);
   }
-  static void get_adjoint(lbm_ctx* c, const void* lam, double* lf, double* lg) {
+  static void get_adjoint(lbm_ctx* c, const void* lam, double* lf, double* lg, int pattern) {
     Geo g = node_geometry(c->cfg);
     hipLaunchKernelGGL((k_get_adjoint<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)lam, lf, lg,
-                       acc(c));
+                       pattern);
   }
   static void fields(lbm_ctx* c, const void* src, double* rho, double* u, double* s) {
     Geo g = node_geometry(c->cfg);
@@ -513,7 +550,7 @@ struct RunPrimal {
   static lbm_status run(lbm_ctx* c, int64_t nsteps, int record) {
     if (c->plan.inplace) {
       for (int64_t i = 0; i < nsteps; ++i) {
-        O::primal_inplace(c);
+        O::primal_inplace(c, record ? mom_slot(c, c->t) : nullptr);
         ++c->t;
       }
       return launch_check(c, "in-place primal step");
@@ -574,6 +611,14 @@ struct RunAdjoint {
   static lbm_status run(lbm_ctx* c, int64_t nsteps) {
     const int64_t C = c->plan.C;
     if (!c->adj_started) start_adjoint<O>(c);
+    if (c->plan.inplace) {  // every step's moments are held: no recompute
+      for (int64_t i = 0; i < nsteps; ++i) {
+        const int64_t n = c->t_adj - 1;
+        O::adjoint_inplace(c, mom_slot(c, n), c->rec_len - c->t_adj);
+        --c->t_adj;
+      }
+      return launch_check(c, "in-place adjoint step");
+    }
     for (int64_t i = 0; i < nsteps; ++i) {
       const int64_t n = c->t_adj - 1;
       const int64_t s = n / C;
@@ -629,7 +674,10 @@ struct RunGetState {
 template <class O>
 struct RunGetAdjoint {
   static lbm_status run(lbm_ctx* c, double* lf, double* lg) {
-    O::get_adjoint(c, c->lam[c->lam_cur], lf, c->plan.QS ? lg : nullptr);
+    int pattern = O::acc(c);  // one-shot: the primal's phase
+    if (c->plan.inplace && c->adj_started)
+      pattern = ((c->rec_len - c->t_adj) % 2 == 0) ? ACC_ODD : ACC_EVEN;
+    O::get_adjoint(c, c->lam[c->lam_cur], lf, c->plan.QS ? lg : nullptr, pattern);
     return launch_check(c, "get_adjoint");
   }
 };
@@ -946,7 +994,8 @@ lbm_status lbm_primal_steps(lbm_ctx* c, int64_t nsteps, int32_t record) {
   if (!c->design_set) return fail(c, LBM_ESTATE, "primal_steps: no design field set");
   if (c->adj_started) return fail(c, LBM_ESTATE, "primal_steps: adjoint started; call lbm_reset first");
   if (record && c->os_active) return fail(c, LBM_ESTATE, "primal_steps: one-shot running; call lbm_reset first");
-  if (record && c->plan.inplace) return fail(c, LBM_ESTATE, "primal_steps: an in-place context does not record");
+  if (record && c->plan.inplace && c->cfg.nsteps == 0)
+    return fail(c, LBM_ESTATE, "primal_steps: an in-place context with no horizon does not record");
   if (record) {
     if (!(c->rec_open && c->t == c->rec_len))
       return fail(c, LBM_ESTATE, "primal_steps: recording must start at t = 0 or continue a recorded run");
@@ -990,7 +1039,8 @@ lbm_status lbm_adjoint_steps(lbm_ctx* c, int64_t nsteps) {
   if (!c) return LBM_EINVAL;
   if (nsteps < 0) return fail(c, LBM_EINVAL, "adjoint_steps: negative count");
   if (c->os_active) return fail(c, LBM_ESTATE, "adjoint_steps: one-shot running; call lbm_reset first");
-  if (c->plan.inplace) return fail(c, LBM_ESTATE, "adjoint_steps: an in-place context keeps no trajectory");
+  if (c->plan.inplace && c->cfg.nsteps == 0)
+    return fail(c, LBM_ESTATE, "adjoint_steps: an in-place context with no horizon keeps no trajectory");
   if (!c->adj_started) {
     if (!c->design_set) return fail(c, LBM_ESTATE, "adjoint_steps: no design field set");
     if (!(c->rec_open && c->t == c->rec_len))
