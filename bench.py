@@ -39,6 +39,7 @@ COUNTER_TRAFFIC = {
     "k_primal": 718947969,
     "k_adjoint": 751705747,
     "k_oneshot": 1324596593,
+    "k_primal_inplace": None,
 }
 _COUNTER_SOURCES = ("paper_1501_04741_amd/csrc/kernels.hpp", "paper_1501_04741_amd/csrc/lattice.hpp",
                     "paper_1501_04741_amd/build.py")
@@ -55,7 +56,7 @@ def sources_sha():
 def _measured_traffic(workload, kernel):
     if sources_sha() != COUNTER_TRAFFIC["sources_sha256_16"] or workload != COUNTER_TRAFFIC["workload"]:
         return None
-    return COUNTER_TRAFFIC[kernel]
+    return COUNTER_TRAFFIC.get(kernel)
 
 
 def _class_counts(p):
@@ -160,18 +161,22 @@ def mixer_leg(dev, steps=4000, os_iters=400):
             "note": "two primal states (234 MB) fit the 256 MB last-level cache; the one-shot's four do not"}
 
 
-def mrt_leg(dev, steps=200):
-    """Recorded primal and adjoint launches of the 256x128x128 D3Q19 channel with
-    the forced MRT interior collision (d'Humieres rates), FP32, all moments held."""
+def mrt_leg(dev, steps=200, collision="mrt", inplace=True):
+    """Recorded primal and adjoint launches of the 256x128x128 D3Q19 channel,
+    FP32, all moments held: with the forced MRT interior collision (d'Humieres
+    rates), or with BGK and ping-pong buffers for comparison."""
     import torch
 
     from paper_1501_04741_amd import inputs
     from paper_1501_04741_amd.lbm import Lbm
 
     wl = inputs.workload("d3q19_channel_256x128x128")
-    p = dict(inputs.model_params(wl), collision="mrt")
+    p = dict(inputs.model_params(wl), collision=collision)
     w = torch.from_numpy(inputs.design_for(wl)).to(dev)
-    L = Lbm(p, nsteps=steps, precision="fp32", checkpoint_interval=steps, device=dev)
+    if inplace:
+        L = Lbm(p, nsteps=steps, precision="fp32", device=dev, inplace=True)
+    else:
+        L = Lbm(p, nsteps=steps, precision="fp32", checkpoint_interval=steps, device=dev)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     for rep_ in range(2):  # the second pass is timed
         L.set_design(w)
@@ -191,9 +196,15 @@ def mrt_leg(dev, steps=200):
     nodes = p["nx"] * p["ny"] * p["nz"]
     roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
-    return {"workload": "d3q19_channel_256x128x128 with MRT collision", "steps_timed": steps,
-            "primal": {"kernel": "k_primal<19,0,float,MRT>", "mlups": nodes / prim_us, "roofline": roof(pb, prim_us)},
-            "adjoint": {"kernel": "k_adjoint<19,0,float,MRT>", "mlups": nodes / adj_us, "roofline": roof(ab, adj_us)}}
+    sfx = "_inplace" if inplace else ""
+    tag = ",MRT" if collision == "mrt" else ""
+    return {"workload": "d3q19_channel_256x128x128, %s collision, %s" % (collision.upper(),
+                                                                        "in place" if inplace else "ping-pong"),
+            "steps_timed": steps,
+            "primal": {"kernel": "k_primal%s<19,0,float%s>" % (sfx, tag), "mlups": nodes / prim_us,
+                       "roofline": roof(pb, prim_us)},
+            "adjoint": {"kernel": "k_adjoint%s<19,0,float%s>" % (sfx, tag), "mlups": nodes / adj_us,
+                        "roofline": roof(ab, adj_us)}}
 
 
 def inplace_leg(dev, steps=200):
@@ -325,7 +336,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="d3q19_channel_256x128x128")
     ap.add_argument("--lbm-steps", type=int, default=None, help="override the primal horizon N")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixer", action="store_true", help="skip the mixing-duct, MRT and in-place legs")
+    ap.add_argument("--no-mixer", action="store_true", help="skip the mixing-duct, MRT, in-place and ping-pong legs")
+    ap.add_argument("--ping-pong", action="store_true", help="run the main evaluation with ping-pong buffers")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run one device copy of MB megabytes (counter calibration for profiles)")
@@ -370,8 +382,18 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     budget = int(wl.get("hbm_budget_gb", 0) * 2**30)
-    L = Lbm(p, nsteps=N, precision=prec, checkpoint_interval=wl.get("checkpoint_interval", 0),
-            hbm_budget_bytes=budget, device=dev)
+    # in place (one primal buffer streamed in place, every step's moments held, the adjoint
+    # ping-ponging) when that fits the budget and the workload asks for no checkpoints; else the
+    # ping-pong plan
+    inplace = not args.ping_pong and wl.get("checkpoint_interval", 0) in (0, N)
+    if inplace:
+        try:
+            L = Lbm(p, nsteps=N, precision=prec, hbm_budget_bytes=budget, device=dev, inplace=True)
+        except Exception:
+            inplace = False
+    if not inplace:
+        L = Lbm(p, nsteps=N, precision=prec, checkpoint_interval=wl.get("checkpoint_interval", 0),
+                hbm_budget_bytes=budget, device=dev)
     plan = L.plan()
     C = plan["interval"]
     k_last = N - ((N - 1) // C) * C  # adjoint steps of the last segment (moments held, no recompute)
@@ -438,6 +460,8 @@ def main(argv=None):
 
     nodes = L.N
     pb, ab = algorithmic_bytes(p, prec)
+    kname = lambda k: "%s%s<%d,%d,%s>" % (k, "_inplace" if inplace else "", p["flow"], p.get("scalar", 0),
+                                           "float" if prec == "fp32" else "double")
     ob = oneshot_bytes(p, prec)
     os_gbs = ob / (os_launch_ms * 1e-3) / 1e9
     prim_gbs = pb / (primal_launch_ms * 1e-3) / 1e9
@@ -458,6 +482,7 @@ def main(argv=None):
         "config": {"workload": args.workload, "lattice": "D3Q19" if p["flow"] == 19 else "D2Q9",
                    "scalar": p.get("scalar", 0), "grid": [p["nx"], p["ny"], p["nz"]], "nodes": nodes,
                    "lbm_steps": N, "precision": prec, "checkpoint_interval": C,
+                   "streaming": "in place" if inplace else "ping-pong",
                    "checkpoints": plan["checkpoints"], "moment_sets": plan["moment_sets"],
                    "workspace_gb": round(L.workspace_bytes / 1e9, 3), "switch": "%s(%g)" % (p["switch_fn"],
                                                                                           p["switch_param"])},
@@ -470,11 +495,11 @@ def main(argv=None):
         "backward_mlups": nodes * N / (bwd_ms * 1e-3) / 1e6,
         "forward_ms": fwd_ms,
         "backward_ms": bwd_ms,
-        "roofline": {"bound": "hbm", "kernel": "k_primal<19,0,float>", "achieved": prim_gbs, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": kname("k_primal"), "achieved": prim_gbs, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": prim_gbs / HBM_PEAK_GBS,
-                     "traffic": _measured_traffic(args.workload, "k_primal"),
+                     "traffic": _measured_traffic(args.workload, kname("k_primal").split("<")[0]),
                      "bytes_per_launch": pb, "avg_launch_us": primal_launch_ms * 1e3},
-        "roofline_adjoint": {"bound": "hbm", "kernel": "k_adjoint<19,0,float>", "achieved": adj_gbs,
+        "roofline_adjoint": {"bound": "hbm", "kernel": kname("k_adjoint").replace("_inplace", ""), "achieved": adj_gbs,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": (adj_gbs / HBM_PEAK_GBS) if adj_gbs else None,
                              "traffic": _measured_traffic(args.workload, "k_adjoint"),
@@ -494,6 +519,8 @@ def main(argv=None):
         rec["mrt"] = mrt_leg(dev)
         print("[bench] in-place leg", file=sys.stderr, flush=True)
         rec["inplace"] = inplace_leg(dev)
+        print("[bench] ping-pong leg", file=sys.stderr, flush=True)
+        rec["ping_pong"] = mrt_leg(dev, collision="bgk", inplace=False)
     if not args.no_cpu_baseline:
         print("[bench] GPU timing done; timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(p, w_np.astype(np.float64), args.cpu_steps)

@@ -146,10 +146,10 @@ def test_inplace_refuses_recording_adjoint_and_batches():
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("name,p", CASES, ids=[c[0] for c in CASES])
 def test_inplace_recorded_run_and_adjoint_bitwise_equal_pingpong(name, p, prec):
-    """A recorded in-place run (moments of every step, one primal and one
-    adjoint buffer) against the ping-pong store-all plan: states after every
-    forward chunk, J, the adjoint state after every backward chunk and the
-    gradient are bitwise equal."""
+    """A recorded in-place run (moments of every step, one primal buffer, the
+    adjoint ping-ponging) against the ping-pong store-all plan: states after
+    every forward chunk, J, the adjoint state after every backward chunk and
+    the gradient are bitwise equal."""
     steps = 23
     dt = np.float32 if prec == "fp32" else np.float64
     w = torch.from_numpy(inputs.porosity(p["nx"], p["ny"], p["nz"], 2, 3, dt))
