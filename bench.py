@@ -34,12 +34,12 @@ HBM_PEAK_GBS = 8000.0
 # and compile flags whose SHA-256 prefix is given (kernels.hpp, lattice.hpp, build.py in that
 # order) and are reported only while those files still match.
 COUNTER_TRAFFIC = {
-    "sources_sha256_16": "201fc1d907dbe9b9",
+    "sources_sha256_16": "1b0b025a180b6482",
     "workload": "d3q19_channel_256x128x128",
     "k_primal": None,
-    "k_adjoint": 751710956,
-    "k_oneshot": 1324874060,
-    "k_primal_inplace": 734766190,
+    "k_adjoint": 751471078,
+    "k_oneshot": 1324613915,
+    "k_primal_inplace": 734921738,
 }
 _COUNTER_SOURCES = ("paper_1501_04741_amd/csrc/kernels.hpp", "paper_1501_04741_amd/csrc/lattice.hpp",
                     "paper_1501_04741_amd/build.py")
@@ -495,10 +495,11 @@ def main(argv=None):
         "backward_mlups": nodes * N / (bwd_ms * 1e-3) / 1e6,
         "forward_ms": fwd_ms,
         "backward_ms": bwd_ms,
-        "roofline": {"bound": "hbm", "kernel": kname("k_primal"), "achieved": prim_gbs, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": prim_gbs / HBM_PEAK_GBS,
-                     "traffic": _measured_traffic(args.workload, kname("k_primal").split("<")[0]),
-                     "bytes_per_launch": pb, "avg_launch_us": primal_launch_ms * 1e3},
+        "roofline": None,  # the dominant kernel's, filled in below
+        "roofline_primal": {"bound": "hbm", "kernel": kname("k_primal"), "achieved": prim_gbs,
+                            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": prim_gbs / HBM_PEAK_GBS,
+                            "traffic": _measured_traffic(args.workload, kname("k_primal").split("<")[0]),
+                            "bytes_per_launch": pb, "avg_launch_us": primal_launch_ms * 1e3},
         "roofline_adjoint": {"bound": "hbm", "kernel": kname("k_adjoint").replace("_inplace", ""), "achieved": adj_gbs,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": (adj_gbs / HBM_PEAK_GBS) if adj_gbs else None,
@@ -512,6 +513,10 @@ def main(argv=None):
                                  "traffic": _measured_traffic(args.workload, "k_oneshot"), "bytes_per_launch": ob,
                                  "avg_launch_us": os_launch_ms * 1e3}},
     }
+    # the dominant kernel is the one with more time in an evaluation: N primal launches against
+    # N adjoint launches
+    adj_dominant = k_last > 1 and adjoint_launch_ms > primal_launch_ms
+    rec["roofline"] = dict(rec["roofline_adjoint" if adj_dominant else "roofline_primal"])
     if not args.no_mixer:
         print("[bench] mixing duct leg", file=sys.stderr, flush=True)
         rec["mixer"] = mixer_leg(dev)

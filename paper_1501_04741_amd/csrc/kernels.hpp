@@ -134,6 +134,26 @@ __device__ __forceinline__ void put(Real* p, Real v) {
     *p = v;
   }
 }
+// Streaming loads, for the cotangent populations: each is read once per step.
+// Only accesses that are not shifted along x take the hint.  A load shifted by
+// one site spans one cache line more than its wave's 256 bytes, and that line is
+// also read by the neighbouring wave; without the hint the second read hits the
+// L2, with it the line is fetched from HBM twice.  Measured on the 256x128x128
+// D3Q19 FP32 channel: adjoint 0.743 of peak without hints, 0.761 with every
+// cotangent load hinted (HBM traffic 1.065x the algorithmic bytes), 0.792 with
+// the unshifted ones only.  The hint on the primal state or the recorded
+// moments gains nothing (unshifted) or loses (shifted).  The hint is a template
+// argument and the shifted and unshifted loads sit in separate loops: a run-time
+// flag, even one that folds to a constant after unrolling, lets the compiler
+// merge the hinted and plain load of the same address and drop the hint.
+template <bool NT, typename Real>
+__device__ __forceinline__ Real get(const Real* p) {
+  if constexpr (NT) {
+    return __builtin_nontemporal_load(p);
+  } else {
+    return *p;
+  }
+}
 
 template <typename Real, typename P>
 __device__ __forceinline__ Real inlet_value(const P& p, int y, int z) {
@@ -191,18 +211,6 @@ __device__ __forceinline__ void switch_fn(const Params<Real>& p, Real w, Real& G
 }
 
 // ------------------------------------------------------------------ loads
-template <int Q, int QS, typename Real>
-__device__ __forceinline__ void pull_state(const Real* __restrict__ src, const Nbr& b, Real (&f)[Q],
-                                           Real (&g)[QS > 0 ? QS : 1]) {
-  using L = Lat<Q>;
-  using S = SLat<QS>;
-  constexpr int QT = Q + QS;
-#pragma unroll
-  for (int j = 0; j < Q; ++j) f[j] = src[pull_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))];
-#pragma unroll
-  for (int i = 0; i < QS; ++i) g[i] = src[pull_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
-}
-
 // In-place streaming (one buffer per state, the "AA" access pattern).  The
 // ping-pong form (ACC_PP) keeps post-collision states and pulls.  In place, a
 // buffer alternates between two phases: after an even number of steps slot j
@@ -271,26 +279,42 @@ __device__ __forceinline__ void store_state(Real* a, const Nbr& b, const Real (&
 
 // Cotangent of the post-collision populations, mu_j(x) = lambda_j(x + e_j),
 // and the store of the new lambda(x), for the three access patterns.
-template <int Q, int QS, typename Real, int ACC>
+template <int Q, int QS, typename Real, int ACC, bool NT>
 __device__ __forceinline__ void load_cot(const Real* a, const Nbr& b, Real (&mu)[Q], Real (&nu)[QS > 0 ? QS : 1]) {
   using L = Lat<Q>;
   using S = SLat<QS>;
   constexpr int QT = Q + QS;
   if constexpr (ACC == ACC_PP) {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) mu[j] = a[push_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))];
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) == 0) mu[j] = get<NT>(a + push_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j)));
 #pragma unroll
-    for (int i = 0; i < QS; ++i) nu[i] = a[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) != 0) mu[j] = a[push_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))];
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (S::ex(i) == 0) nu[i] = get<NT>(a + push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i)));
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (S::ex(i) != 0) nu[i] = a[push_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
   } else if constexpr (ACC == ACC_EVEN) {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) mu[j] = a[own_addr<QT>(b, j)];
+    for (int j = 0; j < Q; ++j) mu[j] = get<NT>(a + own_addr<QT>(b, j));
 #pragma unroll
-    for (int i = 0; i < QS; ++i) nu[i] = a[own_addr<QT>(b, Q + i)];
+    for (int i = 0; i < QS; ++i) nu[i] = get<NT>(a + own_addr<QT>(b, Q + i));
   } else {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) mu[j] = a[push_addr<QT>(b, L::opp(j), L::ex(j), L::ey(j), L::ez(j))];
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) == 0) mu[j] = get<NT>(a + push_addr<QT>(b, L::opp(j), L::ex(j), L::ey(j), L::ez(j)));
 #pragma unroll
-    for (int i = 0; i < QS; ++i) nu[i] = a[push_addr<QT>(b, Q + S::opp(i), S::ex(i), S::ey(i), S::ez(i))];
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) != 0) mu[j] = a[push_addr<QT>(b, L::opp(j), L::ex(j), L::ey(j), L::ez(j))];
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (S::ex(i) == 0) nu[i] = get<NT>(a + push_addr<QT>(b, Q + S::opp(i), S::ex(i), S::ey(i), S::ez(i)));
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (S::ex(i) != 0) nu[i] = a[push_addr<QT>(b, Q + S::opp(i), S::ex(i), S::ey(i), S::ez(i))];
   }
 }
 
@@ -1178,7 +1202,7 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_inode(b);  // workspace node arrays
   Real mu[Q], nu[QSA];
-  load_cot<Q, QS, Real, ACC_PP>(lam_in, b, mu, nu);
+  load_cot<Q, QS, Real, ACC_PP, NT>(lam_in, b, mu, nu);
   const int cls = node_class(p, x, y, z, is3d);
   Real m[Mom<Q, QS, V>::N], lf[Q], lg[QSA], gw;
 #pragma unroll
@@ -1394,7 +1418,7 @@ __device__ __forceinline__ void oneshot_node(const Params<Real>& p, const Real* 
   const int cls = node_class(p, x, y, z, is3d);
   Real f[Q], g[QSA], mu[Q], nu[QSA];
   load_state<Q, QS, Real, ACC>(prim_in, b, f, g);
-  load_cot<Q, QS, Real, ACC>(lam_in, b, mu, nu);
+  load_cot<Q, QS, Real, ACC, NT>(lam_in, b, mu, nu);
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
   Real m[Mom<Q, QS, V>::N], lf[Q], lg[QSA], gw;
   node_moments<Q, QS, Real, V>(p, cls, y, z, f, g, m);
