@@ -375,7 +375,7 @@ class GpuExecutor(Executor):
 
     max_batch = 32
 
-    def __init__(self, device=None, per_request_cap_bytes: int = 16 << 30, arena_bytes: Optional[int] = None):
+    def __init__(self, device=None, per_request_cap_bytes: int = 64 << 30, arena_bytes: Optional[int] = None):
         import torch
 
         from . import lbm as _lbm
@@ -389,11 +389,12 @@ class GpuExecutor(Executor):
     def _plan_bytes(self, job: Job) -> int:
         """Workspace for the request: store-all (no recompute) when it fits the
         per-request cap, otherwise the largest checkpoint interval that fits,
-        never less than the sqrt(N) plan."""
+        never less than the sqrt(N) plan.  Sets job._store_all."""
         L = self.lbm
         sqrt_b = L.lbm_required_bytes(L.make_config(job.params, job.steps, job.precision))
         all_b = L.lbm_required_bytes(L.make_config(job.params, job.steps, job.precision,
                                                    checkpoint_interval=max(job.steps, 1)))
+        job._store_all = all_b <= self.cap
         return max(sqrt_b, min(all_b, self.cap))
 
     def footprint(self, job: Job) -> int:
@@ -412,8 +413,12 @@ class GpuExecutor(Executor):
         return (p["flow"] + p.get("scalar", 0)) * p["nx"] * p["ny"] * p["nz"] * s
 
     def estimate(self, job: Job) -> float:
-        # forward (2 states/step) + recompute (2) + adjoint (3) at ~5.5 TB/s, plus launch overhead
-        return job.steps * (7.0 * self.step_bytes(job) / 5.5e12 + 3 * 6e-6)
+        # forward (2 states/step) + adjoint (2) + recorded moments and design (~1), plus a recompute
+        # (2) unless every step's moments are held, at ~5.5 TB/s, plus launch overhead
+        if not hasattr(job, "_store_all"):
+            self._plan_bytes(job)
+        passes = 5.0 if job._store_all else 7.0
+        return job.steps * (passes * self.step_bytes(job) / 5.5e12 + 3 * 6e-6)
 
     def open(self, job: Job):
         torch = self.torch
@@ -495,15 +500,17 @@ class GpuExecutor(Executor):
         mark.synchronize()
 
 
-def run_one_at_a_time(jobs: List[Job], device=None, clock=time.perf_counter):
+def run_one_at_a_time(jobs: List[Job], device=None, clock=time.perf_counter,
+                      per_request_cap_bytes: int = 64 << 30):
     """Baseline: the same trace on the same GPU, one request at a time in
     arrival order (FIFO), no overlap: each request is created, runs its full
     primal, objective, adjoint and gradient with single-context launches,
-    and is read back before the next one starts."""
+    and is read back before the next one starts.  Each request gets the same
+    checkpoint plan as in the server (same per-request cap)."""
     import torch
 
     from .lbm import Lbm
-    ex = GpuExecutor(device)
+    ex = GpuExecutor(device, per_request_cap_bytes=per_request_cap_bytes)
     t0 = clock()
     out = []
     for job in sorted(jobs, key=lambda j: j.arrival):
