@@ -1,8 +1,9 @@
 """The primal/adjoint pair as a ``torch.autograd.Function``.
 
-forward(w)   -> J: records N primal steps of the library (checkpoints every C
-                steps plus a ring of C - 1 states, sized to the workspace) and
-                evaluates the objective on the device (no host sync).
+forward(w)   -> J: records N primal steps of the library (full states every C
+                steps and the moments the adjoint reads for C steps, C sized to
+                the workspace budget) and evaluates the objective on the device
+                (no host sync).
 backward(gJ) -> gJ * dJ/dw: the hand-written adjoint kernel, run N reverse
                 steps with segment recomputes from the checkpoints
                 (theorem of Section 2.2, unsteady form), then the gradient.
