@@ -336,8 +336,9 @@ struct Ops {
     hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V>), dim3(blocks), dim3(kBatchBX), 0, st, A);
   }
 
-  // streaming stores when the states a step touches exceed the last-level cache
-  static bool nt(lbm_ctx* c) { return (c->plan.inplace ? 1 : 2) * c->plan.state_bytes > kLastLevelCacheBytes; }
+  // streaming stores (and cotangent loads) when the state buffers a launch touches exceed the
+  // last-level cache: ping-pong primal and adjoint 2, in-place primal 1, one-shot 4 (2 in place)
+  static bool nt(lbm_ctx* c, int buffers) { return buffers * c->plan.state_bytes > kLastLevelCacheBytes; }
   // access pattern of the current state buffer: ping-pong, or the in-place phase of step t
   static int acc(lbm_ctx* c) { return c->plan.inplace ? ((c->t % 2 == 0) ? ACC_EVEN : ACC_ODD) : ACC_PP; }
   // One in-place step from the current phase; records the moments when mom != null.
@@ -353,7 +354,7 @@ struct Ops {
     const bool even = (c->t % 2 == 0);
 #define LBM_PI(NTV, MOMV, ACCV) \
   hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), a, w, m)
-    if (m && nt(c)) {
+    if (m && nt(c, 1)) {
       if (even) LBM_PI(true, true, ACC_EVEN);
       else LBM_PI(true, true, ACC_ODD);
     } else if (m) {
@@ -376,7 +377,7 @@ struct Ops {
 #define LBM_OS_INPLACE(NTV, ACCV)                                                                         \
   hipLaunchKernelGGL((k_oneshot_inplace<Q, QS, Real, NTV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), a, l, w, gr, \
                      gl, (Real)zeta, (Real)pen)
-    if (nt(c)) {
+    if (nt(c, 2)) {
       if (even) LBM_OS_INPLACE(true, ACC_EVEN);
       else LBM_OS_INPLACE(true, ACC_ODD);
     } else {
@@ -392,7 +393,7 @@ struct Ops {
     h.w = (const Real*)c->w;
     h.grad = (Real*)c->grad;
     h.gx = (c->cfg.nx + kBatchBX - 1) / kBatchBX;
-    h.nt = nt(c) ? 1 : 0;
+    h.nt = nt(c, 2) ? 1 : 0;
     hipLaunchKernelGGL((k_write_desc<Real>), dim3(1), dim3(64), 0, c->stream, h, (BatchStatic<Real>*)c->desc);
     return launch_check(c, "descriptor upload");
   }
@@ -405,7 +406,7 @@ struct Ops {
     Real* d = (Real*)dst;
     const Real* w = (const Real*)c->w;
     Real* m = (Real*)mom;
-    if (nt(c)) {
+    if (nt(c, 2)) {
       if (m)
         hipLaunchKernelGGL((k_primal<Q, QS, Real, true, true, V>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
       else
@@ -431,7 +432,7 @@ struct Ops {
   }
   static void adjoint(lbm_ctx* c, const void* mom, const void* lin, void* lout) {
     Geo g = node_geometry(c->cfg);
-    if (nt(c))
+    if (nt(c, 2))
       hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true, V>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
                          (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
     else
@@ -441,7 +442,7 @@ struct Ops {
   static void oneshot(lbm_ctx* c, const void* src, void* dst, const void* lin, void* lout, double zeta,
                       double pen) {
     Geo g = node_geometry(c->cfg);
-    if (nt(c))
+    if (nt(c, 4))
       hipLaunchKernelGGL((k_oneshot<Q, QS, Real, true, V>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
                          (Real*)dst, (const Real*)lin, (Real*)lout, (Real*)c->w, (Real*)c->grad,
                          (const double*)c->glob, (Real)zeta, (Real)pen);
