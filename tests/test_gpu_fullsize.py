@@ -62,3 +62,59 @@ def test_full_size_steps_match_oracle_operators():
     grad = _np(ctx.gradient())
     assert np.linalg.norm(grad - gsum) <= 1e-3 * np.linalg.norm(gsum)
     ctx.close()
+
+
+def _state(ctx):
+    f, g = ctx.get_state()
+    return _np(f), (None if g is None else _np(g))
+
+
+@pytest.mark.parametrize("name", ["d2q9_d2q5_exchanger_512x256", "d3q19_d3q7_mixer_128x64x64"])
+def test_full_length_run_matches_oracle_operators_and_fp64(name):
+    """The heat-exchanger (512x256 D2Q9+D2Q5, 20000 steps, checkpoint every 500)
+    and mixer (128x64x64 D3Q19+D3Q7, 5000 steps) workloads at full size and full
+    length in FP32, with their own checkpoint plans: the last two primal steps,
+    the objective and the first two adjoint steps against the oracle's single-step
+    operators applied to the GPU's own states and cotangents; then the whole
+    adjoint sweep (segments recomputed from checkpoints) against the same run in
+    FP64, whose arithmetic the small-lattice tests tie to the oracle at 1e-10."""
+    wl = inputs.workload(name)
+    p = inputs.model_params(wl)
+    N, C, tail = wl["steps"], wl["checkpoint_interval"], 2
+    w32 = inputs.design_for(wl)
+    w64 = w32.astype(np.float64)
+    ctx = Lbm(p, nsteps=N, precision="fp32", checkpoint_interval=C)
+    ctx.set_design(torch.from_numpy(w32))
+    ctx.reset()
+    ctx.primal_steps(N - tail, record=True)
+    states = [_state(ctx)]
+    for _ in range(tail):
+        ctx.primal_steps(1, record=True)
+        states.append(_state(ctx))
+    J, _ = ctx.objective()
+    for n in range(tail):
+        rf, rg = oracle.step(p, w64, *states[n])
+        assert np.max(np.abs(states[n + 1][0] - rf)) < 2e-6, n
+        assert np.max(np.abs(states[n + 1][1] - rg)) < 2e-6, n
+    Jr, lf, lg = oracle.objective_seed(p, *states[tail])
+    assert abs(J - Jr) <= 1e-4 * abs(Jr)
+    lam = (lf, lg)
+    for n in reversed(range(tail)):
+        ctx.adjoint_steps(1)
+        gf, gg = ctx.get_adjoint()
+        rf, rg, _ = oracle.step_adjoint(p, w64, *states[n], *lam)
+        scale = max(np.abs(rf).max(), np.abs(rg).max())
+        assert np.max(np.abs(_np(gf) - rf)) <= 1e-4 * scale, n
+        assert np.max(np.abs(_np(gg) - rg)) <= 1e-4 * scale, n
+        lam = (_np(gf), _np(gg))
+    ctx.adjoint_steps(N - tail)
+    grad = _np(ctx.gradient()).astype(np.float64)
+    ctx.close()
+    ref = Lbm(p, nsteps=N, precision="fp64", checkpoint_interval=C)
+    J64, g64 = ref.value_and_grad(torch.from_numpy(w64))
+    g64 = _np(g64)
+    ref.close()
+    err = np.linalg.norm(grad - g64) / np.linalg.norm(g64)
+    print("%s: J %.8g (fp64 %.8g), gradient rel L2 %.3g" % (name, J, J64, err))
+    assert abs(J - J64) <= 1e-4 * abs(J64)
+    assert err <= 1e-3
