@@ -134,15 +134,17 @@ __device__ __forceinline__ void put(Real* p, Real v) {
     *p = v;
   }
 }
-// Streaming loads, for the cotangent populations: each is read once per step.
-// Only accesses that are not shifted along x take the hint.  A load shifted by
+// Streaming loads, for populations read once per step (cotangent, and the primal
+// state in the kernels listed at load_state).  Only accesses that are not shifted
+// along x take the hint.  A load shifted by
 // one site spans one cache line more than its wave's 256 bytes, and that line is
 // also read by the neighbouring wave; without the hint the second read hits the
 // L2, with it the line is fetched from HBM twice.  Measured on the 256x128x128
 // D3Q19 FP32 channel: adjoint 0.743 of peak without hints, 0.761 with every
 // cotangent load hinted (HBM traffic 1.065x the algorithmic bytes), 0.792 with
-// the unshifted ones only.  The hint on the primal state or the recorded
-// moments gains nothing (unshifted) or loses (shifted).  The hint is a template
+// the unshifted ones only.  Hinting shifted loads, or the recorded moments,
+// loses (in-place primal with every load hinted: 0.819 -> 0.657; adjoint with
+// hinted moments: 0.761 -> 0.748).  The hint is a template
 // argument and the shifted and unshifted loads sit in separate loops: a run-time
 // flag, even one that folds to a constant after unrolling, lets the compiler
 // merge the hinted and plain load of the same address and drop the hint.
@@ -222,26 +224,49 @@ __device__ __forceinline__ void switch_fn(const Params<Real>& p, Real w, Real& G
 // way (mu_j(x) = lambda_j(x + e_j)) and mirrors the pattern with e -> -e.
 enum : int { ACC_PP = 0, ACC_EVEN = 1, ACC_ODD = 2 };
 
-template <int Q, int QS, typename Real, int ACC>
+// NT: streaming hint on the loads that are not shifted along x (all of them in
+// the even phase), as for the cotangent.  Which kernels take it was measured on
+// the 256x128x128 D3Q19 FP32 channel: ping-pong primal 0.707 -> 0.728 of peak,
+// ping-pong one-shot 0.739 -> 0.753, in-place one-shot (both phases) 0.707 ->
+// 0.783, recorded in-place primal 0.822 -> 0.837 with the odd phase hinted
+// alone (hinting its even phase too drops it to 0.789).  Unrecorded in-place
+// steps run without streaming hints at all.
+template <int Q, int QS, typename Real, int ACC, bool NT = false>
 __device__ __forceinline__ void load_state(const Real* a, const Nbr& b, Real (&f)[Q], Real (&g)[QS > 0 ? QS : 1]) {
   using L = Lat<Q>;
   using S = SLat<QS>;
   constexpr int QT = Q + QS;
   if constexpr (ACC == ACC_PP) {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) f[j] = a[pull_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))];
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) == 0) f[j] = get<NT>(a + pull_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j)));
 #pragma unroll
-    for (int i = 0; i < QS; ++i) g[i] = a[pull_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) != 0) f[j] = a[pull_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))];
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (S::ex(i) == 0) g[i] = get<NT>(a + pull_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i)));
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (S::ex(i) != 0) g[i] = a[pull_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))];
   } else if constexpr (ACC == ACC_EVEN) {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) f[j] = a[own_addr<QT>(b, j)];
+    for (int j = 0; j < Q; ++j) f[j] = get<NT>(a + own_addr<QT>(b, j));
 #pragma unroll
-    for (int i = 0; i < QS; ++i) g[i] = a[own_addr<QT>(b, Q + i)];
+    for (int i = 0; i < QS; ++i) g[i] = get<NT>(a + own_addr<QT>(b, Q + i));
   } else {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) f[j] = a[pull_addr<QT>(b, L::opp(j), L::ex(j), L::ey(j), L::ez(j))];
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) == 0) f[j] = get<NT>(a + pull_addr<QT>(b, L::opp(j), L::ex(j), L::ey(j), L::ez(j)));
 #pragma unroll
-    for (int i = 0; i < QS; ++i) g[i] = a[pull_addr<QT>(b, Q + S::opp(i), S::ex(i), S::ey(i), S::ez(i))];
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) != 0) f[j] = a[pull_addr<QT>(b, L::opp(j), L::ex(j), L::ey(j), L::ez(j))];
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (S::ex(i) == 0) g[i] = get<NT>(a + pull_addr<QT>(b, Q + S::opp(i), S::ex(i), S::ey(i), S::ez(i)));
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (S::ex(i) != 0) g[i] = a[pull_addr<QT>(b, Q + S::opp(i), S::ex(i), S::ey(i), S::ez(i))];
   }
 }
 
@@ -712,7 +737,7 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* s
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_inode(b);  // workspace node arrays
   Real f[Q], g[QS > 0 ? QS : 1];
-  load_state<Q, QS, Real, ACC>(src, b, f, g);
+  load_state<Q, QS, Real, ACC, NT && ACC != ACC_EVEN>(src, b, f, g);
   const int cls = node_class(p, x, y, z, is3d);
   if constexpr (MOM) {
     if (has_moments(p, cls)) {  // the only classes whose transposes read them
@@ -1432,7 +1457,7 @@ __device__ __forceinline__ void oneshot_node(const Params<Real>& p, const Real* 
   const int n = own_inode(b);  // workspace node arrays
   const int cls = node_class(p, x, y, z, is3d);
   Real f[Q], g[QSA], mu[Q], nu[QSA];
-  load_state<Q, QS, Real, ACC>(prim_in, b, f, g);
+  load_state<Q, QS, Real, ACC, NT>(prim_in, b, f, g);
   load_cot<Q, QS, Real, ACC, NT>(lam_in, b, mu, nu);
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
   Real m[Mom<Q, QS, V>::N], lf[Q], lg[QSA], gw;
