@@ -295,8 +295,14 @@ __device__ __forceinline__ void store_state(Real* a, const Nbr& b, const Real (&
 #pragma unroll
     for (int i = 0; i < QS; ++i) put<NT>(a + own_addr<QT>(bb, Q + S::opp(i)), g[i]);
   } else {
+    // stores shifted along x share their end lines with the neighbouring wave's:
+    // plain stores let the L2 merge the two halves (in-place primal 0.836 -> 0.839)
 #pragma unroll
-    for (int j = 0; j < Q; ++j) put<NT>(a + push_addr<QT>(bb, j, L::ex(j), L::ey(j), L::ez(j)), f[j]);
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) == 0) put<NT>(a + push_addr<QT>(bb, j, L::ex(j), L::ey(j), L::ez(j)), f[j]);
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) != 0) put<false>(a + push_addr<QT>(bb, j, L::ex(j), L::ey(j), L::ez(j)), f[j]);
 #pragma unroll
     for (int i = 0; i < QS; ++i) put<NT>(a + push_addr<QT>(bb, Q + i, S::ex(i), S::ey(i), S::ez(i)), g[i]);
   }
@@ -368,8 +374,13 @@ __device__ __forceinline__ void store_cot(Real* a, const Nbr& b, const Real (&lf
 #pragma unroll
     for (int i = 0; i < QS; ++i) put<NT>(a + own_addr<QT>(bb, Q + S::opp(i)), lg[i]);
   } else {
+    // shifted stores plain, as for the state
 #pragma unroll
-    for (int j = 0; j < Q; ++j) put<NT>(a + pull_addr<QT>(bb, j, L::ex(j), L::ey(j), L::ez(j)), lf[j]);
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) == 0) put<NT>(a + pull_addr<QT>(bb, j, L::ex(j), L::ey(j), L::ez(j)), lf[j]);
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) != 0) put<false>(a + pull_addr<QT>(bb, j, L::ex(j), L::ey(j), L::ez(j)), lf[j]);
 #pragma unroll
     for (int i = 0; i < QS; ++i) put<NT>(a + pull_addr<QT>(bb, Q + i, S::ex(i), S::ey(i), S::ez(i)), lg[i]);
   }
