@@ -270,17 +270,18 @@ __device__ __forceinline__ void load_state(const Real* a, const Nbr& b, Real (&f
   }
 }
 
-template <int Q, int QS, typename Real, bool NT, int ACC, bool HIDE = true>
+template <int Q, int QS, typename Real, bool NT, int ACC>
 __device__ __forceinline__ void store_state(Real* a, const Nbr& b, const Real (&f)[Q], const Real (&g)[QS > 0 ? QS : 1]) {
   using L = Lat<Q>;
   using S = SLat<QS>;
   constexpr int QT = Q + QS;
   // In place the stores hit the addresses the loads used; an empty asm hides the
   // lane index so the compiler recomputes the store addresses instead of keeping
-  // every load address live across the node update (measured: 92 -> 55 VGPRs for
-  // the in-place primal, 177 -> 92 for the in-place one-shot).  It emits no code.
+  // every load address live across the node update (measured: 92 -> 55 VGPRs and
+  // 0.75 -> 0.81 of peak for the in-place primal; 186 -> 92 VGPRs and 0.784 ->
+  // 0.799 for the in-place one-shot).  It emits no code.
   Nbr bb = b;
-  if constexpr (ACC != ACC_PP && HIDE) {
+  if constexpr (ACC != ACC_PP) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) asm volatile("" : "+v"(bb.X[k]));
   }
@@ -349,17 +350,18 @@ __device__ __forceinline__ void load_cot(const Real* a, const Nbr& b, Real (&mu)
   }
 }
 
-template <int Q, int QS, typename Real, bool NT, int ACC, bool HIDE = true>
+template <int Q, int QS, typename Real, bool NT, int ACC>
 __device__ __forceinline__ void store_cot(Real* a, const Nbr& b, const Real (&lf)[Q], const Real (&lg)[QS > 0 ? QS : 1]) {
   using L = Lat<Q>;
   using S = SLat<QS>;
   constexpr int QT = Q + QS;
   // In place the stores hit the addresses the loads used; an empty asm hides the
   // lane index so the compiler recomputes the store addresses instead of keeping
-  // every load address live across the node update (measured: 92 -> 55 VGPRs for
-  // the in-place primal, 177 -> 92 for the in-place one-shot).  It emits no code.
+  // every load address live across the node update (measured: 92 -> 55 VGPRs and
+  // 0.75 -> 0.81 of peak for the in-place primal; 186 -> 92 VGPRs and 0.784 ->
+  // 0.799 for the in-place one-shot).  It emits no code.
   Nbr bb = b;
-  if constexpr (ACC != ACC_PP && HIDE) {
+  if constexpr (ACC != ACC_PP) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) asm volatile("" : "+v"(bb.X[k]));
   }
@@ -954,7 +956,9 @@ __device__ __forceinline__ void seed_values(const Params<Real>& p, int cls, cons
 template <int Q, int QS, typename Real>
 __device__ __forceinline__ void seed_node(const Params<Real>& p, const Real* __restrict__ src,
                                           const double* __restrict__ glob, Real* __restrict__ lam, int x, int y,
-                                          int z, int pattern) {
+                                          int z, int pattern, int inplace_out) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
   constexpr bool is3d = (Q == 19);
   constexpr int QT = Q + QS;
   const Nbr b = make_nbr(p, x, y, z);
@@ -970,18 +974,21 @@ __device__ __forceinline__ void seed_node(const Params<Real>& p, const Real* __r
   }
   double lf[Q], lg[QS > 0 ? QS : 1];
   seed_values<Q, QS, Real>(p, cls, f, g, glob, lf, lg);
+  // in place, lambda^N enters in the layout the first (odd-pattern) adjoint step
+  // reads: lambda_j(x) in slot opp(j) of x
 #pragma unroll
-  for (int j = 0; j < Q; ++j) lam[own_addr<QT>(b, j)] = (Real)lf[j];
+  for (int j = 0; j < Q; ++j) lam[own_addr<QT>(b, inplace_out ? L::opp(j) : j)] = (Real)lf[j];
 #pragma unroll
-  for (int i = 0; i < QS; ++i) lam[own_addr<QT>(b, Q + i)] = (Real)lg[i];
+  for (int i = 0; i < QS; ++i) lam[own_addr<QT>(b, Q + (inplace_out ? S::opp(i) : i))] = (Real)lg[i];
 }
 
 template <int Q, int QS, typename Real>
 __global__ __launch_bounds__(256) void k_seed(Params<Real> p, const Real* __restrict__ src,
-                                              const double* __restrict__ glob, Real* __restrict__ lam, int pattern) {
+                                              const double* __restrict__ glob, Real* __restrict__ lam, int pattern,
+                                              int inplace_out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
-  seed_node<Q, QS, Real>(p, src, glob, lam, x, blockIdx.y, blockIdx.z, pattern);
+  seed_node<Q, QS, Real>(p, src, glob, lam, x, blockIdx.y, blockIdx.z, pattern, inplace_out);
 }
 
 // ------------------------------------------------------------ adjoint step
@@ -1244,7 +1251,8 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
 // lambda^n(x) = (dW^x/df)^T(f^n(x)) mu(x),  mu_j(x) = lambda^{n+1}_j(x + e_j)
 // grad(x)    += (dW^x/dw)^T mu(x)            (interior nodes only)
 // The vector-Jacobian products below are hand-derived from the operators above.
-template <int Q, int QS, typename Real, bool NT, int V>
+// lam_in and lam_out are the same buffer in place (ACC_EVEN / ACC_ODD).
+template <int Q, int QS, typename Real, bool NT, int V, int ACC = ACC_PP>
 __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* __restrict__ mom,
                                              const Real* lam_in, Real* lam_out, const Real* __restrict__ w,
                                              Real* __restrict__ grad, int x, int y, int z) {
@@ -1253,7 +1261,7 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_inode(b);  // workspace node arrays
   Real mu[Q], nu[QSA];
-  load_cot<Q, QS, Real, ACC_PP, NT>(lam_in, b, mu, nu);
+  load_cot<Q, QS, Real, ACC, NT>(lam_in, b, mu, nu);
   const int cls = node_class(p, x, y, z, is3d);
   Real m[Mom<Q, QS, V>::N], lf[Q], lg[QSA], gw;
 #pragma unroll
@@ -1265,7 +1273,7 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
   adjoint_vjp<Q, QS, Real, V>(p, cls, m, wn, mu, nu, lf, lg, gw);
   if (cls == INTERIOR) grad[n] += gw;
-  store_cot<Q, QS, Real, NT, ACC_PP>(lam_out, b, lf, lg);
+  store_cot<Q, QS, Real, NT, ACC>(lam_out, b, lf, lg);
 }
 
 template <int Q, int QS, typename Real, bool NT, int V>
@@ -1275,6 +1283,15 @@ __global__ __launch_bounds__(256) void k_adjoint(Params<Real> p, const Real* __r
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
   adjoint_node<Q, QS, Real, NT, V>(p, mom, lam_in, lam_out, w, grad, x, blockIdx.y, blockIdx.z);
+}
+
+// One in-place adjoint step (even or odd pattern of the cotangent buffer l).
+template <int Q, int QS, typename Real, bool NT, int V, int ACC>
+__global__ __launch_bounds__(256) void k_adjoint_inplace(Params<Real> p, const Real* __restrict__ mom, Real* l,
+                                                         const Real* __restrict__ w, Real* __restrict__ grad) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  adjoint_node<Q, QS, Real, NT, V, ACC>(p, mom, l, l, w, grad, x, blockIdx.y, blockIdx.z);
 }
 
 
@@ -1491,10 +1508,8 @@ __device__ __forceinline__ void oneshot_node(const Params<Real>& p, const Real* 
   } else {
     collide_outlet<Q, QS, Real>(p, f, g);
   }
-  // the one-shot keeps its load addresses live (no HIDE): with the barrier it
-  // ran at 0.61 of peak in place against 0.69 without, despite fewer registers
-  store_state<Q, QS, Real, NT, ACC, false>(prim_out, b, f, g);
-  store_cot<Q, QS, Real, NT, ACC, false>(lam_out, b, lf, lg);
+  store_state<Q, QS, Real, NT, ACC>(prim_out, b, f, g);
+  store_cot<Q, QS, Real, NT, ACC>(lam_out, b, lf, lg);
   grad[n] = gw;
   if (cls == INTERIOR) {
     const Real v = wn + zeta * (gw + c_pen * (Real(1) - Real(2) * wn));

@@ -7,7 +7,7 @@
 //   grad     N x Real      dJ/dw accumulator (one-shot: last estimate)
 //   glob     boundary sums + J of the last objective evaluation, objective partials
 //   desc     this context's batch descriptor (constants for batched launches)
-//   lam[2]   2 states      adjoint ping-pong
+//   lam[2]   2 states      adjoint ping-pong (in place: one state)
 //   pp[2]    2 states      primal ping-pong
 //   ckpt[S]  S states      checkpoints h^{sC-1}, s = 0..S-1 (ckpt[0] = h^{-1})
 //   mom[C]   C moment sets the moments of f^k for the C steps k of one segment
@@ -197,15 +197,14 @@ lbm_status make_plan(const lbm_config* c, Plan* p, std::string* why) {
   p->mom_bytes = align_up((uint64_t)mom_values(c) * p->Np * p->rs);
   p->node_bytes = align_up((uint64_t)p->Np * p->rs);
   if (c->inplace) {
-    // the state (kept in the first checkpoint slot) and one adjoint buffer; a
-    // recorded run adds the moments of every step (its adjoint then never needs
-    // a state) and a second adjoint buffer: the adjoint steps ping-pong, which
-    // measured faster than streaming the cotangent in place
+    // the state (kept in the first checkpoint slot) and one adjoint buffer, both
+    // streamed in place; a recorded run adds the moments of every step (its
+    // adjoint then never needs a state)
     p->inplace = true;
     p->C = c->nsteps;
     p->S = 1;
-    p->total = 2 * p->node_bytes + align_up(kGlobBytes) + align_up(kDescBytes) +
-               (c->nsteps > 0 ? 3 : 2) * p->state_bytes + (uint64_t)p->C * p->mom_bytes;
+    p->total = 2 * p->node_bytes + align_up(kGlobBytes) + align_up(kDescBytes) + 2 * p->state_bytes +
+               (uint64_t)p->C * p->mom_bytes;
     if (c->hbm_budget_bytes && p->total > c->hbm_budget_bytes) {
       if (why) *why = "the moments of every step do not fit hbm_budget_bytes";
       return LBM_ENOMEM;
@@ -428,7 +427,27 @@ struct Ops {
   static void seed(lbm_ctx* c, const void* src, void* lam) {
     Geo g = node_geometry(c->cfg);
     hipLaunchKernelGGL((k_seed<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
-                       (const double*)c->glob, (Real*)lam, acc(c));
+                       (const double*)c->glob, (Real*)lam, acc(c), c->plan.inplace ? 1 : 0);
+  }
+  // One in-place adjoint step: the cotangent buffer is in the odd-pattern layout
+  // after an even number of adjoint steps (the seed writes that layout).
+  static void adjoint_inplace(lbm_ctx* c, const void* mom, int64_t steps_done) {
+    Geo g = node_geometry(c->cfg);
+    const Real* m = (const Real*)mom;
+    Real* l = (Real*)c->lam[0];
+    const Real* w = (const Real*)c->w;
+    Real* gr = (Real*)c->grad;
+    const bool odd = (steps_done % 2 == 0);
+#define LBM_AI(NTV, ACCV) \
+  hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, NTV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), m, l, w, gr)
+    if (nt(c, 1)) {
+      if (odd) LBM_AI(true, ACC_ODD);
+      else LBM_AI(true, ACC_EVEN);
+    } else {
+      if (odd) LBM_AI(false, ACC_ODD);
+      else LBM_AI(false, ACC_EVEN);
+    }
+#undef LBM_AI
   }
   static void adjoint(lbm_ctx* c, const void* mom, const void* lin, void* lout) {
     Geo g = node_geometry(c->cfg);
@@ -597,6 +616,14 @@ struct RunAdjoint {
   static lbm_status run(lbm_ctx* c, int64_t nsteps) {
     const int64_t C = c->plan.C;
     if (!c->adj_started) start_adjoint<O>(c);
+    if (c->plan.inplace) {  // every step's moments are held: no recompute
+      for (int64_t i = 0; i < nsteps; ++i) {
+        const int64_t n = c->t_adj - 1;
+        O::adjoint_inplace(c, mom_slot(c, n), c->rec_len - c->t_adj);
+        --c->t_adj;
+      }
+      return launch_check(c, "in-place adjoint step");
+    }
     for (int64_t i = 0; i < nsteps; ++i) {
       const int64_t n = c->t_adj - 1;
       const int64_t s = n / C;
@@ -652,8 +679,10 @@ struct RunGetState {
 template <class O>
 struct RunGetAdjoint {
   static lbm_status run(lbm_ctx* c, double* lf, double* lg) {
-    // the one-shot's in-place buffer follows the primal's phase; the unsteady adjoint ping-pongs
-    const int pattern = c->adj_started ? ACC_PP : O::acc(c);
+    // the one-shot's in-place buffer follows the primal's phase; the unsteady adjoint's
+    // alternates from the seed's layout (odd pattern after an even number of steps)
+    int pattern = c->adj_started ? ACC_PP : O::acc(c);
+    if (c->plan.inplace && c->adj_started) pattern = ((c->rec_len - c->t_adj) % 2 == 0) ? ACC_ODD : ACC_EVEN;
     O::get_adjoint(c, c->lam[c->lam_cur], lf, c->plan.QS ? lg : nullptr, pattern);
     return launch_check(c, "get_adjoint");
   }
@@ -902,12 +931,8 @@ lbm_status lbm_create(const lbm_config* cfg, void* hip_stream, void* workspace_d
   c->desc = q;
   q += align_up(kDescBytes);
   if (p.inplace) {
-    c->lam[0] = c->lam[1] = q;  // the one-shot rewrites one adjoint buffer in place
+    c->lam[0] = c->lam[1] = q;  // one adjoint buffer, rewritten in place
     q += p.state_bytes;
-    if (cfg->nsteps > 0) {      // the recorded run's adjoint ping-pongs
-      c->lam[1] = q;
-      q += p.state_bytes;
-    }
     c->pp[0] = c->pp[1] = nullptr;
   } else {
     for (int i = 0; i < 2; ++i) {

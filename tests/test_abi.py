@@ -114,11 +114,11 @@ def test_inplace_workspace_holds_two_states(lib):
     inpl = lbm.lbm_required_bytes(lbm.make_config(p, 0, inplace=True))
     assert inpl < 2.2 * state + 64 * 2 ** 20
     assert small - inpl >= 3 * state      # ping-pong: 4 states + checkpoint + moment set
-    # a recorded in-place run holds the moments of every step, no checkpoints, and a
-    # second adjoint buffer (its adjoint ping-pongs)
+    # a recorded in-place run adds the moments of every step and no checkpoints (its
+    # adjoint streams in place too)
     rec = lbm.lbm_required_bytes(lbm.make_config(p, 10, inplace=True))
     mom = 4 * 256 * 128 * 128 * 4
-    assert rec == inpl + state + 10 * mom
+    assert rec == inpl + 10 * mom
     with pytest.raises(lbm.LbmError):
         lbm.lbm_required_bytes(lbm.make_config(p, 10, checkpoint_interval=3, inplace=True))
     with pytest.raises(lbm.LbmError):

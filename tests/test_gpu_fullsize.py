@@ -1,6 +1,6 @@
 """The benchmark workload at full size (D3Q19 256x128x128, FP32) in the launch
 configuration the benchmark times (forward streamed in place with streaming
-stores, moments of every step held, adjoint ping-ponging): from a developed
+stores, moments of every step held, adjoint streamed in place): from a developed
 flow, every primal step, the objective, every adjoint step and the gradient of
 a short recorded run against the FP64 oracle's single-step operators applied
 to the GPU's own states, node by node over the whole lattice."""

@@ -147,7 +147,7 @@ def test_inplace_refuses_recording_adjoint_and_batches():
 @pytest.mark.parametrize("name,p", CASES, ids=[c[0] for c in CASES])
 def test_inplace_recorded_run_and_adjoint_bitwise_equal_pingpong(name, p, prec):
     """A recorded in-place run (moments of every step, one primal buffer, the
-    adjoint ping-ponging) against the ping-pong store-all plan: states after
+    adjoint streamed in place too) against the ping-pong store-all plan: states after
     every forward chunk, J, the adjoint state after every backward chunk and
     the gradient are bitwise equal."""
     steps = 23
