@@ -142,9 +142,10 @@ __device__ __forceinline__ void put(Real* p, Real v) {
 // L2, with it the line is fetched from HBM twice.  Measured on the 256x128x128
 // D3Q19 FP32 channel: adjoint 0.743 of peak without hints, 0.761 with every
 // cotangent load hinted (HBM traffic 1.065x the algorithmic bytes), 0.792 with
-// the unshifted ones only.  Hinting shifted loads, or the recorded moments,
-// loses (in-place primal with every load hinted: 0.819 -> 0.657; adjoint with
-// hinted moments: 0.761 -> 0.748).  The hint is a template
+// the unshifted ones only.  Hinting shifted loads loses (in-place primal with
+// every load hinted: 0.819 -> 0.657).  The adjoint's recorded moments take the
+// hint too (in-place adjoint 0.819 -> 0.829); its design value does not (that
+// loses, 0.829 -> 0.818).  The hint is a template
 // argument and the shifted and unshifted loads sit in separate loops: a run-time
 // flag, even one that folds to a constant after unrolling, lets the compiler
 // merge the hinted and plain load of the same address and drop the hint.
@@ -1268,7 +1269,7 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
   for (int k = 0; k < Mom<Q, QS, V>::N; ++k) m[k] = Real(0);
   if (has_moments(p, cls)) {
 #pragma unroll
-    for (int k = 0; k < Mom<Q, QS, V>::N; ++k) m[k] = mom[(size_t)k * p.Np + n];
+    for (int k = 0; k < Mom<Q, QS, V>::N; ++k) m[k] = get<NT>(mom + (size_t)k * p.Np + n);  // read once
   }
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
   adjoint_vjp<Q, QS, Real, V>(p, cls, m, wn, mu, nu, lf, lg, gw);
