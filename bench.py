@@ -284,7 +284,9 @@ def serve_main(args):
     cap = int(args.max_active_gb * 2**30) if args.max_active_gb > 0 else None
     budget = int(args.budget_gb * 2**30)
     req_cap = int(args.request_cap_gb * 2**30)
-    ex = GpuExecutor(arena_bytes=budget, per_request_cap_bytes=req_cap)  # workspaces come from one arena
+    inpl_min = int(args.inplace_min_mb * 2**20) if args.inplace_min_mb >= 0 else None
+    # workspaces come from one arena
+    ex = GpuExecutor(arena_bytes=budget, per_request_cap_bytes=req_cap, inplace_min_state_bytes=inpl_min)
     Server(ex, budget, quantum=args.quantum).replay(warm, realtime=False)
     torch.cuda.synchronize()
     print("[bench] serving %d requests at %.1f/s" % (args.requests, args.rate), file=sys.stderr, flush=True)
@@ -306,7 +308,7 @@ def serve_main(args):
                    "sizes": ["D2Q9 256x128", "D2Q9 1024x512", "D3Q19 96x48x48", "D3Q19 192x96x96"],
                    "steps": args.serve_steps, "quantum": args.quantum, "budget_gb": args.budget_gb,
                    "policy": args.policy, "max_active_gb": args.max_active_gb, "quantum_ms": args.quantum_ms,
-                   "request_cap_gb": args.request_cap_gb,
+                   "request_cap_gb": args.request_cap_gb, "inplace_min_mb": args.inplace_min_mb,
                    "trace_seed": 1},
         "serving": s_batched,
         "scheduler": dict(srv.stats),
@@ -317,7 +319,7 @@ def serve_main(args):
     torch.cuda.empty_cache()
     if not args.no_baseline:
         print("[bench] one-at-a-time replay", file=sys.stderr, flush=True)
-        base = run_one_at_a_time(jobs(), per_request_cap_bytes=req_cap)
+        base = run_one_at_a_time(jobs(), per_request_cap_bytes=req_cap, inplace_min_state_bytes=inpl_min)
         rec["one_at_a_time"] = summarize(base)
         bg = rec["one_at_a_time"].get("gradients_per_s")
         rec["speedup_vs_one_at_a_time"] = (s_batched["gradients_per_s"] / bg) if bg else None
@@ -350,6 +352,9 @@ def main(argv=None):
     ap.add_argument("--rate", type=float, default=20.0, help="mean arrivals per second")
     ap.add_argument("--serve-steps", type=int, default=2000, help="primal (= adjoint) steps per request")
     ap.add_argument("--budget-gb", type=float, default=240.0, help="HBM budget for admitted requests")
+    ap.add_argument("--inplace-min-mb", type=float, default=32.0,
+                    help="served requests whose state is at least this large stream in place with single-context "
+                         "launches (negative: never)")
     ap.add_argument("--request-cap-gb", type=float, default=64.0,
                     help="workspace cap per served request: every step's moments are held (no recompute) "
                          "when they fit, else the largest checkpoint interval that does")

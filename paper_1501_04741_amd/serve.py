@@ -375,7 +375,12 @@ class GpuExecutor(Executor):
 
     max_batch = 32
 
-    def __init__(self, device=None, per_request_cap_bytes: int = 64 << 30, arena_bytes: Optional[int] = None):
+    def __init__(self, device=None, per_request_cap_bytes: int = 64 << 30, arena_bytes: Optional[int] = None,
+                 inplace_min_state_bytes: Optional[int] = 32 << 20):
+        """inplace_min_state_bytes: requests whose state is at least this large and whose
+        moments of every step fit the cap stream in place (one primal and one adjoint
+        buffer) with single-context launches, which move their bytes faster than the
+        batched ping-pong kernels; smaller requests share batched launches.  None: never."""
         import torch
 
         from . import lbm as _lbm
@@ -384,28 +389,34 @@ class GpuExecutor(Executor):
         self.device = torch.device(device if device is not None else "cuda")
         self.stream = torch.cuda.current_stream(self.device)
         self.cap = int(per_request_cap_bytes)
+        self.inplace_min = inplace_min_state_bytes
         self.arena = Arena(arena_bytes, self.device) if arena_bytes else None
 
     def _plan_bytes(self, job: Job) -> int:
         """Workspace for the request: store-all (no recompute) when it fits the
         per-request cap, otherwise the largest checkpoint interval that fits,
-        never less than the sqrt(N) plan.  Sets job._store_all."""
+        never less than the sqrt(N) plan; the in-place plan for a large request that keeps
+        every step's moments.  Sets job._store_all and job._inplace."""
         L = self.lbm
         sqrt_b = L.lbm_required_bytes(L.make_config(job.params, job.steps, job.precision))
         all_b = L.lbm_required_bytes(L.make_config(job.params, job.steps, job.precision,
                                                    checkpoint_interval=max(job.steps, 1)))
         job._store_all = all_b <= self.cap
+        job._inplace = bool(self.inplace_min is not None and job._store_all and job.steps > 0
+                            and self.step_bytes(job) >= self.inplace_min)
+        if job._inplace:
+            return L.lbm_required_bytes(L.make_config(job.params, job.steps, job.precision, inplace=True))
         return max(sqrt_b, min(all_b, self.cap))
 
     def footprint(self, job: Job) -> int:
         job._budget = self._plan_bytes(job)
         L = self.lbm
         return L.lbm_required_bytes(L.make_config(job.params, job.steps, job.precision,
-                                                  hbm_budget_bytes=job._budget))
+                                                  hbm_budget_bytes=job._budget, inplace=job._inplace))
 
     def kind(self, job: Job):
         p = job.params
-        return (p["flow"], p.get("scalar", 0), job.precision)
+        return (p["flow"], p.get("scalar", 0), job.precision, bool(getattr(job, "_inplace", False)))
 
     def step_bytes(self, job: Job) -> int:
         p = job.params
@@ -431,7 +442,7 @@ class GpuExecutor(Executor):
             ws = block[1]
         make = lambda: self.lbm.Lbm(job.params, nsteps=job.steps, precision=job.precision,
                                     hbm_budget_bytes=job._budget, device=self.device, stream=self.stream,
-                                    workspace=ws)
+                                    workspace=ws, inplace=job._inplace)
         try:
             try:
                 L = make()
@@ -447,6 +458,7 @@ class GpuExecutor(Executor):
             raise
         L._block = block
         L._footprint = job.footprint
+        L._inplace = job._inplace
         dt = torch.float32 if job.precision == "fp32" else torch.float64
         host = torch.as_tensor(np.ascontiguousarray(np.asarray(job.design).reshape(-1)), dtype=dt).pin_memory()
         L._w_host = host
@@ -457,14 +469,22 @@ class GpuExecutor(Executor):
         return L
 
     def primal(self, handles, k):
-        self.lbm.lbm_primal_steps_batch([h.ctx for h in handles], k, record=True)
+        if handles[0]._inplace:  # in-place contexts do not join batched launches
+            for h in handles:
+                h.primal_steps(k, record=True)
+        else:
+            self.lbm.lbm_primal_steps_batch([h.ctx for h in handles], k, record=True)
         for h in handles:
             t, rec, _ = h.times()
             if rec == h.nsteps:
                 self.lbm.lbm_objective_async(h.ctx, h._J)
 
     def adjoint(self, handles, k):
-        self.lbm.lbm_adjoint_steps_batch([h.ctx for h in handles], k)
+        if handles[0]._inplace:
+            for h in handles:
+                h.adjoint_steps(k)
+        else:
+            self.lbm.lbm_adjoint_steps_batch([h.ctx for h in handles], k)
 
     def finish(self, handle):
         torch = self.torch
@@ -501,23 +521,26 @@ class GpuExecutor(Executor):
 
 
 def run_one_at_a_time(jobs: List[Job], device=None, clock=time.perf_counter,
-                      per_request_cap_bytes: int = 64 << 30):
+                      per_request_cap_bytes: int = 64 << 30, inplace_min_state_bytes: Optional[int] = 32 << 20):
     """Baseline: the same trace on the same GPU, one request at a time in
     arrival order (FIFO), no overlap: each request is created, runs its full
     primal, objective, adjoint and gradient with single-context launches,
     and is read back before the next one starts.  Each request gets the same
-    checkpoint plan as in the server (same per-request cap)."""
+    checkpoint plan and streaming as in the server (same per-request cap and
+    in-place threshold)."""
     import torch
 
     from .lbm import Lbm
-    ex = GpuExecutor(device, per_request_cap_bytes=per_request_cap_bytes)
+    ex = GpuExecutor(device, per_request_cap_bytes=per_request_cap_bytes,
+                     inplace_min_state_bytes=inplace_min_state_bytes)
     t0 = clock()
     out = []
     for job in sorted(jobs, key=lambda j: j.arrival):
         while clock() - t0 < job.arrival:
             time.sleep(min(1e-3, job.arrival - (clock() - t0)))
         budget = ex._plan_bytes(job)
-        L = Lbm(job.params, nsteps=job.steps, precision=job.precision, hbm_budget_bytes=budget, device=ex.device)
+        L = Lbm(job.params, nsteps=job.steps, precision=job.precision, hbm_budget_bytes=budget, device=ex.device,
+                inplace=job._inplace)
         J, g = L.value_and_grad(job.design)
         job.J = J
         job.grad = g.cpu().numpy()

@@ -158,3 +158,27 @@ def test_arena_backed_server_results_equal_alone():
         J, g = ctx.value_and_grad(torch.from_numpy(j.design))
         assert j.J == J and np.array_equal(j.grad, g.cpu().numpy()), j.rid
         ctx.close()
+
+
+def test_inplace_requests_served_equal_alone_bitwise():
+    """Requests above the in-place threshold (here every request of the 40x12x10 size)
+    stream in place with single-context launches beside the batched ping-pong ones;
+    every result equals the request run alone (ping-pong, every step's moments held)."""
+    jobs = _jobs(n_each=2, steps=33)
+    big = 19 * 40 * 12 * 10 * 4
+    ex = GpuExecutor(inplace_min_state_bytes=big)
+    srv = Server(ex, hbm_budget_bytes=4 << 30, quantum=10)
+    for j in jobs[:4]:
+        srv.submit(j)
+    for _ in range(2):
+        srv.tick()
+    for j in jobs[4:]:
+        srv.submit(j)
+    srv.drain()
+    assert all(j.state == DONE for j in jobs), [(j.rid, j.state, j.error) for j in jobs]
+    inplace = [j for j in jobs if j._inplace]
+    assert len(inplace) == 2 and all(j.params["nx"] == 40 for j in inplace)
+    for j in jobs:
+        J, g = _alone(j.params, j.design, j.steps, j.precision, interval=j.steps)
+        assert j.J == J, (j.rid, j.J, J)
+        assert np.array_equal(j.grad, g), j.rid
