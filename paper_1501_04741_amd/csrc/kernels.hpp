@@ -230,8 +230,10 @@ enum : int { ACC_PP = 0, ACC_EVEN = 1, ACC_ODD = 2 };
 // the 256x128x128 D3Q19 FP32 channel: ping-pong primal 0.707 -> 0.728 of peak,
 // ping-pong one-shot 0.739 -> 0.753, in-place one-shot (both phases) 0.707 ->
 // 0.783, recorded in-place primal 0.822 -> 0.837 with the odd phase hinted
-// alone (hinting its even phase too drops it to 0.789).  Unrecorded in-place
-// steps run without streaming hints at all.
+// alone: hinting its even phase too drops it to 0.776 on that 319 MB state,
+// most of which the last-level cache keeps between the two phases, but lifts
+// states beyond twice the cache (512x128x128: 0.659 -> 0.774; 512x256x128:
+// 0.652 -> 0.733).  Unrecorded in-place steps run without streaming hints.
 template <int Q, int QS, typename Real, int ACC, bool NT = false>
 __device__ __forceinline__ void load_state(const Real* a, const Nbr& b, Real (&f)[Q], Real (&g)[QS > 0 ? QS : 1]) {
   using L = Lat<Q>;
@@ -743,7 +745,9 @@ __device__ __forceinline__ void node_moments(const Params<Real>& p, int cls, int
 // With MOM, also records the node's pre-collision moments (see Mom).
 // src and dst are the same buffer for the in-place patterns, so they carry no
 // restrict qualifier here (the ping-pong kernels declare theirs).
-template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC = ACC_PP>
+// NTE: streaming hint on the even phase's loads as well (states far beyond the
+// last-level cache; see load_state)
+template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC = ACC_PP, bool NTE = false>
 __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* src, Real* dst,
                                             const Real* __restrict__ w, Real* __restrict__ mom, int x, int y,
                                             int z) {
@@ -751,7 +755,7 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* s
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_inode(b);  // workspace node arrays
   Real f[Q], g[QS > 0 ? QS : 1];
-  load_state<Q, QS, Real, ACC, NT && ACC != ACC_EVEN>(src, b, f, g);
+  load_state<Q, QS, Real, ACC, NT && (ACC != ACC_EVEN || NTE)>(src, b, f, g);
   const int cls = node_class(p, x, y, z, is3d);
   if constexpr (MOM) {
     if (has_moments(p, cls)) {  // the only classes whose transposes read them
@@ -783,12 +787,12 @@ __global__ __launch_bounds__(256) void k_primal(Params<Real> p, const Real* __re
 }
 
 // One in-place step (even or odd phase); with MOM it also records the moments.
-template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC>
+template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC, bool NTE = false>
 __global__ __launch_bounds__(256) void k_primal_inplace(Params<Real> p, Real* a, const Real* __restrict__ w,
                                                         Real* __restrict__ mom) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
-  primal_node<Q, QS, Real, NT, MOM, V, ACC>(p, a, a, w, mom, x, blockIdx.y, blockIdx.z);
+  primal_node<Q, QS, Real, NT, MOM, V, ACC, NTE>(p, a, a, w, mom, x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------------ objective

@@ -354,7 +354,11 @@ struct Ops {
 #define LBM_PI(NTV, MOMV, ACCV) \
   hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), a, w, m)
     if (m && nt(c, 1)) {
-      if (even) LBM_PI(true, true, ACC_EVEN);
+      // the even phase's loads take the streaming hint too once the state is far beyond the cache
+      if (even && c->plan.state_bytes > 2 * kLastLevelCacheBytes)
+        hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, true, true, V, ACC_EVEN, true>), g.grid, g.block, 0,
+                           c->stream, P(c), a, w, m);
+      else if (even) LBM_PI(true, true, ACC_EVEN);
       else LBM_PI(true, true, ACC_ODD);
     } else if (m) {
       if (even) LBM_PI(false, true, ACC_EVEN);
