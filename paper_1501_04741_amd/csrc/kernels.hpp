@@ -233,7 +233,8 @@ enum : int { ACC_PP = 0, ACC_EVEN = 1, ACC_ODD = 2 };
 // alone: hinting its even phase too drops it to 0.776 on that 319 MB state,
 // most of which the last-level cache keeps between the two phases, but lifts
 // states beyond twice the cache (512x128x128: 0.659 -> 0.774; 512x256x128:
-// 0.652 -> 0.733).  Unrecorded in-place steps run without streaming hints.
+// 0.652 -> 0.733).  Unrecorded in-place steps take the hints (both phases) only
+// beyond twice the cache as well.
 template <int Q, int QS, typename Real, int ACC, bool NT = false>
 __device__ __forceinline__ void load_state(const Real* a, const Nbr& b, Real (&f)[Q], Real (&g)[QS > 0 ? QS : 1]) {
   using L = Lat<Q>;

@@ -341,10 +341,13 @@ struct Ops {
   // access pattern of the current state buffer: ping-pong, or the in-place phase of step t
   static int acc(lbm_ctx* c) { return c->plan.inplace ? ((c->t % 2 == 0) ? ACC_EVEN : ACC_ODD) : ACC_PP; }
   // One in-place step from the current phase; records the moments when mom != null.
-  // Streaming stores only when recording: an unrecorded in-place step is faster
-  // with plain stores even when its state exceeds the last-level cache (measured,
-  // D3Q19 FP32: 0.741 -> 0.766 of peak at 256x128x128, 0.632 -> 0.661 at
-  // 512x256x128), a recorded one slower (0.819 -> 0.748).
+  // Streaming stores and hints: a recorded step takes them once its state exceeds
+  // the last-level cache (plain stores: 0.819 -> 0.748 of peak, D3Q19 FP32
+  // 256x128x128), its even phase's loads only beyond twice the cache.  An
+  // unrecorded step stores plainly up to twice the cache (NT stores without load
+  // hints: 0.766 -> 0.741 at 256x128x128) and beyond it takes NT stores and hinted
+  // loads in both phases (0.662 -> 0.750 at 512x256x128, 0.668 -> 0.815 at
+  // 512x128x128; ping-pong 0.753 and 0.766).
   static void primal_inplace(lbm_ctx* c, void* mom) {
     Geo g = node_geometry(c->cfg);
     Real* a = (Real*)c->cur;
@@ -363,6 +366,12 @@ struct Ops {
     } else if (m) {
       if (even) LBM_PI(false, true, ACC_EVEN);
       else LBM_PI(false, true, ACC_ODD);
+    } else if (c->plan.state_bytes > 2 * kLastLevelCacheBytes) {
+      // unrecorded, state far beyond the cache: streaming stores and hinted loads in both phases
+      if (even)
+        hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, true, false, V, ACC_EVEN, true>), g.grid, g.block, 0,
+                           c->stream, P(c), a, w, m);
+      else LBM_PI(true, false, ACC_ODD);
     } else {
       if (even) LBM_PI(false, false, ACC_EVEN);
       else LBM_PI(false, false, ACC_ODD);
