@@ -1,0 +1,24 @@
+"""bench.py's contract on the CPU: more than one GPU is refused with a message,
+and the counter-traffic table is consulted only for the profiled sources."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_counter_traffic_keyed_to_sources():
+    w = bench.COUNTER_TRAFFIC["workload"]
+    if bench.sources_sha() == bench.COUNTER_TRAFFIC["sources_sha256_16"]:
+        assert bench._measured_traffic(w, "k_adjoint_inplace") == bench.COUNTER_TRAFFIC["k_adjoint_inplace"]
+    assert bench._measured_traffic("another_workload", "k_adjoint_inplace") is None
