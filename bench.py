@@ -185,10 +185,10 @@ def mixer_leg(dev, steps=4000, os_iters=400):
             "note": "two primal states (234 MB) fit the 256 MB last-level cache; the one-shot's four do not"}
 
 
-def mrt_leg(dev, steps=200, collision="mrt", inplace=True):
+def mrt_leg(dev, steps=200, collision="mrt", inplace=True, prec="fp32"):
     """Recorded primal and adjoint launches of the 256x128x128 D3Q19 channel,
-    FP32, all moments held: with the forced MRT interior collision (d'Humieres
-    rates), or with BGK and ping-pong buffers for comparison."""
+    all moments held: with the forced MRT interior collision (d'Humieres
+    rates), or with BGK and ping-pong buffers, or in FP64, for comparison."""
     import torch
 
     from paper_1501_04741_amd import inputs
@@ -197,10 +197,12 @@ def mrt_leg(dev, steps=200, collision="mrt", inplace=True):
     wl = inputs.workload("d3q19_channel_256x128x128")
     p = dict(inputs.model_params(wl), collision=collision)
     w = torch.from_numpy(inputs.design_for(wl)).to(dev)
+    if prec == "fp64":
+        w = w.double()
     if inplace:
-        L = Lbm(p, nsteps=steps, precision="fp32", device=dev, inplace=True)
+        L = Lbm(p, nsteps=steps, precision=prec, device=dev, inplace=True)
     else:
-        L = Lbm(p, nsteps=steps, precision="fp32", checkpoint_interval=steps, device=dev)
+        L = Lbm(p, nsteps=steps, precision=prec, checkpoint_interval=steps, device=dev)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     for rep_ in range(2):  # the second pass is timed
         L.set_design(w)
@@ -216,18 +218,19 @@ def mrt_leg(dev, steps=200, collision="mrt", inplace=True):
     L.close()
     prim_us = ev[0].elapsed_time(ev[1]) * 1e3 / steps
     adj_us = ev[2].elapsed_time(ev[3]) * 1e3 / (steps - 1)
-    pb, ab = algorithmic_bytes(p, "fp32")
+    pb, ab = algorithmic_bytes(p, prec)
     nodes = p["nx"] * p["ny"] * p["nz"]
     roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
     sfx = "_inplace" if inplace else ""
     tag = ",MRT" if collision == "mrt" else ""
-    return {"workload": "d3q19_channel_256x128x128, %s collision, %s" % (collision.upper(),
-                                                                        "in place" if inplace else "ping-pong"),
+    real = "float" if prec == "fp32" else "double"
+    return {"workload": "d3q19_channel_256x128x128, %s collision, %s, %s" % (
+                collision.upper(), "in place" if inplace else "ping-pong", prec.upper()),
             "steps_timed": steps,
-            "primal": {"kernel": "k_primal%s<19,0,float%s>" % (sfx, tag), "mlups": nodes / prim_us,
+            "primal": {"kernel": "k_primal%s<19,0,%s%s>" % (sfx, real, tag), "mlups": nodes / prim_us,
                        "roofline": roof(pb, prim_us)},
-            "adjoint": {"kernel": "k_adjoint%s<19,0,float%s>" % (sfx, tag), "mlups": nodes / adj_us,
+            "adjoint": {"kernel": "k_adjoint%s<19,0,%s%s>" % (sfx, real, tag), "mlups": nodes / adj_us,
                         "roofline": roof(ab, adj_us)}}
 
 
@@ -364,7 +367,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="d3q19_channel_256x128x128")
     ap.add_argument("--lbm-steps", type=int, default=None, help="override the primal horizon N")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixer", action="store_true", help="skip the mixing-duct, MRT, in-place and ping-pong legs")
+    ap.add_argument("--no-mixer", action="store_true", help="skip the mixing-duct, MRT, in-place, ping-pong and FP64 legs")
     ap.add_argument("--ping-pong", action="store_true", help="run the main evaluation with ping-pong buffers")
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
@@ -562,6 +565,8 @@ def main(argv=None):
         rec["inplace"] = inplace_leg(dev)
         print("[bench] ping-pong leg", file=sys.stderr, flush=True)
         rec["ping_pong"] = mrt_leg(dev, collision="bgk", inplace=False)
+        print("[bench] FP64 leg", file=sys.stderr, flush=True)
+        rec["fp64"] = mrt_leg(dev, collision="bgk", inplace=True, prec="fp64")
     if not args.no_cpu_baseline:
         print("[bench] GPU timing done; timing the CPU oracle sample", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(p, w_np.astype(np.float64), args.cpu_steps)
