@@ -161,8 +161,13 @@ def mixer_leg(dev, steps=4000, os_iters=400):
     I = Lbm(p, nsteps=0, precision="fp32", device=dev, inplace=True)
     I.set_design(w)
     I.reset()
+    I.primal_steps(200)
+    ei = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ei[2].record()
+    I.primal_steps(steps)
+    ei[3].record()
+    I.reset()
     I.oneshot_steps(20, 0.0, 0.0)
-    ei = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     ei[0].record()
     I.oneshot_steps(os_iters, 0.0, 0.0)
     ei[1].record()
@@ -172,6 +177,7 @@ def mixer_leg(dev, steps=4000, os_iters=400):
     prim_us = ev[0].elapsed_time(ev[1]) * 1e3 / steps
     os_us = ev[2].elapsed_time(ev[3]) * 1e3 / os_iters
     osi_us = ei[0].elapsed_time(ei[1]) * 1e3 / os_iters
+    pi_us = ei[2].elapsed_time(ei[3]) * 1e3 / steps
     pb, ob = primal_bytes(p, "fp32", recorded=False), oneshot_bytes(p, "fp32")
     roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
@@ -180,6 +186,8 @@ def mixer_leg(dev, steps=4000, os_iters=400):
                        "roofline": roof(pb, prim_us)},
             "oneshot": {"kernel": "k_oneshot<19,7,float>", "iterations_timed": os_iters, "mlups": nodes / os_us,
                         "roofline": roof(ob, os_us)},
+            "primal_inplace": {"kernel": "k_primal_inplace<19,7,float>", "steps_timed": steps, "mlups": nodes / pi_us,
+                               "roofline": roof(pb, pi_us)},
             "oneshot_inplace": {"kernel": "k_oneshot_inplace<19,7,float>", "iterations_timed": os_iters,
                                 "mlups": nodes / osi_us, "roofline": roof(ob, osi_us)},
             "note": "two primal states (234 MB) fit the 256 MB last-level cache; the one-shot's four do not"}
