@@ -134,21 +134,20 @@ __device__ __forceinline__ void put(Real* p, Real v) {
     *p = v;
   }
 }
-// Streaming loads, for populations read once per step (cotangent, and the primal
-// state in the kernels listed at load_state).  Only accesses that are not shifted
-// along x take the hint.  A load shifted by
-// one site spans one cache line more than its wave's 256 bytes, and that line is
+// Streaming loads, for populations read once per step (cotangent, recorded
+// moments, and the primal state in the kernels listed at load_state).  Only
+// accesses that are not shifted along x take the hint: a load shifted by one
+// site spans one cache line more than its wave's 256 bytes, and that line is
 // also read by the neighbouring wave; without the hint the second read hits the
 // L2, with it the line is fetched from HBM twice.  Measured on the 256x128x128
 // D3Q19 FP32 channel: adjoint 0.743 of peak without hints, 0.761 with every
 // cotangent load hinted (HBM traffic 1.065x the algorithmic bytes), 0.792 with
-// the unshifted ones only.  Hinting shifted loads loses (in-place primal with
-// every load hinted: 0.819 -> 0.657).  The adjoint's recorded moments take the
-// hint too (in-place adjoint 0.819 -> 0.829); its design value does not (that
-// loses, 0.829 -> 0.818).  The hint is a template
-// argument and the shifted and unshifted loads sit in separate loops: a run-time
-// flag, even one that folds to a constant after unrolling, lets the compiler
-// merge the hinted and plain load of the same address and drop the hint.
+// the unshifted ones only; in-place primal with every load hinted 0.819 ->
+// 0.657.  The adjoint's recorded moments take the hint too (in-place adjoint
+// 0.819 -> 0.829); its design value does not (0.829 -> 0.818).  The hint is a
+// template argument and the shifted and unshifted loads sit in separate loops:
+// a run-time flag, even one that folds to a constant after unrolling, lets the
+// compiler merge the hinted and plain load of the same address and drop the hint.
 template <bool NT, typename Real>
 __device__ __forceinline__ Real get(const Real* p) {
   if constexpr (NT) {
