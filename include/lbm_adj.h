@@ -236,7 +236,8 @@ lbm_status lbm_export_maps(lbm_ctx* ctx, uint8_t* mask_dev, int64_t* src_dev);
  * where 1 - 2w is the derivative of the penalty P = sum w(1-w) (eq. P); a
  * negative zeta*penalty drives w toward 0 and 1.  The design is updated in
  * the workspace (read it with lbm_get_design); lbm_gradient returns the last
- * g.  Unrecorded: the primal uses the ping-pong buffers.  Errors: LBM_ESTATE
+ * g.  Unrecorded: the primal uses the ping-pong buffers (with inplace = 1 the
+ * primal and adjoint buffers are streamed in place).  Errors: LBM_ESTATE
  * (no design, or an unsteady adjoint in progress), LBM_EINVAL. */
 lbm_status lbm_oneshot_steps(lbm_ctx* ctx, int64_t nsteps, double zeta, double penalty);
 
