@@ -455,6 +455,9 @@ struct Ops {
   hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, NTV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), m, l, w, gr)
     if (nt(c, 1)) {
       if (odd) LBM_AI(true, ACC_ODD);
+      else if (c->plan.state_bytes > 2 * kLastLevelCacheBytes)  // even-phase hint far beyond the cache
+        hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, true, V, ACC_EVEN, true>), g.grid, g.block, 0, c->stream,
+                           P(c), m, l, w, gr);
       else LBM_AI(true, ACC_EVEN);
     } else {
       if (odd) LBM_AI(false, ACC_ODD);
