@@ -1,16 +1,22 @@
 """Benchmark: one design evaluation (J and dJ/dw) of the adjoint LBM hot path.
 
 A bench step is the whole hot path over one design field: set the design,
-reset, N recorded primal steps, objective, N adjoint steps (with segment
-recomputes from checkpoints) and the gradient export.  Default workload: the
-D3Q19 Brinkman channel 256x128x128 (4.19M nodes), N = 2000, FP32.
+reset, N recorded primal steps, objective, N adjoint steps and the gradient
+export.  Default workload: the D3Q19 Brinkman channel 256x128x128 (4.19M
+nodes), N = 2000, FP32, in the plan the 160 GB budget allows: every step's
+moments held (store-all), so the timed backward recomputes nothing.  The
+fixed-interval checkpoint plan, whose backward recomputes every trajectory
+segment, is timed in the ``recompute`` leg.
 
 Prints ONE JSON line.  ``value`` is the gradient-evaluation throughput in
-MLUPS: lattice nodes x primal steps differentiated per second (forward,
-recompute and adjoint all inside the timed region).  Kernel-level figures
-come from HIP events recorded on the library's stream inside the timed steps:
-the primal kernel over the N forward launches, the adjoint kernel over the
-launches of the last trajectory segment (which needs no recompute).
+MLUPS: lattice nodes x primal steps differentiated per second (forward and
+adjoint inside the timed region).  Kernel-level figures come from HIP events
+recorded on the library's stream inside the timed steps: the primal kernel
+over the N forward launches, the adjoint kernel over the launches of the last
+trajectory segment (which needs no recompute).  The same line carries the
+serving measurement (a Poisson trace of design-evaluation requests through
+the continuous-batching server and, on the same GPU, one request at a time)
+and the CPU oracle timed on bounded samples of the configured workloads.
 
 Only one GPU is supported: ``--gpus N`` with N > 1 exits with a message.
 """
@@ -242,6 +248,77 @@ def mrt_leg(dev, steps=200, collision="mrt", inplace=True, prec="fp32"):
                         "roofline": roof(ab, adj_us)}}
 
 
+def recompute_leg(dev, workload="d3q19_channel_256x128x128"):
+    """The fixed-interval checkpoint plan of the 256x128x128 channel (N = 2000,
+    FP32): the checkpoint interval C that minimises the workspace (no budget),
+    ping-pong buffers.  The recorded forward writes a full state every C steps
+    and the moments of the last segment; the backward recomputes every other
+    segment from its checkpoint before reversing it.  One warm-up evaluation,
+    one timed."""
+    import torch
+
+    from paper_1501_04741_amd import inputs
+    from paper_1501_04741_amd.lbm import Lbm
+
+    wl = inputs.workload(workload)
+    p = inputs.model_params(wl)
+    N = int(wl["steps"])
+    prec = wl["precision"]
+    w = torch.from_numpy(inputs.design_for(wl)).to(dev)
+    L = Lbm(p, nsteps=N, precision=prec, device=dev)
+    plan = L.plan()
+    C = plan["interval"]
+    k_last = N - ((N - 1) // C) * C
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    grad = torch.empty(L.N, dtype=L.dtype, device=dev)
+    for rep_ in range(2):  # the second pass is timed
+        L.set_design(w)
+        L.reset()
+        ev[0].record()
+        L.primal_steps(N, record=True)
+        ev[1].record()
+        L.adjoint_steps(1)
+        ev[2].record()
+        L.adjoint_steps(k_last - 1)
+        ev[3].record()
+        L.adjoint_steps(N - k_last)
+        ev[4].record()
+        L.gradient(out=grad)
+    torch.cuda.synchronize()
+    ws = L.workspace_bytes
+    L.close()
+    nodes = L.N
+    fwd_ms = ev[0].elapsed_time(ev[1])
+    bwd_ms = ev[1].elapsed_time(ev[4])
+    prim_us = fwd_ms * 1e3 / N
+    adj_us = ev[2].elapsed_time(ev[3]) * 1e3 / (k_last - 1)
+    pb, ab = algorithmic_bytes(p, prec)
+    recomputed = N - k_last  # every segment but the last is recomputed once
+    bwd_bytes = N * ab + recomputed * pb
+    roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
+    real = "float" if prec == "fp32" else "double"
+    return {"workload": "%s, checkpoint every %d steps (%d checkpoints, %d moment sets), ping-pong" % (
+                workload, C, plan["checkpoints"], plan["moment_sets"]),
+            "lbm_steps": N, "checkpoint_interval": C, "workspace_gb": round(ws / 1e9, 3),
+            "recomputed_steps": recomputed,
+            "evaluation_mlups": nodes * N / ((fwd_ms + bwd_ms) * 1e-3) / 1e6,
+            "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+            "forward_mlups": nodes * N / (fwd_ms * 1e-3) / 1e6,
+            "backward_mlups": nodes * N / (bwd_ms * 1e-3) / 1e6,
+            "backward_roofline": {"bound": "hbm", "achieved": bwd_bytes / (bwd_ms * 1e-3) / 1e9,
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": bwd_bytes / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                  "bytes": bwd_bytes,
+                                  "note": "N adjoint launches + the recorded primal launches of the recompute"},
+            "primal": {"kernel": "k_primal<19,0,%s>" % real, "mlups": nodes / prim_us,
+                       "roofline": dict(roof(pb, prim_us),
+                                        traffic=_measured_traffic(workload, "k_primal"))},
+            "adjoint": {"kernel": "k_adjoint<19,0,%s>" % real, "mlups": nodes / adj_us,
+                        "roofline": dict(roof(ab, adj_us),
+                                         traffic=_measured_traffic(workload, "k_adjoint"))}}
+
+
 def inplace_leg(dev, steps=200):
     """The 256x128x128 channel streamed in place (one buffer per state): an
     unrecorded forward and the one-shot iteration, FP32, with the workspace of
@@ -283,21 +360,61 @@ def inplace_leg(dev, steps=200):
             "workspace_gb": {"inplace": round(ws_inplace / 1e9, 3), "ping_pong": round(ws_pp / 1e9, 3)}}
 
 
-def cpu_baseline(p, w64, steps):
+# Bounded oracle samples: (workload, steps).  The 64x32 channel runs its full
+# horizon; the others a few steps, since the per-step cost is constant.
+CPU_SAMPLES = (("d2q9_channel_64x32", 1000), ("d2q9_d2q5_exchanger_512x256", 20),
+               ("d3q19_d3q7_mixer_128x64x64", 4), ("d3q19_channel_256x128x128", 4))
+
+
+def _cpu_sample(name, steps):
+    import numpy as np
+
     import oracle
-    cores = oracle.threads()
+    from paper_1501_04741_amd import inputs
+    wl = inputs.workload(name)
+    p = inputs.model_params(wl)
+    w64 = inputs.design_for(wl).astype(np.float64)
     t0 = time.perf_counter()
     oracle.adjoint(p, w64, steps)
     dt = time.perf_counter() - t0
     n = p["nx"] * p["ny"] * p["nz"]
-    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": "%dx%dx%d D3Q19 grid, %d primal + %d adjoint steps of the FP64 oracle (adjoint by complex-step "
-                      "local Jacobians), %.1f s" % (p["nx"], p["ny"], p["nz"], steps, steps, dt)}
+    return {"workload": name, "steps": steps, "seconds": dt, "mlups": n * steps / dt / 1e6}
 
 
-def serve_main(args):
+def cpu_baseline(workload, samples=CPU_SAMPLES):
+    """The FP64 oracle (primal + unsteady adjoint, local Jacobians by complex step)
+    on the host's cores: bounded samples of every configured workload; ``value``
+    is the benchmark workload's, in the unit of the GPU figure (nodes x steps
+    differentiated per second)."""
+    import oracle
+    cores = oracle.threads()
+    runs = [_cpu_sample(name, steps) for name, steps in samples]
+    main = next((r for r in runs if r["workload"] == workload), runs[-1])
+    return {"value": main["mlups"], "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "nproc": os.cpu_count(),
+            "sample": "%s: %d primal + %d adjoint steps of the FP64 oracle (adjoint by complex-step local "
+                      "Jacobians), %.1f s; other workloads in 'samples'" % (
+                          main["workload"], main["steps"], main["steps"], main["seconds"]),
+            "samples": runs}
+
+
+def _request_designs(trace):
+    """Seeded design fields of the trace's requests, drawn in parallel host threads
+    (numpy's rolls and sums release the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_1501_04741_amd import inputs
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as pool:
+        return list(pool.map(inputs.request_design, trace))
+
+
+def serving_leg(args):
     """Replays a Poisson trace through the continuous-batching server and, on the
-    same GPU, one request at a time (FIFO, no overlap); prints one JSON line."""
+    same GPU, one request at a time (FIFO, no overlap).  Returns a dict: served
+    and one-at-a-time gradients/s with p50/p99 latency, their ratio, and the
+    largest difference between a served result and the same request run alone."""
+    import gc
+
     import numpy as np
     import torch
 
@@ -305,10 +422,11 @@ def serve_main(args):
     from paper_1501_04741_amd.serve import GpuExecutor, Job, Server, run_one_at_a_time, summarize
 
     trace = inputs.poisson_trace(args.requests, args.rate, seed=1, steps=args.serve_steps)
+    designs = _request_designs(trace)
 
     def jobs():
-        return [Job(rid=r.rid, params=r.params, steps=r.steps, design=inputs.request_design(r),
-                    precision="fp32", arrival=r.arrival_s) for r in trace]
+        return [Job(rid=r.rid, params=r.params, steps=r.steps, design=d, precision="fp32", arrival=r.arrival_s)
+                for r, d in zip(trace, designs)]
 
     torch.cuda.set_device(0)
     # warm-up: one small request through both paths (kernel loading, allocator)
@@ -330,39 +448,53 @@ def serve_main(args):
     served = srv.replay(jobs(), realtime=True)
     s_batched = summarize(served)
     rec = {
+        "config": {"workload": "poisson_trace", "requests": args.requests, "rate_per_s": args.rate,
+                   "sizes": ["D2Q9 256x128", "D2Q9 1024x512", "D3Q19 96x48x48", "D3Q19 192x96x96"],
+                   "steps": args.serve_steps, "precision": "fp32", "objective": "pressure drop",
+                   "quantum": args.quantum, "budget_gb": args.budget_gb,
+                   "policy": args.policy, "max_active_gb": args.max_active_gb, "quantum_ms": args.quantum_ms,
+                   "request_cap_gb": args.request_cap_gb, "inplace_min_mb": args.inplace_min_mb,
+                   "trace_seed": 1},
+        "served": s_batched,
+        "scheduler": dict(srv.stats),
+    }
+    results = [(j.rid, j.J, j.grad) for j in served if j.state == "done"]
+    del srv, ex, served
+    gc.collect()
+    torch.cuda.empty_cache()
+    if not args.no_baseline:
+        print("[bench] one-at-a-time replay", file=sys.stderr, flush=True)
+        base = run_one_at_a_time(jobs(), per_request_cap_bytes=req_cap, inplace_min_state_bytes=inpl_min)
+        one = summarize(base)
+        rec["one_at_a_time"] = one
+        bg = one.get("gradients_per_s")
+        rec["speedup_vs_one_at_a_time"] = (s_batched["gradients_per_s"] / bg) if bg else None
+        rec["p50_vs_one_at_a_time"] = (one["p50_ms"] / s_batched["p50_ms"]) if bg else None
+        rec["p99_vs_one_at_a_time"] = (one["p99_ms"] / s_batched["p99_ms"]) if bg else None
+        alone = {j.rid: j for j in base}
+        dj = [abs(J - alone[r].J) / max(abs(alone[r].J), 1e-300) for r, J, _ in results if r in alone]
+        dg = [np.linalg.norm(g - alone[r].grad) / max(np.linalg.norm(alone[r].grad), 1e-300)
+              for r, _, g in results if r in alone and g is not None]
+        rec["served_vs_alone"] = {"compared": len(dj), "max_rel_J": float(max(dj)) if dj else None,
+                                  "max_rel_l2_grad": float(max(dg)) if dg else None}
+    return rec
+
+
+def serve_main(args):
+    """The serving measurement alone, as its own JSON line."""
+    leg = serving_leg(args)
+    rec = {
         "metric": "served gradients/s, p50/p99 ms",
-        "value": s_batched.get("gradients_per_s"),
+        "value": leg["served"].get("gradients_per_s"),
         "unit": "gradients/s",
         "n_gpus": 1,
         "higher_is_better": True,
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "poisson_trace", "requests": args.requests, "rate_per_s": args.rate,
-                   "sizes": ["D2Q9 256x128", "D2Q9 1024x512", "D3Q19 96x48x48", "D3Q19 192x96x96"],
-                   "steps": args.serve_steps, "quantum": args.quantum, "budget_gb": args.budget_gb,
-                   "policy": args.policy, "max_active_gb": args.max_active_gb, "quantum_ms": args.quantum_ms,
-                   "request_cap_gb": args.request_cap_gb, "inplace_min_mb": args.inplace_min_mb,
-                   "trace_seed": 1},
-        "serving": s_batched,
-        "scheduler": dict(srv.stats),
+        "config": leg.pop("config"),
     }
-    del srv, ex
-    import gc
-    gc.collect()
-    torch.cuda.empty_cache()
-    if not args.no_baseline:
-        print("[bench] one-at-a-time replay", file=sys.stderr, flush=True)
-        base = run_one_at_a_time(jobs(), per_request_cap_bytes=req_cap, inplace_min_state_bytes=inpl_min)
-        rec["one_at_a_time"] = summarize(base)
-        bg = rec["one_at_a_time"].get("gradients_per_s")
-        rec["speedup_vs_one_at_a_time"] = (s_batched["gradients_per_s"] / bg) if bg else None
-        by_id = {j.rid: j for j in base}
-        dj = [abs(j.J - by_id[j.rid].J) / max(abs(by_id[j.rid].J), 1e-300) for j in served if j.rid in by_id]
-        dg = [np.linalg.norm(j.grad - by_id[j.rid].grad) / max(np.linalg.norm(by_id[j.rid].grad), 1e-300)
-              for j in served if j.rid in by_id and j.grad is not None]
-        rec["served_vs_alone"] = {"max_rel_J": float(max(dj)) if dj else None,
-                                  "max_rel_l2_grad": float(max(dg)) if dg else None}
+    rec.update(leg)
     print(json.dumps(rec), flush=True)
     return 0
 
@@ -377,7 +509,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixer", action="store_true", help="skip the mixing-duct, MRT, in-place, ping-pong and FP64 legs")
     ap.add_argument("--ping-pong", action="store_true", help="run the main evaluation with ping-pong buffers")
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--no-recompute", action="store_true", help="skip the checkpoint + recompute leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run one device copy of MB megabytes (counter calibration for profiles)")
     ap.add_argument("--serve", action="store_true",
@@ -533,7 +666,9 @@ def main(argv=None):
                    "workspace_gb": round(L.workspace_bytes / 1e9, 3), "switch": "%s(%g)" % (p["switch_fn"],
                                                                                           p["switch_param"])},
         "value_definition": "nodes x primal steps differentiated per second: one step = design set, "
-                            "recorded forward, objective, adjoint with recompute, gradient",
+                            "recorded forward, objective, adjoint, gradient; %s" % (
+                                "store-all plan: every step's moments held, nothing recomputed" if C >= N else
+                                "checkpoint every %d steps: the backward recomputes each segment" % C),
         "J": J,
         "gradients_per_s": 1e3 / ms_per_step,
         "primal_mlups": nodes / (primal_launch_ms * 1e-3) / 1e6,
@@ -575,9 +710,18 @@ def main(argv=None):
         rec["ping_pong"] = mrt_leg(dev, collision="bgk", inplace=False)
         print("[bench] FP64 leg", file=sys.stderr, flush=True)
         rec["fp64"] = mrt_leg(dev, collision="bgk", inplace=True, prec="fp64")
+    if not args.no_recompute:
+        print("[bench] checkpoint + recompute leg", file=sys.stderr, flush=True)
+        rec["recompute"] = recompute_leg(dev)
+    if not args.no_serve:
+        import gc
+        del L, O, grad
+        gc.collect()
+        torch.cuda.empty_cache()
+        rec["serving"] = serving_leg(args)
     if not args.no_cpu_baseline:
-        print("[bench] GPU timing done; timing the CPU oracle sample", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline(p, w_np.astype(np.float64), args.cpu_steps)
+        print("[bench] GPU timing done; timing the CPU oracle samples", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(args.workload)
     else:
         rec["cpu_baseline"] = None
     print(json.dumps(rec), flush=True)

@@ -53,6 +53,10 @@
 //    the single unknown population; outlet takes the unknown population at its
 //    equilibrium value; walls adiabatic (bounce-back) or Dirichlet (equilibrium
 //    at T_wall, u = 0).
+//  * heat exchanger (Section 4): its D x D heating plate at the bottom of the
+//    duct is the stretch plate_x0 <= x < plate_x1 of the y = 0 wall, across the
+//    whole width; those wall nodes hold the scalar at s_plate (Dirichlet) while
+//    the rest of the walls stay as configured.
 //  * the objective is evaluated on the pre-collision state after N steps,
 //    reconstructed at the inlet/outlet exactly as the node operators do.
 #include <complex>
@@ -150,6 +154,9 @@ struct lbmo_cfg {
   int32_t reserved3;
   double mrt_s[5];       // MRT rates of the moments e, eps, q, pi, m (viscous moments relax at 1/tau)
   double tau_s_solid;    // scalar relaxation time at w = 0 (0: tau_s everywhere)
+  int32_t plate_x0, plate_x1;  // heating plate: the bottom-wall (y = 0) nodes with
+                               // plate_x0 <= x < plate_x1, every z (none when equal)
+  double s_plate;        // scalar value the plate imposes (Dirichlet)
 };
 }
 
@@ -235,6 +242,7 @@ bool make_model(const lbmo_cfg* c, Model* m) {
   if (c->collision == COLL_MRT && c->flow_q != 19) return false;
   if (c->tau_s_solid != 0.0 && !(c->tau_s_solid > 0.5)) return false;
   if (c->inlet_mode == IN_PRESSURE && !(c->rho_in > 0.0 && c->u_cap >= 0.0 && c->u_cap < 1.0)) return false;
+  if (c->plate_x0 < 0 || c->plate_x1 < c->plate_x0 || c->plate_x1 > c->nx) return false;
   m->c = *c;
   m->F = make_lattice(c->flow_q);
   m->S = Lattice();
@@ -255,6 +263,10 @@ int node_class(const lbmo_cfg& c, int x, int y, int z) {
   if (x == c.nx - 1) return OUTLET;
   return INTERIOR;
 }
+
+// Heating plate (Section 4, heat exchanger): part of the bottom wall held at a
+// fixed scalar value; the flow still bounces back there.
+bool on_plate(const lbmo_cfg& c, int x, int y) { return y == 0 && x >= c.plate_x0 && x < c.plate_x1; }
 
 inline int64_t node_index(const lbmo_cfg& c, int x, int y, int z) {
   return (int64_t)x + (int64_t)c.nx * ((int64_t)y + (int64_t)c.ny * z);
@@ -333,7 +345,7 @@ void inlet_state(const lbmo_cfg& c, const T& P, T* rho, T* ux) {
 
 // Local node operator W^x: pre-collision (f, g) at node x -> post-collision (h, gp).
 template <class T>
-void node_op(const Model& M, int cls, int y, int z, const T* f, const T* g, const T& w, T* h, T* gp) {
+void node_op(const Model& M, int cls, int x, int y, int z, const T* f, const T* g, const T& w, T* h, T* gp) {
   const Lattice& F = M.F;
   const Lattice& S = M.S;
   const lbmo_cfg& c = M.c;
@@ -380,7 +392,9 @@ void node_op(const Model& M, int cls, int y, int z, const T* f, const T* g, cons
   if (cls == WALL) {
     for (int j = 0; j < F.q; ++j) h[j] = f[F.opp[j]];
     if (S.q) {
-      if (c.scalar_wall == S_DIRICHLET) {
+      if (on_plate(c, x, y)) {
+        for (int i = 0; i < S.q; ++i) gp[i] = T(S.wt[i] * c.s_plate);
+      } else if (c.scalar_wall == S_DIRICHLET) {
         for (int i = 0; i < S.q; ++i) gp[i] = T(S.wt[i] * c.s_wall);
       } else {
         for (int i = 0; i < S.q; ++i) gp[i] = g[S.opp[i]];
@@ -541,7 +555,7 @@ void step(const Model& M, const TW* w, const State<T>& cur, State<T>& nxt) {
         for (int j = 0; j < Q; ++j) f[j] = cur.f[j * N + n];
         for (int i = 0; i < Qs; ++i) g[i] = cur.g[i * N + n];
         T wn = T(w[n]);
-        node_op(M, node_class(c, x, y, z), y, z, f, g, wn, h, gp);
+        node_op(M, node_class(c, x, y, z), x, y, z, f, g, wn, h, gp);
         for (int j = 0; j < Q; ++j) {
           int64_t d = node_index(c, wrap(x + M.F.e[j][0], c.nx), wrap(y + M.F.e[j][1], c.ny),
                                  wrap(z + M.F.e[j][2], c.nz));
@@ -660,7 +674,7 @@ void adjoint_step(const Model& M, const double* w, const State<double>& fn, cons
           if (k < Q) f[k] += cplx(0.0, kCsH);
           else if (k < Q + Qs) g[k - Q] += cplx(0.0, kCsH);
           else wc += cplx(0.0, kCsH);
-          node_op(M, cls, y, z, f, g, wc, h, gp);
+          node_op(M, cls, x, y, z, f, g, wc, h, gp);
           double acc = 0;
           for (int j = 0; j < Q; ++j) acc += v[j] * (std::imag(h[j]) / kCsH);
           for (int i = 0; i < Qs; ++i) acc += vs[i] * (std::imag(gp[i]) / kCsH);
@@ -744,7 +758,7 @@ int lbmo_node_op(const lbmo_cfg* cfg, int x, int y, int z, const double* f, cons
   Model M;
   if (!make_model(cfg, &M)) return -1;
   double gdummy[7] = {0}, gpd[7];
-  node_op<double>(M, node_class(M.c, x, y, z), y, z, f, g ? g : gdummy, w, h, gp ? gp : gpd);
+  node_op<double>(M, node_class(M.c, x, y, z), x, y, z, f, g ? g : gdummy, w, h, gp ? gp : gpd);
   return 0;
 }
 
@@ -864,7 +878,8 @@ int lbmo_fields(const lbmo_cfg* cfg, const double* fs, const double* gs, double*
         if (cls == INTERIOR) {
           for (int a = 0; a < 3; ++a) uo[a] = m[a] / r;
         } else if (cls == WALL) {
-          if (Qs && c.scalar_wall == S_DIRICHLET) s = c.s_wall;
+          if (Qs && on_plate(c, x, y)) s = c.s_plate;
+          else if (Qs && c.scalar_wall == S_DIRICHLET) s = c.s_wall;
         } else {
           double G[kNG];
           node_globals<double>(M, cls, f, g, G);

@@ -8,8 +8,9 @@ backward(gJ) -> gJ * dJ/dw: the hand-written adjoint kernel, run N reverse
                 steps with segment recomputes from the checkpoints
                 (theorem of Section 2.2, unsteady form), then the gradient.
 
-The context (``Lbm``) holds one recorded trajectory at a time: a second
-forward on the same context before the first one's backward raises.
+The context (``Lbm``) holds one recorded trajectory at a time.  Each forward
+overwrites it, so the backward of an earlier forward whose trajectory has been
+overwritten raises instead of returning another design's gradient.
 """
 from __future__ import annotations
 
@@ -20,16 +21,16 @@ from .lbm import Lbm, lbm_objective_async
 
 class LbmObjective(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, w: torch.Tensor, solver: "LbmSolver"):
+    def forward(ctx, w: torch.Tensor, solver: "LbmSolver", record: bool):
         L = solver.lbm
-        if solver._pending:
-            raise RuntimeError("LbmObjective: a previous forward on this solver has not been back-propagated")
         L.set_design(w.detach().reshape(-1))
         L.reset()
-        L.primal_steps(solver.nsteps, record=True)
+        L.primal_steps(solver.nsteps, record=record)
         J = torch.empty(1, dtype=torch.float64, device=L.device)
         lbm_objective_async(L.ctx, J)
-        solver._pending = True
+        solver._generation += 1
+        solver._pending = record
+        ctx.generation = solver._generation
         ctx.solver = solver
         ctx.w_shape = w.shape
         ctx.w_dtype = w.dtype
@@ -39,13 +40,16 @@ class LbmObjective(torch.autograd.Function):
     def backward(ctx, gJ):
         solver = ctx.solver
         L = solver.lbm
+        if ctx.generation != solver._generation or not solver._pending:
+            raise RuntimeError("LbmObjective.backward: the recorded trajectory of this forward was overwritten "
+                               "by a later evaluation on the same solver")
         try:
             L.adjoint_steps(solver.nsteps)
             g = L.gradient()
         finally:
             solver._pending = False
         grad_w = (gJ.to(g.dtype) * g).reshape(ctx.w_shape).to(ctx.w_dtype)
-        return grad_w, None
+        return grad_w, None, None
 
 
 class LbmSolver:
@@ -60,7 +64,8 @@ class LbmSolver:
         self.differentiable = differentiable
         self.lbm = Lbm(params, nsteps=self.nsteps if differentiable else 0, precision=precision,
                        checkpoint_interval=checkpoint_interval, hbm_budget_bytes=hbm_budget_bytes, device=device)
-        self._pending = False
+        self._pending = False  # a recorded trajectory is waiting for its backward
+        self._generation = 0   # forwards run so far (a backward must belong to the latest)
 
     @property
     def dtype(self):
@@ -69,13 +74,15 @@ class LbmSolver:
     def __call__(self, w: torch.Tensor) -> torch.Tensor:
         if not self.differentiable:
             raise RuntimeError("LbmSolver built with differentiable=False offers value() only")
-        return LbmObjective.apply(w, self)
+        # record the trajectory only when a backward can follow
+        record = torch.is_grad_enabled() and w.requires_grad
+        return LbmObjective.apply(w, self, record)
 
     def value(self, w: torch.Tensor) -> float:
         """J(w) only (unrecorded forward, synchronises)."""
         L = self.lbm
-        if self._pending:
-            raise RuntimeError("LbmSolver.value: a recorded forward is waiting for its backward")
+        self._generation += 1  # overwrites any recorded trajectory
+        self._pending = False
         L.set_design(torch.as_tensor(w).reshape(-1))
         L.reset()
         L.primal_steps(self.nsteps, record=False)

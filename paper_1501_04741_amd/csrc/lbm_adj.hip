@@ -103,6 +103,8 @@ struct lbm_ctx {
   int lam_cur = 0;
   int64_t mom_seg = -1;   // trajectory segment whose moments mom holds
   bool os_active = false; // one-shot iteration running (adjoint state in lam[lam_cur])
+  bool state_lost = false; // a new design arrived after an adjoint had started: the primal
+                           // buffers may hold recomputed states, so c->cur is not h^{t-1}
   std::string err;
 };
 
@@ -896,6 +898,7 @@ void reset_times(lbm_ctx* c) {
   c->lam_cur = 0;
   c->mom_seg = -1;
   c->os_active = false;
+  c->state_lost = false;
 }
 
 lbm_status sync_check(lbm_ctx* c, const char* what) {
@@ -987,7 +990,10 @@ lbm_status lbm_set_design(lbm_ctx* c, const void* w_dev) {
   lbm_status s = dispatch<RunSetDesign>(c, w_dev);
   if (s != LBM_OK) return s;
   c->design_set = true;
-  // a recorded trajectory or adjoint of another design is no longer valid
+  // a recorded trajectory or adjoint of another design is no longer valid; once an
+  // adjoint has run, recomputed segments may have overwritten the buffer that held
+  // the primal state, so calls that read it wait for lbm_reset / lbm_set_state
+  if (c->adj_started) c->state_lost = true;
   if (c->rec_len > 0 || c->adj_started) {
     c->rec_len = 0;
     c->rec_open = false;
@@ -1015,6 +1021,7 @@ lbm_status lbm_primal_steps(lbm_ctx* c, int64_t nsteps, int32_t record) {
   if (nsteps < 0) return fail(c, LBM_EINVAL, "primal_steps: negative count");
   if (!c->design_set) return fail(c, LBM_ESTATE, "primal_steps: no design field set");
   if (c->adj_started) return fail(c, LBM_ESTATE, "primal_steps: adjoint started; call lbm_reset first");
+  if (c->state_lost) return fail(c, LBM_ESTATE, "primal_steps: primal state consumed by an adjoint; call lbm_reset");
   if (record && c->os_active) return fail(c, LBM_ESTATE, "primal_steps: one-shot running; call lbm_reset first");
   if (record && c->plan.inplace && c->cfg.nsteps == 0)
     return fail(c, LBM_ESTATE, "primal_steps: an in-place context with no horizon does not record");
@@ -1037,13 +1044,13 @@ lbm_status lbm_primal_steps(lbm_ctx* c, int64_t nsteps, int32_t record) {
 
 lbm_status lbm_objective_async(lbm_ctx* c, double* J_dev) {
   if (!c) return LBM_EINVAL;
-  if (c->adj_started) return fail(c, LBM_ESTATE, "objective: primal state consumed by the adjoint");
+  if (c->adj_started || c->state_lost) return fail(c, LBM_ESTATE, "objective: primal state consumed by the adjoint");
   return dispatch<RunObjective>(c, J_dev);
 }
 
 lbm_status lbm_objective(lbm_ctx* c, double* J_host, double* globals_host) {
   if (!c) return LBM_EINVAL;
-  if (c->adj_started) return fail(c, LBM_ESTATE, "objective: primal state consumed by the adjoint");
+  if (c->adj_started || c->state_lost) return fail(c, LBM_ESTATE, "objective: primal state consumed by the adjoint");
   lbm_status s = dispatch<RunObjective>(c, (double*)nullptr);
   if (s != LBM_OK) return s;
   double h[kNG + 1];
@@ -1085,14 +1092,15 @@ lbm_status lbm_gradient(lbm_ctx* c, void* grad_dev) {
 lbm_status lbm_fields(lbm_ctx* c, double* rho_dev, double* u_dev, double* s_dev) {
   if (!c) return LBM_EINVAL;
   if (!rho_dev || !u_dev) return fail(c, LBM_EINVAL, "fields: NULL output");
-  if (c->adj_started) return fail(c, LBM_ESTATE, "fields: primal state consumed by the adjoint");
+  if (c->adj_started || c->state_lost) return fail(c, LBM_ESTATE, "fields: primal state consumed by the adjoint");
   return dispatch<RunFields>(c, rho_dev, u_dev, s_dev);
 }
 
 lbm_status lbm_get_state(lbm_ctx* c, double* f_dev, double* g_dev) {
   if (!c) return LBM_EINVAL;
   if (!f_dev) return fail(c, LBM_EINVAL, "get_state: NULL output");
-  if (c->adj_started) return fail(c, LBM_ESTATE, "get_state: primal state consumed by the adjoint");
+  if (c->adj_started || c->state_lost)
+    return fail(c, LBM_ESTATE, "get_state: primal state consumed by the adjoint");
   return dispatch<RunGetState>(c, f_dev, g_dev);
 }
 
@@ -1113,7 +1121,8 @@ lbm_status lbm_oneshot_steps(lbm_ctx* c, int64_t nsteps, double zeta, double pen
   if (nsteps < 0) return fail(c, LBM_EINVAL, "oneshot_steps: negative count");
   if (!std::isfinite(zeta) || !std::isfinite(penalty)) return fail(c, LBM_EINVAL, "oneshot_steps: non-finite step");
   if (!c->design_set) return fail(c, LBM_ESTATE, "oneshot_steps: no design field set");
-  if (c->adj_started) return fail(c, LBM_ESTATE, "oneshot_steps: unsteady adjoint started; call lbm_reset first");
+  if (c->adj_started || c->state_lost)
+    return fail(c, LBM_ESTATE, "oneshot_steps: unsteady adjoint started; call lbm_reset first");
   return dispatch<RunOneshot>(c, nsteps, zeta, penalty);
 }
 
@@ -1150,7 +1159,8 @@ lbm_status lbm_primal_steps_batch(lbm_ctx* const* ctxs, int32_t n, int64_t nstep
   for (int k = 0; k < n; ++k) {
     lbm_ctx* c = ctxs[k];
     if (!c->design_set) return fail(c0, LBM_ESTATE, "primal_steps_batch: context %d has no design", k);
-    if (c->adj_started) return fail(c0, LBM_ESTATE, "primal_steps_batch: context %d is in its adjoint", k);
+    if (c->adj_started || c->state_lost)
+      return fail(c0, LBM_ESTATE, "primal_steps_batch: context %d is in its adjoint", k);
     if (record && !(c->rec_open && c->t == c->rec_len))
       return fail(c0, LBM_ESTATE, "primal_steps_batch: context %d cannot continue recording", k);
     if (record && c->t + nsteps > c->cfg.nsteps)

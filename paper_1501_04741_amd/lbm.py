@@ -305,8 +305,11 @@ class Lbm:
                  hbm_budget_bytes: int = 0, device=None, stream=None, workspace=None, inplace: bool = False):
         """workspace: optional caller-owned uint8 device tensor (256-byte aligned) of at
         least lbm_required_bytes; by default one is allocated with torch.empty.
-        inplace: stream in place (one buffer per state; unrecorded runs and one-shot
-        only, nsteps must be 0)."""
+        inplace: stream in place (one primal and one adjoint buffer, each read and
+        rewritten by every step).  With nsteps = 0 the context runs unrecorded steps
+        and the one-shot iteration; with nsteps > 0 a recorded run keeps the moments
+        of every step (no checkpoints, no recompute: checkpoint_interval must be 0
+        or >= nsteps) and its adjoint streams in place too."""
         library()
         self.device = torch.device(device if device is not None else "cuda")
         self.params = dict(params)

@@ -1,0 +1,83 @@
+"""Writes the oracle's whole-run results for the FP32 workloads to tests/golden/.
+
+Calls only the FP64 CPU oracle (``oracle``) and the seeded input generators
+(``paper_1501_04741_amd.inputs``, which hold none of the method's arithmetic);
+nothing here touches the GPU library.  Each file holds the objective J and the
+gradient dJ/dw of the unsteady discrete adjoint (Section 2.2, eq.
+adjoint:derivative, summed over every step) for the workload's own seeded
+design field, rounded to FP32 as the GPU run receives it.
+
+  exchanger  D2Q9+D2Q5 512x256, 20000 steps: J and the full gradient
+  mixer      D3Q19+D3Q7 128x64x64, 5000 steps: J and the full gradient
+  channel    D3Q19 256x128x128 at 200 steps (the full 2000-step horizon needs
+             more host memory than the oracle's square-root checkpointing can
+             spare): J, the gradient at 8192 interior nodes drawn with
+             PCG64(0), and the L2 norm of the full gradient
+
+Usage: python tests/golden/make_oracle_goldens.py {exchanger|mixer|channel} [threads]
+Run time on 8 host cores: about 50 min, 2-3 h and 35 min.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1501_04741_amd import inputs  # noqa: E402
+
+CASES = {
+    "exchanger": dict(workload="d2q9_d2q5_exchanger_512x256", steps=None, sample=0),
+    "mixer": dict(workload="d3q19_d3q7_mixer_128x64x64", steps=None, sample=0),
+    "channel": dict(workload="d3q19_channel_256x128x128", steps=200, sample=8192),
+}
+
+
+def golden_path(case: str) -> str:
+    return os.path.join(HERE, "oracle_%s.npz" % CASES[case]["workload"])
+
+
+def sample_nodes(params: dict, count: int) -> np.ndarray:
+    """Sorted indices of `count` distinct interior nodes, drawn with PCG64(0)."""
+    interior = np.flatnonzero(oracle.mask(params) == 0)
+    rng = np.random.Generator(np.random.PCG64(0))
+    return np.sort(rng.choice(interior, size=count, replace=False)).astype(np.int64)
+
+
+def make(case: str) -> str:
+    spec = CASES[case]
+    wl = inputs.workload(spec["workload"])
+    p = inputs.model_params(wl)
+    steps = spec["steps"] or wl["steps"]
+    w = inputs.design_for(wl).astype(np.float64)  # the FP32-rounded field the GPU run receives
+    t0 = time.time()
+    r = oracle.adjoint(p, w, steps)
+    secs = time.time() - t0
+    grad = r["grad"]
+    out = dict(workload=np.array(spec["workload"]), steps=np.int64(steps), J=np.float64(r["J"]),
+               grad_norm=np.float64(np.linalg.norm(grad)), seconds=np.float64(secs),
+               threads=np.int64(oracle.threads()))
+    if spec["sample"]:
+        idx = sample_nodes(p, spec["sample"])
+        out.update(sample_idx=idx, grad_sample=grad[idx])
+    else:
+        out.update(grad=grad)
+    path = golden_path(case)
+    np.savez_compressed(path, **out)
+    print("%s: %s, %d steps, J = %.12g, |grad| = %.6g, %.0f s on %d threads" % (
+        case, spec["workload"], steps, r["J"], out["grad_norm"], secs, out["threads"]), flush=True)
+    return path
+
+
+if __name__ == "__main__":
+    which = sys.argv[1]
+    if len(sys.argv) > 2:
+        oracle.threads(int(sys.argv[2]))
+    make(which)

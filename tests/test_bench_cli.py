@@ -22,3 +22,13 @@ def test_counter_traffic_keyed_to_sources():
     if bench.sources_sha() == bench.COUNTER_TRAFFIC["sources_sha256_16"]:
         assert bench._measured_traffic(w, "k_adjoint_inplace") == bench.COUNTER_TRAFFIC["k_adjoint_inplace"]
     assert bench._measured_traffic("another_workload", "k_adjoint_inplace") is None
+
+
+def test_cpu_baseline_reports_every_sample():
+    """The CPU oracle leg times each workload sample and reports the bench
+    workload's figure as its value, with the thread count it used."""
+    samples = (("d2q9_channel_64x32", 3), ("d2q9_d2q5_exchanger_512x256", 1))
+    r = bench.cpu_baseline("d2q9_d2q5_exchanger_512x256", samples)
+    assert r["kind"] == "oracle" and r["unit"] == "MLUPS" and r["cores"] >= 1
+    assert [s["workload"] for s in r["samples"]] == [s[0] for s in samples]
+    assert r["value"] == r["samples"][1]["mlups"] > 0

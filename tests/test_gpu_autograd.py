@@ -47,15 +47,45 @@ def test_autograd_dot_product_fp64():
     assert abs(dot - fd) <= 1e-7 * abs(fd)
 
 
-def test_second_forward_before_backward_raises():
+def test_backward_of_overwritten_forward_raises():
+    """A later forward overwrites the recorded trajectory: the earlier forward's
+    backward raises instead of returning the later design's gradient; forwards
+    under no_grad or on a w that needs no gradient record nothing and leave the
+    solver usable."""
     p = dict(flow=9, nx=16, ny=8, nz=1)
     s = LbmSolver(p, 10, precision="fp64")
     w = torch.full((128,), 0.7, dtype=torch.float64, device="cuda", requires_grad=True)
-    J = s(w)
+    J1 = s(w)
+    J2 = s(w * 0.9)
     with pytest.raises(RuntimeError):
+        J1.backward()
+    J2.backward()
+    with torch.no_grad():
         s(w)
-    J.backward()
+    s(w.detach())
+    w.grad = None
     s(w).backward()  # fine again
+    assert torch.isfinite(w.grad).all()
+
+
+def test_autograd_gradient_matches_oracle_adjoint_fp64():
+    """LbmSolver's backward (checkpoint interval 7 < N = 60, so segments are
+    recomputed) equals the FP64 oracle's unsteady adjoint at 1e-10."""
+    import oracle
+    p = dict(flow=19, scalar=7, nx=20, ny=9, nz=7, tau=0.8, tau_s=0.6, u_in=0.02, switch_fn="ramp",
+             switch_param=0.01, c_dp=0.1, c_var=1.0, s_in_lo=0.0, s_in_hi=1.0, s_split_axis=1)
+    steps = 60
+    w_np = inputs.porosity(20, 9, 7, 4, 3)
+    s = LbmSolver(p, steps, precision="fp64", checkpoint_interval=7)
+    assert s.lbm.plan()["interval"] == 7
+    w = torch.from_numpy(w_np).cuda().requires_grad_(True)
+    J = s(w)
+    J.backward()
+    ref = oracle.adjoint(p, w_np, steps)
+    g = w.grad.detach().cpu().numpy()
+    assert abs(float(J) - ref["J"]) <= 1e-10 * abs(ref["J"])
+    assert np.linalg.norm(g - ref["grad"]) <= 1e-10 * np.linalg.norm(ref["grad"])
+    s.close()
 
 
 def test_channel_256x128x128_fd_on_32_nodes():

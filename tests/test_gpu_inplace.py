@@ -183,3 +183,79 @@ def test_inplace_recorded_value_and_grad_matches_oracle():
     ref = oracle.adjoint(p, w, steps)
     assert abs(J - ref["J"]) <= 1e-10 * abs(ref["J"])
     assert np.linalg.norm(_np(g) - ref["grad"]) <= 1e-10 * np.linalg.norm(ref["grad"])
+
+
+def test_inplace_streaming_hint_variants_bitwise_equal_pingpong_fp64_256x128x128():
+    """The benchmark channel in FP64 (638 MB states, beyond twice the 256 MB
+    last-level cache) takes the in-place kernels' streaming-hint variants in both
+    phases: a recorded run with its adjoint, and an unrecorded run, against the
+    ping-pong path, bitwise, after chunks ending in both phases."""
+    wl = inputs.workload("d3q19_channel_256x128x128")
+    p = inputs.model_params(wl)
+    steps = 5
+    w = torch.from_numpy(inputs.design_for(wl, np.float64)).cuda()
+    a = Lbm(p, nsteps=steps, precision="fp64", checkpoint_interval=steps)
+    b = Lbm(p, nsteps=steps, precision="fp64", inplace=True)
+    assert b.plan()["state_bytes"] > 2 * 256 * 2**20
+    for c in (a, b):
+        c.set_design(w)
+        c.reset()
+
+    def same_state():
+        fa, _ = a.get_state()
+        fb, _ = b.get_state()
+        assert torch.equal(fa, fb)
+        del fa, fb
+
+    for k in (2, 3):
+        a.primal_steps(k, record=True)
+        b.primal_steps(k, record=True)
+        same_state()
+    assert a.objective() == b.objective()
+    for k in (1, 2, 2):
+        a.adjoint_steps(k)
+        b.adjoint_steps(k)
+        la, _ = a.get_adjoint()
+        lb, _ = b.get_adjoint()
+        assert torch.equal(la, lb)
+        del la, lb
+    assert torch.equal(a.gradient(), b.gradient())
+    a.close()
+    b.close()
+    # unrecorded: the unrecorded in-place variants beyond twice the cache
+    a = Lbm(p, nsteps=0, precision="fp64")
+    b = Lbm(p, nsteps=0, precision="fp64", inplace=True)
+    for c in (a, b):
+        c.set_design(w)
+        c.reset()
+    for k in (3, 2):
+        a.primal_steps(k)
+        b.primal_steps(k)
+        same_state()
+    a.close()
+    b.close()
+
+
+def test_set_design_after_adjoint_refuses_state_reads_until_reset():
+    """Once an adjoint has run (and recomputed segments have overwritten the
+    primal buffers), a new design invalidates the primal state: calls that read it
+    are refused until lbm_reset or lbm_set_state."""
+    p = CASES[2][1]
+    w = torch.from_numpy(inputs.porosity(p["nx"], p["ny"], p["nz"], 0, 3))
+    c = Lbm(p, nsteps=12, precision="fp64", checkpoint_interval=4)
+    c.set_design(w)
+    c.reset()
+    c.primal_steps(12, record=True)
+    c.adjoint_steps(12)
+    c.gradient()
+    c.set_design(w * 0.5)
+    for call in (c.objective, c.fields, c.get_state, lambda: c.primal_steps(1),
+                 lambda: c.oneshot_steps(1, 0.0)):
+        with pytest.raises(LbmError) as e:
+            call()
+        assert e.value.status == L.LBM_ESTATE
+    c.reset()
+    c.primal_steps(3)
+    J, _ = c.objective()
+    ref = oracle.primal(p, _np(w * 0.5).astype(np.float64), 3)
+    assert abs(J - ref["J"]) <= 1e-10 * abs(ref["J"])

@@ -579,3 +579,43 @@ def test_oneshot_penalty_update_closed_form():
     assert np.all(r["lam_f"] == 0) and np.all(r["grad"] == 0)
     rc = oracle.oneshot(p, w0, 3, 10.0, -1.0)               # pushes away from 1/2 past the bounds
     assert set(np.unique(rc["w"][interior])) <= {0.0, 1.0}
+
+
+def test_inlet_scalar_split_on_z_is_the_y_split_mirrored():
+    """The inlet scalar split on z (s_split_axis = 2) imposes s_in_lo below nz/2
+    and s_in_hi from there on, whatever y; and a whole run with the split on z is
+    the run with the split on y mirrored through the y <-> z swap of the lattice
+    (D3Q19 and D3Q7 are closed under it), state for state."""
+    e, wt, _, _ = oracle.lattice(19)
+    es, wts, _, _ = oracle.lattice(7)
+    rng = np.random.default_rng(11)
+    base = dict(flow=19, scalar=7, tau=0.8, tau_s=0.6, u_in=0.02, s_in_lo=0.2, s_in_hi=0.9,
+                switch_fn="power", switch_param=3.0, c_dp=0.1, c_var=1.0, c_hf=0.5)
+    pz = dict(base, nx=7, ny=5, nz=6, s_split_axis=2)
+    for y in (1, 2, 3):
+        for z, tin in ((1, 0.2), (2, 0.2), (3, 0.9), (4, 0.9)):
+            f = _random_state(19, rng, rho=1.01)
+            g = wts * (0.5 + 0.1 * rng.standard_normal(7))
+            _, gp = oracle.node_op(pz, 0, y, z, f, g, 0.5)
+            assert abs(gp.sum() - tin) < 1e-15
+    # mirror: (x, y, z) -> (x, z, y), velocity j -> the one with e_y and e_z swapped
+    def perm(ev):
+        return np.array([int(np.flatnonzero((ev[:, 0] == a) & (ev[:, 1] == c) & (ev[:, 2] == b))[0])
+                         for a, b, c in ev])
+    pf, ps = perm(e), perm(es)
+    nx, ny, nz = 7, 5, 6
+    py = dict(base, nx=nx, ny=nz, nz=ny, s_split_axis=1)
+    w = inputs.porosity(nx, ny, nz, 3, 3)
+    w_m = w.reshape(nz, ny, nx).transpose(1, 0, 2).reshape(-1)  # mirrored lattice: (z', y', x) = (y, z, x)
+    steps = 40
+    rz = oracle.primal(pz, w, steps)
+    ry = oracle.primal(py, w_m, steps)
+    mirror = lambda a, q: a.reshape(q, ny, nz, nx).transpose(0, 2, 1, 3).reshape(q, -1)
+    assert np.allclose(mirror(ry["f"], 19)[pf], rz["f"], rtol=0, atol=1e-14)
+    assert np.allclose(mirror(ry["g"], 7)[ps], rz["g"], rtol=0, atol=1e-14)
+    assert abs(ry["J"] - rz["J"]) <= 1e-13 * abs(rz["J"])
+    # and the adjoint through the z-split inlet: whole-run gradient against complex step
+    dw = rng.standard_normal(w.size)
+    _, dJ = oracle.directional(pz, w, dw, 30)
+    g = oracle.adjoint(pz, w, 30)["grad"]
+    assert abs(g @ dw - dJ) <= 1e-12 * abs(dJ)
