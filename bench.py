@@ -248,13 +248,14 @@ def mrt_leg(dev, steps=200, collision="mrt", inplace=True, prec="fp32"):
                         "roofline": roof(ab, adj_us)}}
 
 
-def recompute_leg(dev, workload="d3q19_channel_256x128x128"):
+def recompute_leg(dev, workload="d3q19_channel_256x128x128", inplace=True):
     """The fixed-interval checkpoint plan of the 256x128x128 channel (N = 2000,
-    FP32): the checkpoint interval C that minimises the workspace (no budget),
-    ping-pong buffers.  The recorded forward writes a full state every C steps
-    and the moments of the last segment; the backward recomputes every other
-    segment from its checkpoint before reversing it.  One warm-up evaluation,
-    one timed."""
+    FP32): the checkpoint interval C that minimises the workspace.  The recorded
+    forward keeps a full state every C steps and the moments of the last
+    segment; the backward recomputes every other segment from its checkpoint
+    before reversing it.  In place: one working buffer (copied to a checkpoint
+    every C steps) and one adjoint buffer, segments recomputed in place inside
+    their checkpoint; ping-pong: two of each.  One warm-up evaluation, one timed."""
     import torch
 
     from paper_1501_04741_amd import inputs
@@ -265,9 +266,13 @@ def recompute_leg(dev, workload="d3q19_channel_256x128x128"):
     N = int(wl["steps"])
     prec = wl["precision"]
     w = torch.from_numpy(inputs.design_for(wl)).to(dev)
-    L = Lbm(p, nsteps=N, precision=prec, device=dev)
+    L = Lbm(p, nsteps=N, precision=prec, device=dev)  # the smallest ping-pong workspace
     plan = L.plan()
     C = plan["interval"]
+    if inplace:  # the same interval, streamed in place
+        L.close()
+        L = Lbm(p, nsteps=N, precision=prec, checkpoint_interval=C, device=dev, inplace=True)
+        plan = L.plan()
     k_last = N - ((N - 1) // C) * C
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     grad = torch.empty(L.N, dtype=L.dtype, device=dev)
@@ -298,8 +303,9 @@ def recompute_leg(dev, workload="d3q19_channel_256x128x128"):
     roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
     real = "float" if prec == "fp32" else "double"
-    return {"workload": "%s, checkpoint every %d steps (%d checkpoints, %d moment sets), ping-pong" % (
-                workload, C, plan["checkpoints"], plan["moment_sets"]),
+    sfx = "_inplace" if inplace else ""
+    return {"workload": "%s, checkpoint every %d steps (%d checkpoints, %d moment sets), %s" % (
+                workload, C, plan["checkpoints"], plan["moment_sets"], "in place" if inplace else "ping-pong"),
             "lbm_steps": N, "checkpoint_interval": C, "workspace_gb": round(ws / 1e9, 3),
             "recomputed_steps": recomputed,
             "evaluation_mlups": nodes * N / ((fwd_ms + bwd_ms) * 1e-3) / 1e6,
@@ -311,12 +317,12 @@ def recompute_leg(dev, workload="d3q19_channel_256x128x128"):
                                   "frac": bwd_bytes / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                   "bytes": bwd_bytes,
                                   "note": "N adjoint launches + the recorded primal launches of the recompute"},
-            "primal": {"kernel": "k_primal<19,0,%s>" % real, "mlups": nodes / prim_us,
+            "primal": {"kernel": "k_primal%s<19,0,%s>" % (sfx, real), "mlups": nodes / prim_us,
                        "roofline": dict(roof(pb, prim_us),
-                                        traffic=_measured_traffic(workload, "k_primal"))},
-            "adjoint": {"kernel": "k_adjoint<19,0,%s>" % real, "mlups": nodes / adj_us,
+                                        traffic=_measured_traffic(workload, "k_primal" + sfx))},
+            "adjoint": {"kernel": "k_adjoint%s<19,0,%s>" % (sfx, real), "mlups": nodes / adj_us,
                         "roofline": dict(roof(ab, adj_us),
-                                         traffic=_measured_traffic(workload, "k_adjoint"))}}
+                                         traffic=_measured_traffic(workload, "k_adjoint" + sfx))}}
 
 
 def inplace_leg(dev, steps=200):
@@ -712,7 +718,8 @@ def main(argv=None):
         rec["fp64"] = mrt_leg(dev, collision="bgk", inplace=True, prec="fp64")
     if not args.no_recompute:
         print("[bench] checkpoint + recompute leg", file=sys.stderr, flush=True)
-        rec["recompute"] = recompute_leg(dev)
+        rec["recompute"] = recompute_leg(dev, inplace=True)
+        rec["recompute_ping_pong"] = recompute_leg(dev, inplace=False)
     if not args.no_serve:
         import gc
         del L, O, grad

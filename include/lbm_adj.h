@@ -102,8 +102,9 @@ typedef struct lbm_config {
                           * recorded forward run may not exceed it           */
   int64_t checkpoint_interval; /* C >= 1, or 0 = automatic (see below)       */
   uint64_t hbm_budget_bytes;   /* automatic C: 0 = the C with the smallest   *
-                          * workspace; else the largest C whose workspace    *
-                          * fits the budget (C = N, store-all, when it fits) */
+                          * workspace (in place: C = N); else the largest C  *
+                          * whose workspace fits the budget (C = N,          *
+                          * store-all, when it fits)                         */
   int32_t inlet;         /* LBM_INLET_VELOCITY: Zou-He velocity u = (u_in,0,0)*
                           * LBM_INLET_PRESSURE: Zou-He density rho_in with   *
                           * u = (u_x,0,0) from the known populations; a node *
@@ -132,14 +133,25 @@ typedef struct lbm_config {
   int32_t inplace;       /* 1: one buffer per state, streamed in place       *
                           * (alternating even/odd access patterns): one     *
                           * primal and one adjoint buffer instead of two    *
-                          * each.  A recorded run then keeps the moments of  *
-                          * every step (checkpoint_interval 0 or >= nsteps; *
-                          * LBM_ENOMEM when they exceed the budget), so the *
-                          * adjoint never needs a stored state.  With       *
-                          * nsteps = 0 only unrecorded runs and the one-shot *
-                          * iteration are available.  In-place contexts do  *
-                          * not join batched launches (LBM_EINVAL)          */
+                          * each.  A recorded run keeps the moments of every *
+                          * step (no recompute) unless checkpoint_interval  *
+                          * (1 <= C < nsteps) is given or hbm_budget_bytes   *
+                          * cannot hold them: then it keeps a full state    *
+                          * every C steps (the largest C the budget holds)  *
+                          * and the adjoint recomputes each segment in      *
+                          * place inside its checkpoint.  With nsteps = 0   *
+                          * only unrecorded runs and the one-shot iteration *
+                          * are available.  In-place contexts do not join   *
+                          * batched launches (LBM_EINVAL)                   */
   int32_t reserved3;     /* must be 0                                        */
+  int32_t plate_x0, plate_x1; /* heating plate of the heat exchanger (Section *
+                          * 4): the bottom-wall (y = 0) nodes with           *
+                          * plate_x0 <= x < plate_x1, every z, hold the      *
+                          * scalar at s_plate (Dirichlet) while the flow     *
+                          * still bounces back there; the other walls keep   *
+                          * scalar_wall.  plate_x0 = plate_x1: no plate.     *
+                          * 0 <= plate_x0 <= plate_x1 <= nx                  */
+  double s_plate;        /* scalar value of the plate                        */
 } lbm_config;
 
 /* Workspace size for cfg (cfg->nsteps and the checkpoint plan included).
@@ -205,6 +217,14 @@ lbm_status lbm_adjoint_steps(lbm_ctx* ctx, int64_t nsteps);
  * reached t = 0, or a one-shot iteration (then the last gradient estimate);
  * LBM_ESTATE otherwise.  Asynchronous. */
 lbm_status lbm_gradient(lbm_ctx* ctx, void* grad_dev);
+
+/* Same as lbm_gradient for the penalised objective J + penalty * P(w), with
+ * P = sum over interior nodes of w (1 - w) (eq. P, the term the optimiser of
+ * Section 3.3 adds with a growing weight to drive w toward 0 and 1): writes
+ * dJ/dw + penalty * (1 - 2w) at interior nodes and dJ/dw (zero) elsewhere.
+ * Same state requirements and errors as lbm_gradient, plus LBM_EINVAL for a
+ * non-finite penalty. */
+lbm_status lbm_gradient_penalty(lbm_ctx* ctx, double penalty, void* grad_dev);
 
 /* Macroscopic fields of the current pre-collision state, reconstructed at the
  * inlet/outlet like the node operators do: rho (N doubles), u (3 x N doubles,

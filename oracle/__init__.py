@@ -369,3 +369,16 @@ def oneshot(params, w, iters, zeta, c_pen=0.0, f0=None, g0=None):
                                 _dp(fN), _dp(gN), _dp(lf), _dp(lg), _dp(gr), ctypes.byref(J)), "oneshot")
     return dict(w=wa, f=fN.reshape(q, n), g=gN[: qs * n].reshape(qs, n), lam_f=lf.reshape(q, n),
                 lam_g=lg[: qs * n].reshape(qs, n), grad=gr, J=J.value)
+
+
+def penalty(params, w):
+    """P(w) = sum over interior nodes of w (1 - w) (eq. P): zero at w in {0, 1}."""
+    w = _f64(w, _sizes(_cfg(params))[0])
+    return float(np.sum((w * (1.0 - w))[mask(params) == 0]))
+
+
+def penalty_gradient(params, w, c_pen):
+    """c_pen * dP/dw = c_pen (1 - 2w) at interior nodes, 0 elsewhere (eq. P); the
+    term the optimiser adds to dJ/dw for the penalised objective J + c_pen P."""
+    w = _f64(w, _sizes(_cfg(params))[0])
+    return np.where(mask(params) == 0, c_pen * (1.0 - 2.0 * w), 0.0)

@@ -7,7 +7,8 @@ a multiply is fused into an add only inside one source expression, so the
 fusion pattern is a property of the source, not of how a node function was
 inlined.  The single-context and batched kernels share the node functions,
 and with this flag they round identically (batched results are bitwise the
-single-context ones).
+single-context ones).  The library links the profiler's marker library
+(rocprofiler-sdk-roctx) for its named ranges.
 """
 from __future__ import annotations
 
@@ -22,6 +23,8 @@ SOURCES = [os.path.join(CSRC, "lbm_adj.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in ("kernels.hpp", "lattice.hpp")] + [
     os.path.join(ROOT, "include", "lbm_adj.h")]
 ARCH = os.environ.get("LBM_OFFLOAD_ARCH", "gfx950")
+# profiler marker library (named ranges around forward, recompute and adjoint segments)
+ROCM_LIB = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
 
 
 def hipcc() -> str:
@@ -35,7 +38,7 @@ def command(out: str = LIB, extra=()) -> list:
     return [hipcc(), "--offload-arch=%s" % ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on",
             "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include"), *extra,
-            "-o", out, *SOURCES]
+            "-o", out, *SOURCES, "-L", ROCM_LIB, "-Wl,-rpath," + ROCM_LIB, "-lrocprofiler-sdk-roctx"]
 
 
 def stale() -> bool:

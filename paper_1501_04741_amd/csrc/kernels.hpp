@@ -61,6 +61,8 @@ struct Params {
   double c_dp, c_hf, c_var, c_mix;  // objective weights
   Real mrt_k[19];           // MRT: (1 - rate_k) / |U row k|^2 (interior collision U^T diag(mrt_k) U)
   Real taus_f, taus_s;      // scalar relaxation time of fluid (w = 1) and solid (w = 0), blended variant
+  int plate_x0, plate_x1;   // heating plate: y = 0 wall nodes with plate_x0 <= x < plate_x1 (none if equal)
+  Real s_plate;             // scalar value the plate holds
 };
 
 template <typename P>
@@ -520,10 +522,24 @@ __device__ __forceinline__ void collide_interior(const Params<Real>& p, Real wn,
   }
 }
 
+// Scalar condition of a wall node: Dirichlet at the heating plate (the stretch
+// plate_x0 <= x < plate_x1 of the y = 0 wall, every z: the exchanger of Section
+// 4), or at s_wall when the walls are Dirichlet; otherwise adiabatic (false).
+template <typename Real>
+__device__ __forceinline__ bool wall_dirichlet(const Params<Real>& p, int x, int y, Real& value) {
+  if (y == 0 && x >= p.plate_x0 && x < p.plate_x1) {
+    value = p.s_plate;
+    return true;
+  }
+  value = p.s_wall;
+  return p.scalar_wall == S_DIRICHLET;
+}
+
 // Wall: full-way bounce-back h_j = f_opp(j); scalar bounce-back (adiabatic)
-// or equilibrium at the wall value with u = 0 (Dirichlet).
+// or equilibrium at the wall value with u = 0 (Dirichlet, see wall_dirichlet).
 template <int Q, int QS, typename Real>
-__device__ __forceinline__ void collide_wall(const Params<Real>& p, Real (&f)[Q], Real (&g)[QS > 0 ? QS : 1]) {
+__device__ __forceinline__ void collide_wall(const Params<Real>& p, int x, int y, Real (&f)[Q],
+                                             Real (&g)[QS > 0 ? QS : 1]) {
   using L = Lat<Q>;
   using S = SLat<QS>;
   Real t[Q];
@@ -532,9 +548,10 @@ __device__ __forceinline__ void collide_wall(const Params<Real>& p, Real (&f)[Q]
 #pragma unroll
   for (int j = 0; j < Q; ++j) f[j] = t[j];
   if constexpr (QS > 0) {
-    if (p.scalar_wall == S_DIRICHLET) {
+    Real tw;
+    if (wall_dirichlet(p, x, y, tw)) {
 #pragma unroll
-      for (int i = 0; i < QS; ++i) g[i] = Real(S::w(i)) * p.s_wall;
+      for (int i = 0; i < QS; ++i) g[i] = Real(S::w(i)) * tw;
     } else {
       Real s[QS];
 #pragma unroll
@@ -768,7 +785,7 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* s
   if (cls == INTERIOR) {
     collide_interior<Q, QS, Real, V>(p, w[n], f, g);
   } else if (cls == WALL) {
-    collide_wall<Q, QS, Real>(p, f, g);
+    collide_wall<Q, QS, Real>(p, x, y, f, g);
   } else if (cls == INLET) {
     collide_inlet<Q, QS, Real>(p, y, z, f, g);
   } else {
@@ -1004,7 +1021,8 @@ __global__ __launch_bounds__(256) void k_seed(Params<Real> p, const Real* __rest
 // nodes).  Wall and velocity-inlet operators are affine in (f, g): their
 // products do not read m.  Hand-derived from the operators above.
 template <int Q, int QS, typename Real, int V = 0>
-__device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, const Real (&m)[Mom<Q, QS, V>::N],
+__device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, int x, int y,
+                                            const Real (&m)[Mom<Q, QS, V>::N],
                                             Real wn, const Real (&mu)[Q], const Real (&nu)[QS > 0 ? QS : 1],
                                             Real (&lf)[Q], Real (&lg)[QS > 0 ? QS : 1], Real& gw) {
   using L = Lat<Q>;
@@ -1018,8 +1036,10 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, cons
   if (cls == WALL) {
 #pragma unroll
     for (int j = 0; j < Q; ++j) lf[j] = mu[L::opp(j)];
+    Real tw;
+    const bool dir = wall_dirichlet(p, x, y, tw);  // Dirichlet: g' does not depend on g
 #pragma unroll
-    for (int i = 0; i < QS; ++i) lg[i] = (p.scalar_wall == S_DIRICHLET) ? Real(0) : nu[S::opp(i)];
+    for (int i = 0; i < QS; ++i) lg[i] = dir ? Real(0) : nu[S::opp(i)];
   } else if (cls == INLET) {
     // Velocity form (u_in, or u_cap where the pressure form was limited):
     // h = (1-omega) f* + omega E(rho, u) is affine in f.  Pressure form: rho is
@@ -1281,7 +1301,7 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
     for (int k = 0; k < Mom<Q, QS, V>::N; ++k) m[k] = get<NT>(mom + (size_t)k * p.Np + n);  // read once
   }
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
-  adjoint_vjp<Q, QS, Real, V>(p, cls, m, wn, mu, nu, lf, lg, gw);
+  adjoint_vjp<Q, QS, Real, V>(p, cls, x, y, m, wn, mu, nu, lf, lg, gw);
   if (cls == INTERIOR) grad[n] += gw;
   store_cot<Q, QS, Real, NT, ACC>(lam_out, b, lf, lg);
 }
@@ -1338,7 +1358,8 @@ __global__ __launch_bounds__(256) void k_fields(Params<Real> p, const Real* __re
     oy = my / r;
     oz = mz / r;
   } else if (cls == WALL) {
-    if (QS > 0 && p.scalar_wall == S_DIRICHLET) T = (double)p.s_wall;
+    Real tw;
+    if (QS > 0 && wall_dirichlet(p, x, y, tw)) T = (double)tw;
   } else {
     double s0 = 0, sk = 0;
     Real s0r = 0, skr = 0;
@@ -1500,7 +1521,7 @@ __device__ __forceinline__ void oneshot_node(const Params<Real>& p, const Real* 
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
   Real m[Mom<Q, QS, V>::N], lf[Q], lg[QSA], gw;
   node_moments<Q, QS, Real, V>(p, cls, y, z, f, g, m);
-  adjoint_vjp<Q, QS, Real, V>(p, cls, m, wn, mu, nu, lf, lg, gw);
+  adjoint_vjp<Q, QS, Real, V>(p, cls, x, y, m, wn, mu, nu, lf, lg, gw);
   if (cls == INLET || cls == OUTLET) {
     double sf[Q], sg[QSA];
     seed_values<Q, QS, Real>(p, cls, f, g, glob, sf, sg);
@@ -1512,7 +1533,7 @@ __device__ __forceinline__ void oneshot_node(const Params<Real>& p, const Real* 
   if (cls == INTERIOR) {
     collide_interior<Q, QS, Real, V>(p, wn, f, g);
   } else if (cls == WALL) {
-    collide_wall<Q, QS, Real>(p, f, g);
+    collide_wall<Q, QS, Real>(p, x, y, f, g);
   } else if (cls == INLET) {
     collide_inlet<Q, QS, Real>(p, y, z, f, g);
   } else {
@@ -1552,12 +1573,14 @@ __global__ __launch_bounds__(256) void k_oneshot_inplace(Params<Real> p, Real* a
 
 // --------------------------------------------------------- batched launches
 // One launch advances many contexts of the same (Q, QS, Real) by one step.
-// Blocks are one wave wide (64 x-nodes of one row); block b belongs to the
-// context k with start[k] <= b < start[k+1].  The per-node code is the same
-// device function as in the single-context kernels, so results are bitwise
-// identical to them.
+// Blocks cover kw consecutive waves (64 x-nodes each) of one row, kw chosen per
+// launch as the widest of 4, 3, 2, 1 waves that divides every context's waves
+// per row (so no block straddles two rows and none holds more idle lanes than
+// the row's padding to whole waves); block b belongs to the context k with
+// start[k] <= b < start[k+1].  The per-node code is the same device function
+// as in the single-context kernels, so results are bitwise identical to them.
 constexpr int kBatchMax = 32;
-constexpr int kBatchBX = 64;
+constexpr int kWave = 64;
 
 // Per-context constants, stored once in the context's own workspace.
 template <typename Real>
@@ -1565,7 +1588,7 @@ struct BatchStatic {
   Params<Real> p;
   const Real* w;
   Real* grad;
-  int gx;  // blocks per row: ceil(nx / kBatchBX)
+  int waves;  // waves per row: ceil(nx / 64)
   int nt;  // non-temporal stores
 };
 
@@ -1573,6 +1596,7 @@ struct BatchStatic {
 template <typename Real>
 struct BatchArgs {
   int n;
+  int kw;  // waves per block (blockDim.x = 64 kw), dividing every context's waves per row
   int start[kBatchMax + 1];
   const BatchStatic<Real>* st[kBatchMax];
   const Real* a[kBatchMax];  // primal: source state; adjoint: moments of f^n
@@ -1596,13 +1620,14 @@ __device__ __forceinline__ int batch_find(const BatchArgs<Real>& A, int blk) {
 }
 
 template <int Q, int QS, typename Real, int V>
-__global__ __launch_bounds__(kBatchBX) void k_primal_batch(BatchArgs<Real> A) {
+__global__ __launch_bounds__(256) void k_primal_batch(BatchArgs<Real> A) {
   const int blk = blockIdx.x;
   const int k = batch_find(A, blk);
   const BatchStatic<Real>& S = *A.st[k];
   const int lb = blk - A.start[k];
-  const int bx = lb % S.gx, row = lb / S.gx;
-  const int x = bx * kBatchBX + threadIdx.x;
+  const int gx = S.waves / A.kw;  // blocks per row
+  const int bx = lb % gx, row = lb / gx;
+  const int x = bx * (kWave * A.kw) + threadIdx.x;
   if (x >= S.p.nx) return;
   const int y = row % S.p.ny, z = row / S.p.ny;
   if (S.nt) {
@@ -1619,13 +1644,14 @@ __global__ __launch_bounds__(kBatchBX) void k_primal_batch(BatchArgs<Real> A) {
 }
 
 template <int Q, int QS, typename Real, int V>
-__global__ __launch_bounds__(kBatchBX) void k_adjoint_batch(BatchArgs<Real> A) {
+__global__ __launch_bounds__(256) void k_adjoint_batch(BatchArgs<Real> A) {
   const int blk = blockIdx.x;
   const int k = batch_find(A, blk);
   const BatchStatic<Real>& S = *A.st[k];
   const int lb = blk - A.start[k];
-  const int bx = lb % S.gx, row = lb / S.gx;
-  const int x = bx * kBatchBX + threadIdx.x;
+  const int gx = S.waves / A.kw;  // blocks per row
+  const int bx = lb % gx, row = lb / gx;
+  const int x = bx * (kWave * A.kw) + threadIdx.x;
   if (x >= S.p.nx) return;
   const int y = row % S.p.ny, z = row / S.p.ny;
   if (S.nt)
@@ -1655,6 +1681,21 @@ __global__ __launch_bounds__(256) void k_node_in(Params<Real> p, const Real* __r
   if (x >= p.nx) return;
   const int r = blockIdx.y + p.ny * blockIdx.z;
   b[x + p.pitch * r] = a[x + p.nx * r];
+}
+
+// Gradient export with the penalty term: b = a + c_pen (1 - 2w) at interior
+// nodes (the derivative of P = sum w (1 - w), eq. P), a elsewhere (zero: the
+// design acts at interior nodes only); workspace layout in, compact out.
+template <typename Real>
+__global__ __launch_bounds__(256) void k_grad_penalty(Params<Real> p, const Real* __restrict__ a,
+                                                      const Real* __restrict__ w, Real c_pen, Real* __restrict__ b) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= p.nx) return;
+  const int r = blockIdx.y + p.ny * blockIdx.z;
+  const int i = x + p.pitch * r;
+  Real v = a[i];
+  if (node_class(p, x, blockIdx.y, blockIdx.z, p.nz > 1) == INTERIOR) v += c_pen * (Real(1) - Real(2) * w[i]);
+  b[x + p.nx * r] = v;
 }
 
 template <typename Real>

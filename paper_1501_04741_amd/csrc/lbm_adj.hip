@@ -23,6 +23,15 @@
 // s = n / C is not the one held in mom, it is recomputed from ckpt[s] (C
 // primal steps through the ping-pong buffers).  With C = N (store-all) no
 // step is ever recomputed.
+//
+// In-place plan (one primal working buffer and one adjoint buffer, each read
+// and rewritten by every step in the alternating even/odd access patterns):
+// store-all keeps the state in ckpt[0] and never recomputes.  With C < N the
+// working buffer is a slot of its own; before recorded step k with k % C == 0
+// it is copied to ckpt[k / C] (in the buffer layout of phase k), and segment s
+// is recomputed in place inside ckpt[s] itself, which the backward sweep needs
+// no more once the segment's moments are rebuilt (segments are reversed in
+// decreasing order, each once).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +42,8 @@
 #include <cstring>
 #include <string>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "../../include/lbm_adj.h"
 #include "kernels.hpp"
@@ -68,7 +79,7 @@ struct Plan {
   uint64_t mom_bytes = 0;    // aligned, one moment set
   uint64_t node_bytes = 0;   // aligned Np x Real
   int64_t C = 1, S = 1;      // checkpoint interval and slots
-  bool inplace = false;      // one buffer per state (unrecorded runs and one-shot only)
+  bool inplace = false;      // one primal working buffer and one adjoint buffer, streamed in place
   uint64_t total = 0;
 };
 
@@ -92,6 +103,7 @@ struct lbm_ctx {
   void* pp[2] = {nullptr, nullptr};
   char* ckpt = nullptr;
   char* mom = nullptr;
+  void* work = nullptr;   // in place: the primal working buffer (ckpt[0] when store-all)
   // time bookkeeping
   int64_t t = 0;          // primal time: current state is h^{t-1}
   int64_t rec_len = 0;    // recorded steps (trajectory h^{-1}..h^{rec_len-1})
@@ -109,6 +121,16 @@ struct lbm_ctx {
 };
 
 namespace {
+
+// Named range on the profiler's marker timeline (rocprofv3 --marker-trace):
+// forward segments, recomputed segments, adjoint segments and one-shot runs
+// show up as spans around their kernel launches (host-side enqueue time).
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 lbm_status fail(lbm_ctx* c, lbm_status s, const char* fmt, ...) {
@@ -158,8 +180,8 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
   if (c->tau_s_solid != 0.0 && !(c->tau_s_solid > 0.5)) return bad("tau_s_solid must be 0 or exceed 1/2");
   if (c->inplace != 0 && c->inplace != 1) return bad("inplace must be 0 or 1");
   if (c->reserved3 != 0) return bad("reserved3 must be 0");
-  if (c->inplace && c->nsteps > 0 && c->checkpoint_interval > 0 && c->checkpoint_interval < c->nsteps)
-    return bad("an in-place context records the moments of every step: checkpoint_interval must be 0 or >= nsteps");
+  if (c->plate_x0 < 0 || c->plate_x1 < c->plate_x0 || c->plate_x1 > c->nx)
+    return bad("heating plate needs 0 <= plate_x0 <= plate_x1 <= nx");
   if (c->inlet == LBM_INLET_PRESSURE && !(c->rho_in > 0.0 && c->u_cap >= 0.0 && c->u_cap < 1.0))
     return bad("pressure inlet needs rho_in > 0 and 0 <= u_cap < 1");
   if (c->nsteps < 0 || c->checkpoint_interval < 0) return bad("nsteps and checkpoint_interval must be >= 0");
@@ -169,9 +191,14 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
   return LBM_OK;
 }
 
-uint64_t plan_total(const Plan& p, int64_t C, int64_t S) {
+// Workspace of a plan with checkpoint interval C and S checkpoint slots (N steps).
+// Ping-pong: 2 adjoint + 2 primal states besides the checkpoints.  In place: one
+// adjoint state, plus the working buffer unless C >= N (store-all: the state stays
+// in ckpt[0]).
+uint64_t plan_total(const Plan& p, int64_t C, int64_t S, int64_t N) {
   uint64_t t = 2 * p.node_bytes + align_up(kGlobBytes) + align_up(kDescBytes);
-  t += (uint64_t)(2 + 2 + S) * p.state_bytes + (uint64_t)C * p.mom_bytes;
+  const uint64_t extra = p.inplace ? (C >= N ? 1 : 2) : 4;
+  t += (uint64_t)(extra + S) * p.state_bytes + (uint64_t)C * p.mom_bytes;
   return t;
 }
 
@@ -198,31 +225,26 @@ lbm_status make_plan(const lbm_config* c, Plan* p, std::string* why) {
   p->state_bytes = align_up((uint64_t)p->QT * p->Np * p->rs);
   p->mom_bytes = align_up((uint64_t)mom_values(c) * p->Np * p->rs);
   p->node_bytes = align_up((uint64_t)p->Np * p->rs);
-  if (c->inplace) {
-    // the state (kept in the first checkpoint slot) and one adjoint buffer, both
-    // streamed in place; a recorded run adds the moments of every step (its
-    // adjoint then never needs a state)
-    p->inplace = true;
-    p->C = c->nsteps;
+  p->inplace = c->inplace != 0;
+  const int64_t Nst = std::max<int64_t>(c->nsteps, 1);
+  if (p->inplace && c->nsteps == 0) {
+    // unrecorded runs and the one-shot iteration only: the state and one adjoint buffer
+    p->C = 0;
     p->S = 1;
-    p->total = 2 * p->node_bytes + align_up(kGlobBytes) + align_up(kDescBytes) + 2 * p->state_bytes +
-               (uint64_t)p->C * p->mom_bytes;
-    if (c->hbm_budget_bytes && p->total > c->hbm_budget_bytes) {
-      if (why) *why = "the moments of every step do not fit hbm_budget_bytes";
-      return LBM_ENOMEM;
-    }
+    p->total = 2 * p->node_bytes + align_up(kGlobBytes) + align_up(kDescBytes) + 2 * p->state_bytes;
     return LBM_OK;
   }
-  const int64_t Nst = std::max<int64_t>(c->nsteps, 1);
   int64_t C;
   if (c->checkpoint_interval > 0) {
     C = std::min<int64_t>(c->checkpoint_interval, Nst);
+  } else if (c->hbm_budget_bytes == 0 && p->inplace) {
+    C = Nst;  // in place without a budget: every step's moments (no recompute)
   } else if (c->hbm_budget_bytes == 0) {
     // smallest workspace: minimise S*state + C*moments
     C = 1;
-    uint64_t best = plan_total(*p, 1, Nst);
+    uint64_t best = plan_total(*p, 1, Nst, Nst);
     for (int64_t cc = 2; cc <= Nst; ++cc) {
-      const uint64_t t = plan_total(*p, cc, (Nst + cc - 1) / cc);
+      const uint64_t t = plan_total(*p, cc, (Nst + cc - 1) / cc, Nst);
       if (t < best) {
         best = t;
         C = cc;
@@ -233,7 +255,7 @@ lbm_status make_plan(const lbm_config* c, Plan* p, std::string* why) {
     C = 0;
     for (int64_t cc = Nst; cc >= 1; --cc) {
       const int64_t S = (Nst + cc - 1) / cc;
-      if (plan_total(*p, cc, S) <= c->hbm_budget_bytes) {
+      if (plan_total(*p, cc, S, Nst) <= c->hbm_budget_bytes) {
         C = cc;
         break;
       }
@@ -245,7 +267,7 @@ lbm_status make_plan(const lbm_config* c, Plan* p, std::string* why) {
   }
   p->C = C;
   p->S = (Nst + C - 1) / C;
-  p->total = plan_total(*p, p->C, p->S);
+  p->total = plan_total(*p, p->C, p->S, Nst);
   return LBM_OK;
 }
 
@@ -283,6 +305,9 @@ Params<Real> make_params(const lbm_config& c, int64_t N) {
   p.c_mix = c.c_mix;
   p.taus_f = (Real)c.tau_s;
   p.taus_s = (Real)(c.tau_s_solid != 0.0 ? c.tau_s_solid : c.tau_s);
+  p.plate_x0 = c.periodic ? 0 : c.plate_x0;
+  p.plate_x1 = c.periodic ? 0 : c.plate_x1;
+  p.s_plate = (Real)c.s_plate;
   // MRT row scales (1 - rate) / |row|^2; rows of group 0 relax at 1/tau
   for (int k = 0; k < 19; ++k) {
     const int gr = Mrt19::group(k);
@@ -321,20 +346,33 @@ lbm_status launch_check(lbm_ctx* c, const char* what) {
   return LBM_OK;
 }
 
+// Waves per x row of a context (rows padded to whole waves).
+int batch_waves(const lbm_ctx* c) { return (c->cfg.nx + 63) / 64; }
+
+// Waves per block of a batched launch: the widest of 4, 3, 2, 1 that divides
+// every member's waves per row (as in the single-context launch geometry, which
+// measured 0.737 of HBM peak with one-wave blocks against 0.835 with four).
+int batch_block_waves(lbm_ctx* const* cs, int n) {
+  for (int kw = 4; kw > 1; --kw) {
+    bool all = true;
+    for (int k = 0; k < n && all; ++k) all = batch_waves(cs[k]) % kw == 0;
+    if (all) return kw;
+  }
+  return 1;
+}
+
 // Typed operations on one context.
 template <int Q, int QS, typename Real, int V = 0>
 struct Ops {
   using RealT = Real;
   static constexpr int kQ = Q, kQS = QS;
   static Params<Real> P(lbm_ctx* c) { return make_params<Real>(c->cfg, c->plan.N); }
-  static int batch_blocks(lbm_ctx* c) {
-    return (c->cfg.nx + kBatchBX - 1) / kBatchBX * c->cfg.ny * c->cfg.nz;
-  }
+  static int batch_blocks(lbm_ctx* c, int kw) { return batch_waves(c) / kw * c->cfg.ny * c->cfg.nz; }
   static void primal_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks) {
-    hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V>), dim3(blocks), dim3(kBatchBX), 0, st, A);
+    hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V>), dim3(blocks), dim3(kWave * A.kw), 0, st, A);
   }
   static void adjoint_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks) {
-    hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V>), dim3(blocks), dim3(kBatchBX), 0, st, A);
+    hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V>), dim3(blocks), dim3(kWave * A.kw), 0, st, A);
   }
 
   // streaming stores (and cotangent loads) when the state buffers a launch touches exceed the
@@ -350,12 +388,12 @@ struct Ops {
   // hints: 0.766 -> 0.741 at 256x128x128) and beyond it takes NT stores and hinted
   // loads in both phases (0.662 -> 0.750 at 512x256x128, 0.668 -> 0.815 at
   // 512x128x128; ping-pong 0.753 and 0.766).
-  static void primal_inplace(lbm_ctx* c, void* mom) {
+  static void primal_inplace(lbm_ctx* c, void* buf, int64_t t, void* mom) {
     Geo g = node_geometry(c->cfg);
-    Real* a = (Real*)c->cur;
+    Real* a = (Real*)buf;
     const Real* w = (const Real*)c->w;
     Real* m = (Real*)mom;
-    const bool even = (c->t % 2 == 0);
+    const bool even = (t % 2 == 0);
 #define LBM_PI(NTV, MOMV, ACCV) \
   hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), a, w, m)
     if (m && nt(c, 1)) {
@@ -406,7 +444,7 @@ struct Ops {
     h.p = P(c);
     h.w = (const Real*)c->w;
     h.grad = (Real*)c->grad;
-    h.gx = (c->cfg.nx + kBatchBX - 1) / kBatchBX;
+    h.waves = batch_waves(c);
     h.nt = nt(c, 2) ? 1 : 0;
     hipLaunchKernelGGL((k_write_desc<Real>), dim3(1), dim3(64), 0, c->stream, h, (BatchStatic<Real>*)c->desc);
     return launch_check(c, "descriptor upload");
@@ -523,6 +561,11 @@ struct Ops {
     Geo g = node_geometry(c->cfg);
     hipLaunchKernelGGL((k_node_in<Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)a, (Real*)b);
   }
+  static void grad_penalty(lbm_ctx* c, double pen, void* b) {
+    Geo g = node_geometry(c->cfg);
+    hipLaunchKernelGGL((k_grad_penalty<Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)c->grad,
+                       (const Real*)c->w, (Real)pen, (Real*)b);
+  }
   static void node_out(lbm_ctx* c, const void* a, void* b) {
     Geo g = node_geometry(c->cfg);
     hipLaunchKernelGGL((k_node_out<Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)a, (Real*)b);
@@ -572,8 +615,11 @@ template <class O>
 struct RunPrimal {
   static lbm_status run(lbm_ctx* c, int64_t nsteps, int record) {
     if (c->plan.inplace) {
+      const bool ckpts = record && c->work != ckpt_slot(c, 0);  // checkpointed plan (C < N)
       for (int64_t i = 0; i < nsteps; ++i) {
-        O::primal_inplace(c, record ? mom_slot(c, c->t) : nullptr);
+        if (ckpts && c->t % c->plan.C == 0)  // the state at t = sC, in its phase's layout
+          O::copy(c, c->work, ckpt_slot(c, c->t / c->plan.C), (size_t)c->plan.QT * c->plan.Np);
+        O::primal_inplace(c, c->work, c->t, record ? mom_slot(c, c->t) : nullptr);
         ++c->t;
       }
       return launch_check(c, "in-place primal step");
@@ -605,6 +651,7 @@ struct RunObjective {
 // recording their moments (the states themselves go through the ping-pong).
 template <class O>
 void recompute_segment(lbm_ctx* c, int64_t s) {
+  Range r("lbm recompute segment");
   const int64_t C = c->plan.C;
   const int64_t end = std::min<int64_t>(s * C + C, c->rec_len);
   const void* src = ckpt_slot(c, s);
@@ -613,6 +660,19 @@ void recompute_segment(lbm_ctx* c, int64_t s) {
     O::primal(c, src, dst, mom_slot(c, k));
     src = dst;
   }
+  c->mom_seg = s;
+}
+
+// In-place plan: recompute segment s inside its own checkpoint slot (its last
+// use), recording the moments of steps sC .. min(sC + C, N) - 1; step k runs in
+// the access pattern of its phase k mod 2, the layout the slot was saved in.
+template <class O>
+void recompute_segment_inplace(lbm_ctx* c, int64_t s) {
+  Range r("lbm recompute segment (in place)");
+  const int64_t C = c->plan.C;
+  const int64_t end = std::min<int64_t>(s * C + C, c->rec_len);
+  void* buf = ckpt_slot(c, s);
+  for (int64_t k = s * C; k < end; ++k) O::primal_inplace(c, buf, k, mom_slot(c, k));
   c->mom_seg = s;
 }
 
@@ -634,9 +694,11 @@ struct RunAdjoint {
   static lbm_status run(lbm_ctx* c, int64_t nsteps) {
     const int64_t C = c->plan.C;
     if (!c->adj_started) start_adjoint<O>(c);
-    if (c->plan.inplace) {  // every step's moments are held: no recompute
+    if (c->plan.inplace) {  // store-all never recomputes; C < N recomputes each segment in place
       for (int64_t i = 0; i < nsteps; ++i) {
         const int64_t n = c->t_adj - 1;
+        const int64_t s = n / C;
+        if (s != c->mom_seg) recompute_segment_inplace<O>(c, s);
         O::adjoint_inplace(c, mom_slot(c, n), c->rec_len - c->t_adj);
         --c->t_adj;
       }
@@ -654,10 +716,14 @@ struct RunAdjoint {
   }
 };
 
+// The buffer that holds the state at t = 0: the in-place working buffer, or
+// checkpoint slot 0 (ping-pong: the first checkpoint itself).
+void* initial_buffer(lbm_ctx* c) { return c->plan.inplace ? c->work : ckpt_slot(c, 0); }
+
 template <class O>
 struct RunReset {
   static lbm_status run(lbm_ctx* c) {
-    O::fill(c, ckpt_slot(c, 0), (size_t)c->plan.QT * c->plan.Np);
+    O::fill(c, initial_buffer(c), (size_t)c->plan.QT * c->plan.Np);
     return launch_check(c, "reset");
   }
 };
@@ -665,7 +731,7 @@ struct RunReset {
 template <class O>
 struct RunSetState {
   static lbm_status run(lbm_ctx* c, const double* f, const double* g) {
-    O::set_state(c, f, g, ckpt_slot(c, 0));
+    O::set_state(c, f, g, initial_buffer(c));
     return launch_check(c, "set_state");
   }
 };
@@ -675,6 +741,14 @@ struct RunGradient {
   static lbm_status run(lbm_ctx* c, void* out) {
     O::node_out(c, c->grad, out);
     return launch_check(c, "gradient");
+  }
+};
+
+template <class O>
+struct RunGradientPenalty {
+  static lbm_status run(lbm_ctx* c, double pen, void* out) {
+    O::grad_penalty(c, pen, out);
+    return launch_check(c, "gradient_penalty");
   }
 };
 
@@ -774,6 +848,7 @@ struct RunPrimalBatch {
     BatchArgs<Real> A;
     std::memset(&A, 0, sizeof A);
     A.n = n;
+    A.kw = batch_block_waves(cs, n);
     for (int64_t i = 0; i < nsteps; ++i) {
       int total = 0;
       for (int k = 0; k < n; ++k) {
@@ -785,7 +860,7 @@ struct RunPrimalBatch {
         A.b[k] = nullptr;
         A.c[k] = (Real*)dst;
         A.m[k] = record ? (Real*)mom_slot(c, c->t) : nullptr;
-        total += O::batch_blocks(c);
+        total += O::batch_blocks(c, A.kw);
         c->cur = dst;
         ++c->t;
       }
@@ -828,6 +903,11 @@ struct RunAdjointBatch {
         ++nn;
       }
       for (int64_t r = 0; r < longest; ++r) {
+        lbm_ctx* mem[kBatchMax];  // the contexts with a recompute step r left
+        int nm = 0;
+        for (int q = 0; q < nn; ++q)
+          if (first[q] + r <= last[q]) mem[nm++] = need[q];
+        A.kw = batch_block_waves(mem, nm);
         int m = 0, total = 0;
         for (int q = 0; q < nn; ++q) {
           const int64_t kk = first[q] + r;
@@ -840,7 +920,7 @@ struct RunAdjointBatch {
           A.b[m] = nullptr;
           A.c[m] = (Real*)dst;
           A.m[m] = (Real*)mom_slot(c, kk);
-          total += O::batch_blocks(c);
+          total += O::batch_blocks(c, A.kw);
           src[q] = dst;
           ++m;
         }
@@ -852,6 +932,7 @@ struct RunAdjointBatch {
       // one reverse step for every context
       int total = 0;
       A.n = n;
+      A.kw = batch_block_waves(cs, n);
       for (int k = 0; k < n; ++k) {
         lbm_ctx* c = cs[k];
         const int64_t nstep = c->t_adj - 1;
@@ -861,7 +942,7 @@ struct RunAdjointBatch {
         A.m[k] = nullptr;
         A.b[k] = (const Real*)c->lam[c->lam_cur];
         A.c[k] = (Real*)c->lam[1 - c->lam_cur];
-        total += O::batch_blocks(c);
+        total += O::batch_blocks(c, A.kw);
         c->lam_cur ^= 1;
         --c->t_adj;
       }
@@ -892,7 +973,7 @@ void reset_times(lbm_ctx* c) {
   c->t = 0;
   c->rec_len = 0;
   c->rec_open = true;
-  c->cur = ckpt_slot(c, 0);
+  c->cur = initial_buffer(c);
   c->adj_started = false;
   c->t_adj = -1;
   c->lam_cur = 0;
@@ -953,6 +1034,10 @@ lbm_status lbm_create(const lbm_config* cfg, void* hip_stream, void* workspace_d
     c->lam[0] = c->lam[1] = q;  // one adjoint buffer, rewritten in place
     q += p.state_bytes;
     c->pp[0] = c->pp[1] = nullptr;
+    if (cfg->nsteps > 0 && p.C < cfg->nsteps) {  // checkpointed: a working buffer of its own
+      c->work = q;
+      q += p.state_bytes;
+    }
   } else {
     for (int i = 0; i < 2; ++i) {
       c->lam[i] = q;
@@ -967,6 +1052,7 @@ lbm_status lbm_create(const lbm_config* cfg, void* hip_stream, void* workspace_d
   q += (uint64_t)p.S * p.state_bytes;
   c->mom = q;
   q += (uint64_t)p.C * p.mom_bytes;
+  if (p.inplace && !c->work) c->work = c->ckpt;  // store-all / unrecorded: the state lives in ckpt[0]
   reset_times(c);
   s = dispatch<RunReset>(c);
   if (s == LBM_OK) s = dispatch<RunWriteStatic>(c);
@@ -1033,6 +1119,7 @@ lbm_status lbm_primal_steps(lbm_ctx* c, int64_t nsteps, int32_t record) {
                   (long long)(c->t + nsteps), (long long)c->cfg.nsteps);
   }
   if (nsteps == 0) return LBM_OK;
+  Range r(record ? "lbm_primal_steps (recorded)" : "lbm_primal_steps");
   lbm_status s = dispatch<RunPrimal>(c, nsteps, (int)(record != 0));
   if (record) {
     c->rec_len = c->t;
@@ -1078,6 +1165,7 @@ lbm_status lbm_adjoint_steps(lbm_ctx* c, int64_t nsteps) {
   } else if (nsteps > c->t_adj) {
     return fail(c, LBM_EINVAL, "adjoint_steps: only %lld steps remain", (long long)c->t_adj);
   }
+  Range r("lbm_adjoint_steps");
   return dispatch<RunAdjoint>(c, nsteps);
 }
 
@@ -1087,6 +1175,15 @@ lbm_status lbm_gradient(lbm_ctx* c, void* grad_dev) {
   if (!(c->adj_started && c->t_adj == 0) && !c->os_active)
     return fail(c, LBM_ESTATE, "gradient: adjoint has not reached t = 0 and no one-shot iteration ran");
   return dispatch<RunGradient>(c, grad_dev);
+}
+
+lbm_status lbm_gradient_penalty(lbm_ctx* c, double penalty, void* grad_dev) {
+  if (!c) return LBM_EINVAL;
+  if (!grad_dev) return fail(c, LBM_EINVAL, "gradient_penalty: NULL output");
+  if (!std::isfinite(penalty)) return fail(c, LBM_EINVAL, "gradient_penalty: non-finite weight");
+  if (!(c->adj_started && c->t_adj == 0) && !c->os_active)
+    return fail(c, LBM_ESTATE, "gradient_penalty: adjoint has not reached t = 0 and no one-shot iteration ran");
+  return dispatch<RunGradientPenalty>(c, penalty, grad_dev);
 }
 
 lbm_status lbm_fields(lbm_ctx* c, double* rho_dev, double* u_dev, double* s_dev) {
@@ -1123,6 +1220,7 @@ lbm_status lbm_oneshot_steps(lbm_ctx* c, int64_t nsteps, double zeta, double pen
   if (!c->design_set) return fail(c, LBM_ESTATE, "oneshot_steps: no design field set");
   if (c->adj_started || c->state_lost)
     return fail(c, LBM_ESTATE, "oneshot_steps: unsteady adjoint started; call lbm_reset first");
+  Range r("lbm_oneshot_steps");
   return dispatch<RunOneshot>(c, nsteps, zeta, penalty);
 }
 
@@ -1167,6 +1265,7 @@ lbm_status lbm_primal_steps_batch(lbm_ctx* const* ctxs, int32_t n, int64_t nstep
       return fail(c0, LBM_EINVAL, "primal_steps_batch: context %d would exceed its horizon", k);
   }
   if (nsteps == 0) return LBM_OK;
+  Range r("lbm_primal_steps_batch");
   s = dispatch<RunPrimalBatch>(c0, ctxs, (int)n, nsteps, (int)(record != 0));
   for (int k = 0; k < n; ++k) {
     if (record) ctxs[k]->rec_len = ctxs[k]->t;
@@ -1196,6 +1295,7 @@ lbm_status lbm_adjoint_steps_batch(lbm_ctx* const* ctxs, int32_t n, int64_t nste
     // still seed, so that a zero-step call behaves like the single-context form
     return dispatch<RunAdjointBatch>(c0, ctxs, (int)n, (int64_t)0);
   }
+  Range r("lbm_adjoint_steps_batch");
   return dispatch<RunAdjointBatch>(c0, ctxs, (int)n, nsteps);
 }
 

@@ -81,6 +81,9 @@ class LbmConfig(ctypes.Structure):
         ("tau_s_solid", ctypes.c_double),
         ("inplace", ctypes.c_int32),
         ("reserved3", ctypes.c_int32),
+        ("plate_x0", ctypes.c_int32),
+        ("plate_x1", ctypes.c_int32),
+        ("s_plate", ctypes.c_double),
     ]
 
 NG = 9  # boundary sums ("globals") lbm_objective returns
@@ -94,6 +97,7 @@ MODEL_DEFAULTS = dict(
     switch_fn="power", switch_param=3.0, c_dp=1.0, c_hf=0.0, c_var=0.0,
     inlet="velocity", rho_in=1.0, u_cap=0.0, c_mix=0.0,
     collision="bgk", mrt_rates=(1.19, 1.4, 1.2, 1.4, 1.98), tau_s_solid=0.0,
+    plate_x0=0, plate_x1=0, s_plate=1.0,
 )
 
 
@@ -119,7 +123,8 @@ def make_config(params: dict, nsteps: int, precision: str = "fp32", checkpoint_i
         checkpoint_interval=int(checkpoint_interval), hbm_budget_bytes=int(hbm_budget_bytes), inlet=im,
         reserved1=0, rho_in=float(p["rho_in"]), u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]), collision=co,
         reserved2=0, mrt_rates=(ctypes.c_double * 5)(*[float(v) for v in p["mrt_rates"]]),
-        tau_s_solid=float(p["tau_s_solid"]), inplace=1 if inplace else 0, reserved3=0)
+        tau_s_solid=float(p["tau_s_solid"]), inplace=1 if inplace else 0, reserved3=0,
+        plate_x0=int(p["plate_x0"]), plate_x1=int(p["plate_x1"]), s_plate=float(p["s_plate"]))
 
 
 _lock = threading.Lock()
@@ -154,6 +159,7 @@ def library():
             "lbm_objective_async": [vp, vp],
             "lbm_adjoint_steps": [vp, i64],
             "lbm_gradient": [vp, vp],
+            "lbm_gradient_penalty": [vp, d, vp],
             "lbm_fields": [vp, vp, vp, vp],
             "lbm_get_state": [vp, vp, vp],
             "lbm_get_adjoint": [vp, vp, vp],
@@ -243,6 +249,10 @@ def lbm_adjoint_steps(ctx, nsteps: int):
 
 def lbm_gradient(ctx, grad):
     _chk(library().lbm_gradient(ctx, _ptr(grad)), "lbm_gradient", ctx)
+
+
+def lbm_gradient_penalty(ctx, penalty: float, grad):
+    _chk(library().lbm_gradient_penalty(ctx, float(penalty), _ptr(grad)), "lbm_gradient_penalty", ctx)
 
 
 def lbm_fields(ctx, rho, u, s=None):
@@ -373,10 +383,14 @@ class Lbm:
     def adjoint_steps(self, nsteps: int):
         lbm_adjoint_steps(self.ctx, nsteps)
 
-    def gradient(self, out=None):
+    def gradient(self, out=None, penalty: float = 0.0):
+        """dJ/dw; with penalty != 0 the gradient of J + penalty * sum w (1 - w)."""
         if out is None:
             out = torch.empty(self.N, dtype=self.dtype, device=self.device)
-        lbm_gradient(self.ctx, out)
+        if penalty:
+            lbm_gradient_penalty(self.ctx, penalty, out)
+        else:
+            lbm_gradient(self.ctx, out)
         return out
 
     def fields(self):

@@ -34,7 +34,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_config_struct_size_matches(lib):
     cfg = lbm.make_config(dict(flow=9, nx=16, ny=8), 10)
-    assert cfg.struct_size == ctypes.sizeof(lbm.LbmConfig) == 256
+    assert cfg.struct_size == ctypes.sizeof(lbm.LbmConfig) == 272
     bad = lbm.make_config(dict(flow=9, nx=16, ny=8), 10)
     bad.struct_size = 150
     out = ctypes.c_uint64()
@@ -58,6 +58,10 @@ def test_config_struct_size_matches(lib):
     (dict(flow=9, nx=16, ny=8, inlet="pressure", rho_in=1.05, u_cap=1.0), False),
     (dict(flow=9, nx=16, ny=8, inlet="pressure", rho_in=1.05, u_cap=-0.1), False),
     (dict(flow=9, nx=16, ny=8, inlet=2), False),
+    (dict(flow=19, scalar=7, nx=16, ny=8, nz=6, plate_x0=4, plate_x1=12), True),
+    (dict(flow=19, scalar=7, nx=16, ny=8, nz=6, plate_x0=4, plate_x1=17), False),   # beyond nx
+    (dict(flow=19, scalar=7, nx=16, ny=8, nz=6, plate_x0=9, plate_x1=8), False),    # reversed
+    (dict(flow=19, scalar=7, nx=16, ny=8, nz=6, plate_x0=-1, plate_x1=8), False),
     (dict(flow=19, nx=16, ny=8, nz=6, collision="mrt"), True),
     (dict(flow=9, nx=16, ny=8, collision="mrt"), False),                     # MRT is D3Q19 only
     (dict(flow=19, nx=16, ny=8, nz=6, collision="mrt", mrt_rates=(1.19, 1.4, 1.2, 1.4, 2.0)), False),
@@ -107,7 +111,9 @@ def test_checkpoint_plan_sizes(lib):
 
 def test_inplace_workspace_holds_two_states(lib):
     """An in-place context keeps one primal and one adjoint buffer: two states
-    fewer than the smallest ping-pong plan of the same lattice, no moments."""
+    fewer than the smallest ping-pong plan of the same lattice, no moments; a
+    recorded in-place plan keeps every step's moments, or checkpoints every C
+    steps plus a working buffer."""
     p = dict(flow=19, nx=256, ny=128, nz=128)
     state = 19 * 256 * 128 * 128 * 4
     small = lbm.lbm_required_bytes(lbm.make_config(p, 0))
@@ -119,7 +125,23 @@ def test_inplace_workspace_holds_two_states(lib):
     rec = lbm.lbm_required_bytes(lbm.make_config(p, 10, inplace=True))
     mom = 4 * 256 * 128 * 128 * 4
     assert rec == inpl + 10 * mom
-    with pytest.raises(lbm.LbmError):
-        lbm.lbm_required_bytes(lbm.make_config(p, 10, checkpoint_interval=3, inplace=True))
-    with pytest.raises(lbm.LbmError):
-        lbm.lbm_required_bytes(lbm.make_config(p, 10, hbm_budget_bytes=inpl + 5 * mom, inplace=True))
+    # with a checkpoint interval C < N: the working buffer, one adjoint buffer, a
+    # state every C steps and the moments of one segment
+    st = lbm.lbm_required_bytes(lbm.make_config(p, 0, inplace=True)) // 2
+    c3 = lbm.lbm_required_bytes(lbm.make_config(p, 10, checkpoint_interval=3, inplace=True))
+    assert abs(c3 - (inpl + 4 * state + 3 * mom)) < 4 * 2 ** 20
+    # a budget that cannot hold every step's moments picks the largest C that fits
+    all100 = lbm.lbm_required_bytes(lbm.make_config(p, 100, inplace=True))
+    assert all100 == inpl + 100 * mom
+    budget = 5 * 10 ** 9
+    assert all100 > budget
+    b = lbm.lbm_required_bytes(lbm.make_config(p, 100, hbm_budget_bytes=budget, inplace=True))
+    assert b <= budget
+    need = {C: lbm.lbm_required_bytes(lbm.make_config(p, 100, checkpoint_interval=C, inplace=True))
+            for C in range(1, 101)}
+    best = max(C for C in need if need[C] <= budget)   # the largest C whose plan fits
+    assert best < 100 and b == need[best]
+    S = -(-100 // best)
+    assert abs(b - (inpl + S * state + best * mom)) < 4 * 2 ** 20
+    with pytest.raises(lbm.LbmError):   # not even the smallest plan fits
+        lbm.lbm_required_bytes(lbm.make_config(p, 100, hbm_budget_bytes=inpl + mom, inplace=True))

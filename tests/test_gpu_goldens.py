@@ -1,0 +1,85 @@
+"""Whole runs of the FP32 workloads at full size against the FP64 oracle's own
+whole-run results (J and dJ/dw of the unsteady discrete adjoint, Section 2.2),
+stored in tests/golden/ by make_oracle_goldens.py, which calls only the oracle:
+
+  exchanger  D2Q9+D2Q5 512x256, 20000 steps, checkpoint every 500 (segments
+             recomputed): J and the full gradient
+  mixer      D3Q19+D3Q7 128x64x64, 5000 steps, the smallest-workspace plan:
+             J and the full gradient
+  channel    D3Q19 256x128x128, 200 steps, in the benchmark's launch
+             configuration (in place, every step's moments held) and in the
+             checkpointed plan with recompute: J, the gradient at 8192 seeded
+             interior nodes and the norm of the full gradient
+
+Bars: |J - J_ref| <= 1e-4 |J_ref|, ||g - g_ref||_2 <= 1e-3 ||g_ref||_2."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1501_04741_amd import inputs
+from paper_1501_04741_amd.lbm import Lbm
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(workload):
+    path = os.path.join(GOLDEN, "oracle_%s.npz" % workload)
+    if not os.path.exists(path):
+        pytest.skip("oracle golden %s not generated (tests/golden/make_oracle_goldens.py)" % os.path.basename(path))
+    return np.load(path, allow_pickle=False)
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("name", ["d2q9_d2q5_exchanger_512x256", "d3q19_d3q7_mixer_128x64x64"])
+def test_full_length_fp32_run_matches_oracle_golden(name):
+    ref = _golden(name)
+    wl = inputs.workload(name)
+    p = inputs.model_params(wl)
+    N = int(wl["steps"])
+    assert int(ref["steps"]) == N
+    ctx = Lbm(p, nsteps=N, precision="fp32", checkpoint_interval=wl["checkpoint_interval"])
+    J, g = ctx.value_and_grad(torch.from_numpy(inputs.design_for(wl)))
+    g = _np(g)
+    plan = ctx.plan()
+    ctx.close()
+    gr = ref["grad"]
+    err = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    print("%s (C = %d): J %.10g oracle %.10g (rel %.2e), gradient rel-L2 %.2e" % (
+        name, plan["interval"], J, float(ref["J"]), abs(J / float(ref["J"]) - 1), err))
+    assert plan["interval"] < N  # segments were recomputed
+    assert abs(J - float(ref["J"])) <= 1e-4 * abs(float(ref["J"]))
+    assert err <= 1e-3
+
+
+@pytest.mark.parametrize("plan", ["inplace_store_all", "checkpoint_recompute"])
+def test_channel_256x128x128_fp32_matches_oracle_golden(plan):
+    name = "d3q19_channel_256x128x128"
+    ref = _golden(name)
+    wl = inputs.workload(name)
+    p = inputs.model_params(wl)
+    N = int(ref["steps"])
+    if plan == "inplace_store_all":
+        ctx = Lbm(p, nsteps=N, precision="fp32", hbm_budget_bytes=int(wl["hbm_budget_gb"] * 2**30), inplace=True)
+        assert ctx.plan()["moment_sets"] == N
+    else:
+        ctx = Lbm(p, nsteps=N, precision="fp32")
+        assert ctx.plan()["interval"] < N
+    J, g = ctx.value_and_grad(torch.from_numpy(inputs.design_for(wl)))
+    g = _np(g)
+    ctx.close()
+    idx = ref["sample_idx"]
+    gs = ref["grad_sample"]
+    err = np.linalg.norm(g[idx] - gs) / np.linalg.norm(gs)
+    norm_err = abs(np.linalg.norm(g) / float(ref["grad_norm"]) - 1)
+    print("%s %s: J %.10g oracle %.10g, sampled gradient rel-L2 %.2e, norm %.2e" % (
+        name, plan, J, float(ref["J"]), err, norm_err))
+    assert abs(J - float(ref["J"])) <= 1e-4 * abs(float(ref["J"]))
+    assert err <= 1e-3
+    assert norm_err <= 1e-3

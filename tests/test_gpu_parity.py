@@ -205,3 +205,25 @@ def test_fp32_mixer_128x64x64_short():
 def test_fp32_channel_256x128x128_short():
     wl = inputs.workload("d3q19_channel_256x128x128")
     _fp32_check(inputs.model_params(wl), 3, interval=2)
+
+
+@pytest.mark.parametrize("p", [SMALL[2], SMALL[6]], ids=["q9_s5", "q19_s7"])
+def test_penalised_gradient_export_matches_oracle(p):
+    """lbm_gradient_penalty: dJ/dw + c (1 - 2w) at interior nodes (eq. P) after
+    the unsteady adjoint and after one-shot iterations, FP64, 1e-10."""
+    steps, pen = 50, 0.03
+    w = _design(p, 2)
+    L = Lbm(p, nsteps=steps, precision="fp64", checkpoint_interval=9)
+    L.value_and_grad(torch.from_numpy(w))
+    gp = _np(L.gradient(penalty=pen))
+    ref = oracle.adjoint(p, w, steps)["grad"] + oracle.penalty_gradient(p, w, pen)
+    assert np.linalg.norm(gp - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert np.array_equal(_np(L.gradient(penalty=0.0)), _np(L.gradient()))
+    L.close()
+    O = Lbm(p, nsteps=0, precision="fp64")
+    O.set_design(torch.from_numpy(w))
+    O.reset()
+    O.oneshot_steps(20, 0.0, 0.0)   # zeta = 0: the design stays w
+    ro = oracle.oneshot(p, w, 20, 0.0)
+    ref = ro["grad"] + oracle.penalty_gradient(p, w, -pen)
+    assert np.linalg.norm(_np(O.gradient(penalty=-pen)) - ref) <= 1e-10 * np.linalg.norm(ref)

@@ -58,6 +58,32 @@ def test_batched_abi_bitwise_equals_single(kind, prec):
         assert np.array_equal(c.gradient().cpu().numpy(), g)
 
 
+@pytest.mark.parametrize("widths", [(256, 512, 1024), (256, 192, 300), (384, 192, 576), (128, 130)],
+                         ids=["4_waves", "mixed_1", "3_waves", "2_vs_3"])
+def test_batched_block_widths_bitwise_equal_single(widths):
+    """Batched launches take blocks of up to four waves when every member's row
+    splits into them (256/512/1024-wide rows: four; 384/192/576: three; otherwise
+    fewer): results stay bitwise those of the single-context kernels, including
+    recomputed segments batched with members of other widths."""
+    ps = [_p(9, 0, nx, 7, 1) for nx in widths]
+    steps = 21
+    intervals = [4, 21, 6, 5][: len(ps)]
+    ws = [inputs.porosity(p["nx"], p["ny"], p["nz"], 10 + i, 3) for i, p in enumerate(ps)]
+    ref = [_alone(p, w, steps, "fp64", c) for p, w, c in zip(ps, ws, intervals)]
+    ctxs = [Lbm(p, nsteps=steps, precision="fp64", checkpoint_interval=c) for p, c in zip(ps, intervals)]
+    for c, w in zip(ctxs, ws):
+        c.set_design(torch.from_numpy(w))
+        c.reset()
+    handles = [c.ctx for c in ctxs]
+    L.lbm_primal_steps_batch(handles, steps, record=True)
+    Js = [c.objective()[0] for c in ctxs]
+    for k in (3, steps - 3):
+        L.lbm_adjoint_steps_batch(handles, k)
+    for c, (J, g), Jb in zip(ctxs, ref, Js):
+        assert Jb == J
+        assert np.array_equal(c.gradient().cpu().numpy(), g)
+
+
 def test_batched_abi_rejects_mixed_kinds_and_bad_state():
     a = Lbm(_p(9, 0, 20, 8, 1), nsteps=4, precision="fp32")
     b = Lbm(_p(19, 0, 8, 6, 5), nsteps=4, precision="fp32")

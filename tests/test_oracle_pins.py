@@ -619,3 +619,20 @@ def test_inlet_scalar_split_on_z_is_the_y_split_mirrored():
     _, dJ = oracle.directional(pz, w, dw, 30)
     g = oracle.adjoint(pz, w, 30)["grad"]
     assert abs(g @ dw - dJ) <= 1e-12 * abs(dJ)
+
+
+def test_penalty_and_its_gradient():
+    """P = sum_interior w (1 - w) (eq. P) vanishes on a 0/1 design, peaks at 1/2,
+    and its gradient equals central differences of P node by node."""
+    p = dict(flow=9, nx=12, ny=6, nz=1)
+    interior = oracle.mask(p) == 0
+    assert oracle.penalty(p, np.where(np.arange(72) % 3 == 0, 1.0, 0.0)) == 0.0
+    assert abs(oracle.penalty(p, np.full(72, 0.5)) - 0.25 * interior.sum()) < 1e-15
+    w = inputs.porosity(12, 6, 1, 4, 3)
+    g = oracle.penalty_gradient(p, w, 0.7)
+    eps = 1e-6
+    for k in range(72):
+        wp = w.copy(); wp[k] += eps
+        wm = w.copy(); wm[k] -= eps
+        fd = 0.7 * (oracle.penalty(p, wp) - oracle.penalty(p, wm)) / (2 * eps)
+        assert abs(fd - g[k]) < 1e-9
