@@ -166,6 +166,24 @@ lbm_status lbm_required_bytes(const lbm_config* cfg, uint64_t* bytes_out);
 lbm_status lbm_create(const lbm_config* cfg, void* hip_stream, void* workspace_dev,
                       uint64_t workspace_bytes, lbm_ctx** ctx_out);
 
+/* Same as lbm_create, for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops or harnesses that forbid allocation):
+ * the workspace is the library's own static device array of
+ * lbm_static_workspace_bytes() bytes (128 MiB) on the current device, held
+ * until the process ends; nothing is allocated.  One static context may be
+ * alive per device at a time; every static context on a device reuses the same
+ * array (lbm_destroy waits for the context's stream unless it is being
+ * captured, so the next one starts on a quiet array; work of a destroyed
+ * context still queued on a captured stream races with the next context).
+ * Results equal those of a context from lbm_create bitwise.
+ * Errors: LBM_EINVAL (bad cfg), LBM_ENOMEM (lbm_required_bytes(cfg) exceeds the
+ * static array), LBM_ESTATE (another static context is alive on the device),
+ * LBM_EHIP (the array's device address cannot be obtained). */
+lbm_status lbm_create_static(const lbm_config* cfg, void* hip_stream, lbm_ctx** ctx_out);
+
+/* Size of the static device workspace lbm_create_static carves from. */
+uint64_t lbm_static_workspace_bytes(void);
+
 /* Destroys the host object; the workspace is not touched (caller-owned). */
 lbm_status lbm_destroy(lbm_ctx* ctx);
 

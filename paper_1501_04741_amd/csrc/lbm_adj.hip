@@ -40,6 +40,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -117,6 +118,7 @@ struct lbm_ctx {
   bool os_active = false; // one-shot iteration running (adjoint state in lam[lam_cur])
   bool state_lost = false; // a new design arrived after an adjoint had started: the primal
                            // buffers may hold recomputed states, so c->cur is not h^{t-1}
+  int static_dev = -1;     // device whose static workspace this context uses (-1: caller's)
   std::string err;
 };
 
@@ -988,6 +990,24 @@ lbm_status sync_check(lbm_ctx* c, const char* what) {
   return LBM_OK;
 }
 
+// ------------------------------------------------- static device workspace
+// For callers that cannot allocate device memory (code under HIP graph
+// capture, allocation-free serving loops): lbm_create_static carves the
+// context from this file-scope array instead of a caller's workspace.  Each
+// device holds its own copy until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns for the current device (the
+// array's name in host code is a host-side stand-in, not a device address).
+constexpr uint64_t kStaticWorkspaceBytes = 128ull << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+struct StaticSlot {
+  void* ptr = nullptr;  // device address of scratch on this device
+  bool busy = false;    // a static context is alive on this device
+};
+std::mutex g_static_mu;
+StaticSlot g_static[kMaxDevices];
+
 }  // namespace
 
 // ================================================================= C ABI
@@ -1064,8 +1084,54 @@ lbm_status lbm_create(const lbm_config* cfg, void* hip_stream, void* workspace_d
   return LBM_OK;
 }
 
+lbm_status lbm_create_static(const lbm_config* cfg, void* hip_stream, lbm_ctx** ctx_out) {
+  if (!ctx_out) return LBM_EINVAL;
+  *ctx_out = nullptr;
+  uint64_t need = 0;
+  lbm_status s = lbm_required_bytes(cfg, &need);
+  if (s != LBM_OK) return s;
+  if (need > kStaticWorkspaceBytes) {
+    fprintf(stderr, "lbm_create_static: the configuration needs %llu bytes, the static workspace holds %llu\n",
+            (unsigned long long)need, (unsigned long long)kStaticWorkspaceBytes);
+    return LBM_ENOMEM;
+  }
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return LBM_EHIP;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  StaticSlot& slot = g_static[dev];
+  if (!slot.ptr) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      fprintf(stderr, "lbm_create_static: hipGetSymbolAddress: %s\n", hipGetErrorString(e));
+      return LBM_EHIP;
+    }
+    slot.ptr = ptr;
+  }
+  if (slot.busy) {
+    fprintf(stderr, "lbm_create_static: another static context is alive on device %d\n", dev);
+    return LBM_ESTATE;
+  }
+  s = lbm_create(cfg, hip_stream, slot.ptr, kStaticWorkspaceBytes, ctx_out);
+  if (s != LBM_OK) return s;
+  slot.busy = true;
+  (*ctx_out)->static_dev = dev;
+  return LBM_OK;
+}
+
+uint64_t lbm_static_workspace_bytes(void) { return kStaticWorkspaceBytes; }
+
 lbm_status lbm_destroy(lbm_ctx* ctx) {
   if (!ctx) return LBM_EINVAL;
+  if (ctx->static_dev >= 0) {
+    // the next static context on this device reuses the array: let this
+    // context's queued work finish first (unless its stream is being captured)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(ctx->stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+      (void)hipStreamSynchronize(ctx->stream);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    g_static[ctx->static_dev].busy = false;
+  }
   delete ctx;
   return LBM_OK;
 }

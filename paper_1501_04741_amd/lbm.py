@@ -150,6 +150,7 @@ def library():
         sig = {
             "lbm_required_bytes": [cfgp, P(u64)],
             "lbm_create": [cfgp, vp, vp, u64, P(vp)],
+            "lbm_create_static": [cfgp, vp, P(vp)],
             "lbm_destroy": [vp],
             "lbm_set_design": [vp, vp],
             "lbm_reset": [vp],
@@ -175,6 +176,8 @@ def library():
             fn = getattr(lib, name)
             fn.argtypes = args
             fn.restype = ctypes.c_int
+        lib.lbm_static_workspace_bytes.argtypes = []
+        lib.lbm_static_workspace_bytes.restype = ctypes.c_uint64
         lib.lbm_last_error.argtypes = [vp]
         lib.lbm_last_error.restype = ctypes.c_char_p
         lib.lbm_status_string.argtypes = [ctypes.c_int]
@@ -207,6 +210,17 @@ def lbm_create(cfg: LbmConfig, stream_handle: int, workspace_ptr: int, workspace
     _chk(library().lbm_create(ctypes.byref(cfg), ctypes.c_void_p(stream_handle), ctypes.c_void_p(workspace_ptr),
                               workspace_bytes, ctypes.byref(ctx)), "lbm_create")
     return ctx
+
+
+def lbm_create_static(cfg: LbmConfig, stream_handle: int):
+    ctx = ctypes.c_void_p()
+    _chk(library().lbm_create_static(ctypes.byref(cfg), ctypes.c_void_p(stream_handle), ctypes.byref(ctx)),
+         "lbm_create_static")
+    return ctx
+
+
+def lbm_static_workspace_bytes() -> int:
+    return int(library().lbm_static_workspace_bytes())
 
 
 def lbm_destroy(ctx):
@@ -314,7 +328,9 @@ class Lbm:
     def __init__(self, params: dict, nsteps: int, precision: str = "fp32", checkpoint_interval: int = 0,
                  hbm_budget_bytes: int = 0, device=None, stream=None, workspace=None, inplace: bool = False):
         """workspace: optional caller-owned uint8 device tensor (256-byte aligned) of at
-        least lbm_required_bytes; by default one is allocated with torch.empty.
+        least lbm_required_bytes; by default one is allocated with torch.empty;
+        "static": the library's static device workspace (lbm_create_static, no
+        allocation; one such context per device at a time).
         inplace: stream in place (one primal and one adjoint buffer, each read and
         rewritten by every step).  With nsteps = 0 the context runs unrecorded steps
         and the one-shot iteration; with nsteps > 0 a recorded run keeps the moments
@@ -332,6 +348,13 @@ class Lbm:
         self.nsteps = nsteps
         self.workspace_bytes = lbm_required_bytes(self.cfg)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if isinstance(workspace, str) and workspace == "static":
+            # the library's static device workspace: nothing is allocated
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                self.ctx = lbm_create_static(self.cfg, self.stream.cuda_stream)
+            self._design = None
+            return
         if workspace is None:
             workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
         elif workspace.numel() < self.workspace_bytes or workspace.data_ptr() % 256:
