@@ -136,7 +136,9 @@ def oneshot_bytes(p, precision):
 
 def mixer_leg(dev, steps=4000, os_iters=400):
     """Forward steps and one-shot iterations on the paper's mixing duct (450x50x50
-    D3Q19 + D3Q7, pressure inlet with velocity limit, mixing objective), FP32."""
+    D3Q19 + D3Q7, pressure inlet with velocity limit, mixing objective), FP32:
+    ping-pong and in place; the one-shot iteration streams in place (one primal
+    and one adjoint buffer), the ping-pong one-shot is reported beside it."""
     import torch
 
     from paper_1501_04741_amd import inputs
@@ -190,13 +192,14 @@ def mixer_leg(dev, steps=4000, os_iters=400):
     return {"workload": "d3q19_d3q7_mixer_empty_450x50x50", "nodes": nodes,
             "primal": {"kernel": "k_primal<19,7,float>", "steps_timed": steps, "mlups": nodes / prim_us,
                        "roofline": roof(pb, prim_us)},
-            "oneshot": {"kernel": "k_oneshot<19,7,float>", "iterations_timed": os_iters, "mlups": nodes / os_us,
-                        "roofline": roof(ob, os_us)},
+            "oneshot": {"kernel": "k_oneshot_inplace<19,7,float>", "iterations_timed": os_iters,
+                        "mlups": nodes / osi_us, "roofline": roof(ob, osi_us)},
             "primal_inplace": {"kernel": "k_primal_inplace<19,7,float>", "steps_timed": steps, "mlups": nodes / pi_us,
                                "roofline": roof(pb, pi_us)},
-            "oneshot_inplace": {"kernel": "k_oneshot_inplace<19,7,float>", "iterations_timed": os_iters,
-                                "mlups": nodes / osi_us, "roofline": roof(ob, osi_us)},
-            "note": "two primal states (234 MB) fit the 256 MB last-level cache; the one-shot's four do not"}
+            "oneshot_ping_pong": {"kernel": "k_oneshot<19,7,float>", "iterations_timed": os_iters,
+                                  "mlups": nodes / os_us, "roofline": roof(ob, os_us)},
+            "note": "two primal states (234 MB) fit the 256 MB last-level cache; the ping-pong one-shot's four "
+                    "do not, the in-place one-shot's two do"}
 
 
 def mrt_leg(dev, steps=200, collision="mrt", inplace=True, prec="fp32"):
@@ -323,6 +326,60 @@ def recompute_leg(dev, workload="d3q19_channel_256x128x128", inplace=True):
             "adjoint": {"kernel": "k_adjoint%s<19,0,%s>" % (sfx, real), "mlups": nodes / adj_us,
                         "roofline": dict(roof(ab, adj_us),
                                          traffic=_measured_traffic(workload, "k_adjoint" + sfx))}}
+
+
+def batched_leg(dev, n_ctx=8, steps=100):
+    """Batched launches at HBM scale: n_ctx D3Q19 FP32 channels of 128x96x96 (90 MB
+    state each, 1.4 GB per ping-pong step over eight of them), every step's moments
+    held, advanced by one k_primal_batch / k_adjoint_batch launch per step; the
+    same contexts one at a time with the single-context kernels for comparison."""
+    import numpy as np
+    import torch
+
+    from paper_1501_04741_amd import inputs
+    from paper_1501_04741_amd import lbm as L
+    from paper_1501_04741_amd.lbm import Lbm
+
+    p = dict(inputs.SERVE_SIZES[3], nx=128, ny=96, nz=96)
+    p.pop("filter")
+    p.update(c_dp=1.0, c_hf=0.0, c_var=0.0)
+    ws = [torch.from_numpy(inputs.porosity(128, 96, 96, 100 + k, 5, np.float32)).to(dev) for k in range(n_ctx)]
+    ctxs = [Lbm(p, nsteps=steps, precision="fp32", checkpoint_interval=steps, device=dev) for _ in range(n_ctx)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    h = [c.ctx for c in ctxs]
+    for rep_ in range(2):  # the second pass is timed
+        for c, w in zip(ctxs, ws):
+            c.set_design(w)
+            c.reset()
+        ev[0].record()
+        L.lbm_primal_steps_batch(h, steps, record=True)
+        ev[1].record()
+        L.lbm_adjoint_steps_batch(h, 1)
+        ev[2].record()
+        L.lbm_adjoint_steps_batch(h, steps - 1)
+        ev[3].record()
+    # the same work one context at a time (single-context kernels)
+    for c, w in zip(ctxs, ws):
+        c.set_design(w)
+        c.reset()
+    ev[4].record()
+    for c in ctxs:
+        c.primal_steps(steps, record=True)
+    ev[5].record()
+    torch.cuda.synchronize()
+    for c in ctxs:
+        c.close()
+    pb, ab = algorithmic_bytes(p, "fp32")
+    prim_us = ev[0].elapsed_time(ev[1]) * 1e3 / steps
+    adj_us = ev[2].elapsed_time(ev[3]) * 1e3 / (steps - 1)
+    single_us = ev[4].elapsed_time(ev[5]) * 1e3 / (steps * n_ctx)
+    roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
+    return {"workload": "%d x D3Q19 128x96x96 FP32 channels, %d recorded steps, every step's moments held" % (
+                n_ctx, steps),
+            "primal": {"kernel": "k_primal_batch<19,0,float>", "roofline": roof(n_ctx * pb, prim_us)},
+            "adjoint": {"kernel": "k_adjoint_batch<19,0,float>", "roofline": roof(n_ctx * ab, adj_us)},
+            "primal_single_context": {"kernel": "k_primal<19,0,float>", "roofline": roof(pb, single_us)}}
 
 
 def inplace_leg(dev, steps=200):
@@ -716,6 +773,8 @@ def main(argv=None):
         rec["ping_pong"] = mrt_leg(dev, collision="bgk", inplace=False)
         print("[bench] FP64 leg", file=sys.stderr, flush=True)
         rec["fp64"] = mrt_leg(dev, collision="bgk", inplace=True, prec="fp64")
+        print("[bench] batched leg", file=sys.stderr, flush=True)
+        rec["batched"] = batched_leg(dev)
     if not args.no_recompute:
         print("[bench] checkpoint + recompute leg", file=sys.stderr, flush=True)
         rec["recompute"] = recompute_leg(dev, inplace=True)

@@ -111,7 +111,15 @@ typedef struct lbm_config {
                           * whose u_x would exceed u_cap (> 0) takes the     *
                           * velocity form at u_cap instead (Section 4 limits *
                           * the inlet velocity; this is the reading)         */
-  int32_t reserved1;     /* must be 0                                        */
+  int32_t n_avg;         /* objective averaged over the last n_avg states of *
+                          * the horizon, J = (1/W) sum of the objective over *
+                          * f^{N-W+1} .. f^N with W = max(n_avg, 1) and N =  *
+                          * nsteps (needs nsteps >= n_avg): lbm_objective    *
+                          * returns the mean once a run from t = 0 reaches   *
+                          * t = N, and the adjoint of such a recorded run    *
+                          * adds (1/W) dJ/df^n at each window state.  0 or 1:*
+                          * the final state only.  Contexts with n_avg > 1   *
+                          * do not join batched launches (LBM_EINVAL)        */
   double rho_in;         /* pressure inlet density (> 0)                     */
   double u_cap;          /* pressure inlet velocity limit, 0 <= u_cap < 1;   *
                           * 0 = no limit                                     */
@@ -210,7 +218,9 @@ lbm_status lbm_set_state(lbm_ctx* ctx, const double* f_dev, const double* g_dev)
 lbm_status lbm_primal_steps(lbm_ctx* ctx, int64_t nsteps, int32_t record);
 
 /* Objective of the current pre-collision state f^t (the node-sum objective
- * of eq. objective:function through the boundary "Globals").  Synchronises.
+ * of eq. objective:function through the boundary "Globals"); with n_avg > 1
+ * and a run from t = 0 at t = nsteps, the mean over the window (see
+ * lbm_config.n_avg; the globals stay those of f^t).  Synchronises.
  * globals_host (nullable) receives 9 doubles: sum inlet rho, inlet count,
  * sum outlet rho, outlet count, sum outlet u_x*s, sum outlet s,
  * sum outlet s^2, sum outlet u_x, sum outlet u_x*s^2.

@@ -64,6 +64,8 @@ class Config(ctypes.Structure):
         ("plate_x0", ctypes.c_int32),
         ("plate_x1", ctypes.c_int32),
         ("s_plate", ctypes.c_double),
+        ("n_avg", ctypes.c_int32),
+        ("reserved4", ctypes.c_int32),
     ]
 
 NG = 9  # boundary sums ("globals") the objective is built from
@@ -75,7 +77,7 @@ DEFAULTS = dict(
     switch_fn="power", switch_param=3.0, c_dp=1.0, c_hf=0.0, c_var=0.0,
     inlet="velocity", rho_in=1.0, u_cap=0.0, c_mix=0.0,
     collision="bgk", mrt_rates=(1.19, 1.4, 1.2, 1.4, 1.98), tau_s_solid=0.0,
-    plate_x0=0, plate_x1=0, s_plate=1.0,
+    plate_x0=0, plate_x1=0, s_plate=1.0, n_avg=1,
 )
 CONFIG_KEYS = tuple(DEFAULTS)
 
@@ -153,6 +155,7 @@ def make_config(params: dict) -> Config:
         u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]), collision=co, reserved3=0,
         mrt_s=(ctypes.c_double * 5)(*[float(v) for v in p["mrt_rates"]]), tau_s_solid=float(p["tau_s_solid"]),
         plate_x0=int(p["plate_x0"]), plate_x1=int(p["plate_x1"]), s_plate=float(p["s_plate"]),
+        n_avg=int(p["n_avg"]), reserved4=0,
     )
 
 

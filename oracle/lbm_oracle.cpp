@@ -22,7 +22,8 @@
 //    walls (Section 3, node classes); a passive scalar on the first 5/7
 //    velocities relaxed by BGK (Section 3, heat-transfer lattice)
 //  * objective F = sum over nodes of node functions (eq. objective:function),
-//    here through a few boundary sums ("Globals", Section 3.4)
+//    here through a few boundary sums ("Globals", Section 3.4); optionally
+//    averaged over the last n_avg states of the run
 //  * the discrete adjoint of the unsteady N-step map: reverse streaming
 //    (Lemma 1, S^{-1}) followed by the transposed local Jacobian
 //    (eq. adjoint:operator), and the gradient sum_j v_j dW_j/dw
@@ -157,6 +158,8 @@ struct lbmo_cfg {
   int32_t plate_x0, plate_x1;  // heating plate: the bottom-wall (y = 0) nodes with
                                // plate_x0 <= x < plate_x1, every z (none when equal)
   double s_plate;        // scalar value the plate imposes (Dirichlet)
+  int32_t n_avg;         // objective = mean over the last n_avg states (<= 1: the final state)
+  int32_t reserved4;
 };
 }
 
@@ -243,6 +246,7 @@ bool make_model(const lbmo_cfg* c, Model* m) {
   if (c->tau_s_solid != 0.0 && !(c->tau_s_solid > 0.5)) return false;
   if (c->inlet_mode == IN_PRESSURE && !(c->rho_in > 0.0 && c->u_cap >= 0.0 && c->u_cap < 1.0)) return false;
   if (c->plate_x0 < 0 || c->plate_x1 < c->plate_x0 || c->plate_x1 > c->nx) return false;
+  if (c->n_avg < 0) return false;
   m->c = *c;
   m->F = make_lattice(c->flow_q);
   m->S = Lattice();
@@ -598,6 +602,10 @@ T objective_of(const Model& M, const State<T>& st, T* Gout) {
   return objective_from_globals(M, G);
 }
 
+// Length W of the averaging window of the unsteady objective: J is the mean of
+// the node-sum objective over the states f^{N-W+1} .. f^N (W = 1: f^N alone).
+int64_t window(const lbmo_cfg& c) { return c.n_avg > 1 ? c.n_avg : 1; }
+
 // dJ/df^N at every node, by the chain rule J = Phi(G), G = sum_x phi(f(x)):
 // dPhi/dG by complex step on Phi, dphi/df_k(x) by complex step on phi.
 void objective_seed(const Model& M, const State<double>& st, double* J, State<double>& lam) {
@@ -768,12 +776,16 @@ int lbmo_primal(const lbmo_cfg* cfg, const double* w, const double* f0, const do
                 double* fN, double* gN, double* globals, double* J) {
   Model M;
   if (!make_model(cfg, &M) || nsteps < 0) return -1;
+  const int64_t W = window(M.c);
+  if (W > 1 && nsteps < W) return -1;  // the window reaches back before f^1
   State<double> a, b;
   init_state(M, f0, g0, a);
   b.resize(M);
+  double Jsum = 0.0;  // objectives of the window's states before the last
   for (int64_t s = 0; s < nsteps; ++s) {
     step(M, w, a, b);
     std::swap(a, b);
+    if (W > 1 && s + 1 >= nsteps - W + 1 && s + 1 < nsteps) Jsum += objective_of(M, a, (double*)nullptr);
   }
   if (fN) std::memcpy(fN, a.f.data(), sizeof(double) * a.f.size());
   if (gN && M.S.q) std::memcpy(gN, a.g.data(), sizeof(double) * a.g.size());
@@ -781,7 +793,7 @@ int lbmo_primal(const lbmo_cfg* cfg, const double* w, const double* f0, const do
   double Jv = objective_of(M, a, G);
   if (globals)
     for (int k = 0; k < kNG; ++k) globals[k] = G[k];
-  if (J) *J = Jv;
+  if (J) *J = (W > 1) ? (Jsum + Jv) / (double)W : Jv;
   return 0;
 }
 
@@ -793,14 +805,19 @@ int lbmo_directional(const lbmo_cfg* cfg, const double* w, const double* dw, int
   if (!make_model(cfg, &M) || nsteps < 0) return -1;
   std::vector<cplx> wc(M.n);
   for (int64_t n = 0; n < M.n; ++n) wc[n] = cplx(w[n], kCsH * dw[n]);
+  const int64_t W = window(M.c);
+  if (W > 1 && nsteps < W) return -1;
   State<cplx> a, b;
   init_state(M, nullptr, nullptr, a);
   b.resize(M);
+  cplx Jsum(0.0, 0.0);
   for (int64_t s = 0; s < nsteps; ++s) {
     step(M, wc.data(), a, b);
     std::swap(a, b);
+    if (W > 1 && s + 1 >= nsteps - W + 1 && s + 1 < nsteps) Jsum += objective_of<cplx>(M, a, nullptr);
   }
   cplx Jc = objective_of<cplx>(M, a, nullptr);
+  if (W > 1) Jc = (Jsum + Jc) / (double)W;
   if (J) *J = std::real(Jc);
   if (dJ) *dJ = std::imag(Jc) / kCsH;
   return 0;
@@ -816,17 +833,29 @@ int lbmo_adjoint(const lbmo_cfg* cfg, const double* w, const double* f0, const d
   const int64_t N = nsteps;
   int64_t C = 1;
   while (C * C < N) ++C;
+  const int64_t W = window(M.c);
+  if (W > 1 && N < W) return -1;
   std::vector<State<double>> ckpt;
   State<double> cur, nxt;
   init_state(M, f0, g0, cur);
   nxt.resize(M);
+  double Jsum = 0.0;
   for (int64_t s = 0; s < N; ++s) {
     if (s % C == 0) ckpt.push_back(cur);
     step(M, w, cur, nxt);
     std::swap(cur, nxt);
+    if (W > 1 && s + 1 >= N - W + 1 && s + 1 < N) Jsum += objective_of(M, cur, (double*)nullptr);
   }
-  State<double> lam, lam_prev;
-  objective_seed(M, cur, J, lam);  // lam^N = dJ/df^N
+  State<double> lam, lam_prev, src;
+  double JN = 0.0;
+  objective_seed(M, cur, &JN, lam);  // lam^N = dJ/df^N
+  if (J) *J = (W > 1) ? (Jsum + JN) / (double)W : JN;
+  // averaged objective: every state of the window contributes (1/W) dPhi/df^n
+  auto scale = [&](State<double>& st) {
+    for (double& v : st.f) v /= (double)W;
+    for (double& v : st.g) v /= (double)W;
+  };
+  if (W > 1) scale(lam);
   std::vector<double> gw(M.n, 0.0);
   std::vector<State<double>> seg;
   for (int64_t k = (int64_t)ckpt.size() - 1; k >= 0; --k) {
@@ -841,6 +870,12 @@ int lbmo_adjoint(const lbmo_cfg* cfg, const double* w, const double* f0, const d
     for (int64_t s = n1 - 1; s >= n0; --s) {
       adjoint_step(M, w, seg[s - n0], lam, lam_prev, gw.data());
       std::swap(lam, lam_prev);
+      if (W > 1 && s >= N - W + 1) {  // lam^s += (1/W) dPhi/df^s
+        objective_seed(M, seg[s - n0], nullptr, src);
+        scale(src);
+        for (size_t i = 0; i < lam.f.size(); ++i) lam.f[i] += src.f[i];
+        for (size_t i = 0; i < lam.g.size(); ++i) lam.g[i] += src.g[i];
+      }
     }
   }
   if (grad) std::memcpy(grad, gw.data(), sizeof(double) * M.n);

@@ -5,7 +5,7 @@
 // with lbm_oracle.cpp into one host executable).  It covers the node classes and
 // options of the oracle: D2Q9 + D2Q5 and D3Q19 + D3Q7, periodic boxes, velocity
 // and pressure inlets, Dirichlet and adiabatic walls with a heating plate, MRT
-// collision and blended diffusivity.  Exit status 0 when every call succeeded and
+// collision, blended diffusivity and the time-averaged objective.  Exit status 0 when every call succeeded and
 // returned finite results; any sanitizer report aborts the run.
 #include <cmath>
 #include <complex>
@@ -30,6 +30,7 @@ struct lbmo_cfg {
   double tau_s_solid;
   int32_t plate_x0, plate_x1;
   double s_plate;
+  int32_t n_avg, reserved4;
 };
 int lbmo_threads(int n);
 int lbmo_lattice(int q, int32_t* e, double* wt, int32_t* opp, double* cs2);
@@ -154,6 +155,7 @@ int main() {
   lbmo_cfg c = base(9, 5, 14, 7, 1);
   c.scalar_wall = 1;
   c.s_split_axis = 1;
+  c.n_avg = 4;
   cases.push_back(c);
   c = base(19, 7, 9, 6, 5);
   c.s_split_axis = 2;

@@ -978,7 +978,7 @@ __device__ __forceinline__ void seed_values(const Params<Real>& p, int cls, cons
 template <int Q, int QS, typename Real>
 __device__ __forceinline__ void seed_node(const Params<Real>& p, const Real* __restrict__ src,
                                           const double* __restrict__ glob, Real* __restrict__ lam, int x, int y,
-                                          int z, int pattern, int inplace_out) {
+                                          int z, int pattern, int inplace_out, double scale) {
   using L = Lat<Q>;
   using S = SLat<QS>;
   constexpr bool is3d = (Q == 19);
@@ -997,20 +997,98 @@ __device__ __forceinline__ void seed_node(const Params<Real>& p, const Real* __r
   double lf[Q], lg[QS > 0 ? QS : 1];
   seed_values<Q, QS, Real>(p, cls, f, g, glob, lf, lg);
   // in place, lambda^N enters in the layout the first (odd-pattern) adjoint step
-  // reads: lambda_j(x) in slot opp(j) of x
+  // reads: lambda_j(x) in slot opp(j) of x.  scale: 1, or 1/W for an objective
+  // averaged over the last W states
 #pragma unroll
-  for (int j = 0; j < Q; ++j) lam[own_addr<QT>(b, inplace_out ? L::opp(j) : j)] = (Real)lf[j];
+  for (int j = 0; j < Q; ++j) lam[own_addr<QT>(b, inplace_out ? L::opp(j) : j)] = (Real)(lf[j] * scale);
 #pragma unroll
-  for (int i = 0; i < QS; ++i) lam[own_addr<QT>(b, Q + (inplace_out ? S::opp(i) : i))] = (Real)lg[i];
+  for (int i = 0; i < QS; ++i) lam[own_addr<QT>(b, Q + (inplace_out ? S::opp(i) : i))] = (Real)(lg[i] * scale);
 }
 
 template <int Q, int QS, typename Real>
 __global__ __launch_bounds__(256) void k_seed(Params<Real> p, const Real* __restrict__ src,
                                               const double* __restrict__ glob, Real* __restrict__ lam, int pattern,
-                                              int inplace_out) {
+                                              int inplace_out, double scale) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= p.nx) return;
-  seed_node<Q, QS, Real>(p, src, glob, lam, x, blockIdx.y, blockIdx.z, pattern, inplace_out);
+  seed_node<Q, QS, Real>(p, src, glob, lam, x, blockIdx.y, blockIdx.z, pattern, inplace_out, scale);
+}
+
+// ------------------------------------------- time-averaged objective window
+// With J = (1/W) sum of the objective over the states f^{N-W+1} .. f^N, each
+// window state is captured after the step that produces it: its inlet and
+// outlet columns (pre-collision, as pulled; bnd layout [side][Qt][row], row =
+// y + ny z) and, through the objective kernels, its boundary sums and objective.
+// The adjoint adds (1/W) dJ/df^n of every window state n < N to lambda^n.
+template <int Q, int QS, typename Real>
+__global__ __launch_bounds__(256) void k_capture_columns(Params<Real> p, const Real* __restrict__ src, int pattern,
+                                                         Real* __restrict__ bnd) {
+  constexpr int QT = Q + QS;
+  const int plane = p.ny * p.nz;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 2 * plane) return;
+  const int side = k / plane, r = k - side * plane;
+  const int y = r % p.ny, z = r / p.ny;
+  const Nbr b = make_nbr(p, side ? p.nx - 1 : 0, y, z);
+  Real f[Q], g[QS > 0 ? QS : 1];
+  load_state_rt<Q, QS, Real>(src, b, pattern, f, g);
+  Real* o = bnd + (size_t)side * QT * plane + r;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) o[(size_t)j * plane] = f[j];
+#pragma unroll
+  for (int i = 0; i < QS; ++i) o[(size_t)(Q + i) * plane] = g[i];
+}
+
+// lambda^n += scale * dJ/df^n at the inlet and outlet nodes, from the captured
+// columns of f^n and its boundary sums glob; lambda^n in the cotangent layout
+// pattern (ACC_PP: slot j of x; ACC_ODD: slot opp(j) of x; ACC_EVEN: slot j of
+// x - e_j), as the adjoint step left it.
+template <int Q, int QS, typename Real>
+__global__ __launch_bounds__(256) void k_window_seed(Params<Real> p, const Real* __restrict__ bnd,
+                                                     const double* __restrict__ glob, Real* __restrict__ lam,
+                                                     int pattern, double scale) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  constexpr bool is3d = (Q == 19);
+  constexpr int QT = Q + QS;
+  const int plane = p.ny * p.nz;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 2 * plane) return;
+  const int side = k / plane, r = k - side * plane;
+  const int y = r % p.ny, z = r / p.ny;
+  const int x = side ? p.nx - 1 : 0;
+  const int cls = node_class(p, x, y, z, is3d);
+  if (cls != INLET && cls != OUTLET) return;
+  const Nbr b = make_nbr(p, x, y, z);
+  const Real* o = bnd + (size_t)side * QT * plane + r;
+  Real f[Q], g[QS > 0 ? QS : 1];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) f[j] = o[(size_t)j * plane];
+#pragma unroll
+  for (int i = 0; i < (QS > 0 ? QS : 1); ++i) g[i] = QS > 0 ? o[(size_t)(Q + i) * plane] : Real(0);
+  double lf[Q], lg[QS > 0 ? QS : 1];
+  seed_values<Q, QS, Real>(p, cls, f, g, glob, lf, lg);
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const int a = pattern == ACC_EVEN ? pull_addr<QT>(b, j, L::ex(j), L::ey(j), L::ez(j))
+                                      : own_addr<QT>(b, pattern == ACC_ODD ? L::opp(j) : j);
+    lam[a] += (Real)(lf[j] * scale);
+  }
+#pragma unroll
+  for (int i = 0; i < QS; ++i) {
+    const int a = pattern == ACC_EVEN ? pull_addr<QT>(b, Q + i, S::ex(i), S::ey(i), S::ez(i))
+                                      : own_addr<QT>(b, Q + (pattern == ACC_ODD ? S::opp(i) : i));
+    lam[a] += (Real)(lg[i] * scale);
+  }
+}
+
+// J of the window: glob[kNG] = (1/W) sum of the window's objectives (each slot of
+// win holds kNG sums and J); glob[0..kNG) keep the final state's sums.
+__global__ void k_window_mean(const double* __restrict__ win, int W, double* __restrict__ glob) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double J = 0.0;
+  for (int s = 0; s < W; ++s) J += win[(size_t)s * (kNG + 1) + kNG];
+  glob[kNG] = J / (double)W;
 }
 
 // ------------------------------------------------------------ adjoint step

@@ -81,6 +81,9 @@ struct Plan {
   uint64_t node_bytes = 0;   // aligned Np x Real
   int64_t C = 1, S = 1;      // checkpoint interval and slots
   bool inplace = false;      // one primal working buffer and one adjoint buffer, streamed in place
+  int64_t W = 1;             // states averaged by the objective (the last W of the horizon)
+  uint64_t cols_bytes = 0;   // inlet + outlet columns of one state (aligned)
+  uint64_t win_bytes = 0;    // W > 1: W x (sums + J), then W x columns
   uint64_t total = 0;
 };
 
@@ -105,6 +108,8 @@ struct lbm_ctx {
   char* ckpt = nullptr;
   char* mom = nullptr;
   void* work = nullptr;   // in place: the primal working buffer (ckpt[0] when store-all)
+  char* win = nullptr;    // W > 1: window slots (sums + J, then inlet/outlet columns), W of them
+  int64_t win_count = 0;  // window states captured since the run started at t = 0
   // time bookkeeping
   int64_t t = 0;          // primal time: current state is h^{t-1}
   int64_t rec_len = 0;    // recorded steps (trajectory h^{-1}..h^{rec_len-1})
@@ -170,7 +175,10 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
   if (c->switch_fn != LBM_G_POWER && c->switch_fn != LBM_G_RAMP) return bad("bad switch_fn");
   if (c->switch_fn == LBM_G_RAMP && !(c->switch_param > 0.0)) return bad("RAMP needs q > 0");
   if (c->switch_fn == LBM_G_POWER && !(c->switch_param >= 0.0)) return bad("POWER needs theta >= 0");
-  if (c->reserved0 != 0 || c->reserved1 != 0) return bad("reserved0 and reserved1 must be 0");
+  if (c->reserved0 != 0) return bad("reserved0 must be 0");
+  if (c->n_avg < 0) return bad("n_avg must be >= 0");
+  if (c->n_avg > 1 && c->n_avg > c->nsteps)
+    return bad("n_avg > 1 averages the last n_avg states of the horizon: needs nsteps >= n_avg");
   if (c->inlet != LBM_INLET_VELOCITY && c->inlet != LBM_INLET_PRESSURE) return bad("bad inlet");
   if (c->collision != LBM_COLL_BGK && c->collision != LBM_COLL_MRT) return bad("bad collision");
   if (c->collision == LBM_COLL_MRT) {
@@ -198,7 +206,7 @@ lbm_status check_config(const lbm_config* c, std::string* why) {
 // adjoint state, plus the working buffer unless C >= N (store-all: the state stays
 // in ckpt[0]).
 uint64_t plan_total(const Plan& p, int64_t C, int64_t S, int64_t N) {
-  uint64_t t = 2 * p.node_bytes + align_up(kGlobBytes) + align_up(kDescBytes);
+  uint64_t t = 2 * p.node_bytes + align_up(kGlobBytes) + align_up(kDescBytes) + p.win_bytes;
   const uint64_t extra = p.inplace ? (C >= N ? 1 : 2) : 4;
   t += (uint64_t)(extra + S) * p.state_bytes + (uint64_t)C * p.mom_bytes;
   return t;
@@ -228,12 +236,16 @@ lbm_status make_plan(const lbm_config* c, Plan* p, std::string* why) {
   p->mom_bytes = align_up((uint64_t)mom_values(c) * p->Np * p->rs);
   p->node_bytes = align_up((uint64_t)p->Np * p->rs);
   p->inplace = c->inplace != 0;
+  p->W = c->n_avg > 1 ? c->n_avg : 1;
+  p->win_bytes = 0;
+  p->cols_bytes = align_up((uint64_t)2 * p->QT * c->ny * c->nz * p->rs);  // inlet + outlet columns
+  if (p->W > 1) p->win_bytes = align_up((uint64_t)p->W * (kNG + 1) * sizeof(double)) + (uint64_t)p->W * p->cols_bytes;
   const int64_t Nst = std::max<int64_t>(c->nsteps, 1);
   if (p->inplace && c->nsteps == 0) {
     // unrecorded runs and the one-shot iteration only: the state and one adjoint buffer
     p->C = 0;
     p->S = 1;
-    p->total = 2 * p->node_bytes + align_up(kGlobBytes) + align_up(kDescBytes) + 2 * p->state_bytes;
+    p->total = 2 * p->node_bytes + align_up(kGlobBytes) + align_up(kDescBytes) + 2 * p->state_bytes + p->win_bytes;
     return LBM_OK;
   }
   int64_t C;
@@ -363,6 +375,12 @@ int batch_block_waves(lbm_ctx* const* cs, int n) {
   return 1;
 }
 
+// Window of the time-averaged objective: slot s holds state f^{N-W+1+s}.
+double* win_glob(lbm_ctx* c, int64_t s) { return (double*)c->win + s * (kNG + 1); }
+void* win_cols(lbm_ctx* c, int64_t s) {
+  return c->win + align_up((uint64_t)c->plan.W * (kNG + 1) * sizeof(double)) + (uint64_t)s * c->plan.cols_bytes;
+}
+
 // Typed operations on one context.
 template <int Q, int QS, typename Real, int V = 0>
 struct Ops {
@@ -482,7 +500,22 @@ struct Ops {
   static void seed(lbm_ctx* c, const void* src, void* lam) {
     Geo g = node_geometry(c->cfg);
     hipLaunchKernelGGL((k_seed<Q, QS, Real>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
-                       (const double*)c->glob, (Real*)lam, acc(c), c->plan.inplace ? 1 : 0);
+                       (const double*)c->glob, (Real*)lam, acc(c), c->plan.inplace ? 1 : 0,
+                       1.0 / (double)c->plan.W);
+  }
+  // Window state s: its boundary sums and objective, and its inlet/outlet columns.
+  static void capture(lbm_ctx* c, const void* src, int64_t s) {
+    objective(c, src, win_glob(c, s));
+    const int n = 2 * c->cfg.ny * c->cfg.nz;
+    hipLaunchKernelGGL((k_capture_columns<Q, QS, Real>), dim3((n + 255) / 256), dim3(256), 0, c->stream, P(c),
+                       (const Real*)src, acc(c), (Real*)win_cols(c, s));
+  }
+  // lambda^n += (1/W) dJ/df^n of window state s, lambda^n in layout pattern.
+  static void window_seed(lbm_ctx* c, int64_t s, void* lam, int pattern) {
+    const int n = 2 * c->cfg.ny * c->cfg.nz;
+    hipLaunchKernelGGL((k_window_seed<Q, QS, Real>), dim3((n + 255) / 256), dim3(256), 0, c->stream, P(c),
+                       (const Real*)win_cols(c, s), (const double*)win_glob(c, s), (Real*)lam, pattern,
+                       1.0 / (double)c->plan.W);
   }
   // One in-place adjoint step: the cotangent buffer is in the odd-pattern layout
   // after an even number of adjoint steps (the seed writes that layout).
@@ -613,6 +646,22 @@ void* rec_dst(lbm_ctx* c, int64_t k) {
   return other_pp(c, c->cur);
 }
 
+// Time-averaged objective: capture the state just produced (time t) when it is
+// the next state of the window [N - W + 1, N] of a run that started at t = 0.
+template <class O>
+void capture_window(lbm_ctx* c) {
+  const int64_t W = c->plan.W, first = c->cfg.nsteps - W + 1;
+  if (W > 1 && c->t >= first && c->t - first == c->win_count) {
+    O::capture(c, c->cur, c->win_count);
+    ++c->win_count;
+  }
+}
+
+// Whole window captured and the run at its end: the objective is the window mean.
+bool window_complete(const lbm_ctx* c) {
+  return c->plan.W > 1 && c->win_count == c->plan.W && c->t == c->cfg.nsteps;
+}
+
 template <class O>
 struct RunPrimal {
   static lbm_status run(lbm_ctx* c, int64_t nsteps, int record) {
@@ -623,6 +672,7 @@ struct RunPrimal {
           O::copy(c, c->work, ckpt_slot(c, c->t / c->plan.C), (size_t)c->plan.QT * c->plan.Np);
         O::primal_inplace(c, c->work, c->t, record ? mom_slot(c, c->t) : nullptr);
         ++c->t;
+        capture_window<O>(c);
       }
       return launch_check(c, "in-place primal step");
     }
@@ -632,6 +682,7 @@ struct RunPrimal {
       O::primal(c, src, dst, record ? mom_slot(c, c->t) : nullptr);
       c->cur = dst;
       ++c->t;
+      capture_window<O>(c);
     }
     return launch_check(c, "primal step");
   }
@@ -641,6 +692,9 @@ template <class O>
 struct RunObjective {
   static lbm_status run(lbm_ctx* c, double* J_dev) {
     O::objective(c, c->cur, c->glob);
+    if (window_complete(c))
+      hipLaunchKernelGGL(k_window_mean, dim3(1), dim3(64), 0, c->stream, (const double*)c->win, (int)c->plan.W,
+                         c->glob);
     if (J_dev) {
       hipError_t e = hipMemcpyAsync(J_dev, c->glob + kNG, sizeof(double), hipMemcpyDeviceToDevice, c->stream);
       if (e != hipSuccess) return fail(c, LBM_EHIP, "objective copy: %s", hipGetErrorString(e));
@@ -695,6 +749,8 @@ template <class O>
 struct RunAdjoint {
   static lbm_status run(lbm_ctx* c, int64_t nsteps) {
     const int64_t C = c->plan.C;
+    // window states n < N whose objective terms enter lambda^n (none unless W > 1)
+    const int64_t first = c->plan.W > 1 ? c->cfg.nsteps - c->plan.W + 1 : INT64_MAX;
     if (!c->adj_started) start_adjoint<O>(c);
     if (c->plan.inplace) {  // store-all never recomputes; C < N recomputes each segment in place
       for (int64_t i = 0; i < nsteps; ++i) {
@@ -703,6 +759,8 @@ struct RunAdjoint {
         if (s != c->mom_seg) recompute_segment_inplace<O>(c, s);
         O::adjoint_inplace(c, mom_slot(c, n), c->rec_len - c->t_adj);
         --c->t_adj;
+        if (n >= first)  // lambda^n now in the layout of its step count
+          O::window_seed(c, n - first, c->lam[0], ((c->rec_len - c->t_adj) % 2 == 0) ? ACC_ODD : ACC_EVEN);
       }
       return launch_check(c, "in-place adjoint step");
     }
@@ -713,6 +771,7 @@ struct RunAdjoint {
       O::adjoint(c, mom_slot(c, n), c->lam[c->lam_cur], c->lam[1 - c->lam_cur]);
       c->lam_cur ^= 1;
       --c->t_adj;
+      if (n >= first) O::window_seed(c, n - first, c->lam[c->lam_cur], ACC_PP);
     }
     return launch_check(c, "adjoint step");
   }
@@ -963,6 +1022,7 @@ lbm_status check_batch(lbm_ctx* const* cs, int32_t n) {
     for (int q = 0; q < k; ++q)
       if (cs[q] == cs[k]) return fail(cs[0], LBM_EINVAL, "batch: context %d appears twice", k);
     if (cs[k]->plan.inplace) return fail(cs[0], LBM_EINVAL, "batch: context %d streams in place", k);
+    if (cs[k]->plan.W > 1) return fail(cs[0], LBM_EINVAL, "batch: context %d averages its objective", k);
     const lbm_config &a = cs[0]->cfg, &b = cs[k]->cfg;
     if (a.flow != b.flow || a.scalar != b.scalar || a.precision != b.precision)
       return fail(cs[0], LBM_EINVAL, "batch: context %d has another lattice or precision", k);
@@ -982,6 +1042,7 @@ void reset_times(lbm_ctx* c) {
   c->mom_seg = -1;
   c->os_active = false;
   c->state_lost = false;
+  c->win_count = 0;
 }
 
 lbm_status sync_check(lbm_ctx* c, const char* what) {
@@ -1072,6 +1133,10 @@ lbm_status lbm_create(const lbm_config* cfg, void* hip_stream, void* workspace_d
   q += (uint64_t)p.S * p.state_bytes;
   c->mom = q;
   q += (uint64_t)p.C * p.mom_bytes;
+  if (p.W > 1) {
+    c->win = q;
+    q += p.win_bytes;
+  }
   if (p.inplace && !c->work) c->work = c->ckpt;  // store-all / unrecorded: the state lives in ckpt[0]
   reset_times(c);
   s = dispatch<RunReset>(c);
@@ -1228,6 +1293,8 @@ lbm_status lbm_adjoint_steps(lbm_ctx* c, int64_t nsteps) {
     if (!(c->rec_open && c->t == c->rec_len))
       return fail(c, LBM_ESTATE, "adjoint_steps: needs a recorded run ending at the current time");
     if (nsteps > c->rec_len) return fail(c, LBM_EINVAL, "adjoint_steps: more steps than recorded");
+    if (c->plan.W > 1 && !window_complete(c))
+      return fail(c, LBM_ESTATE, "adjoint_steps: the time-averaged objective needs a recorded run to the horizon");
   } else if (nsteps > c->t_adj) {
     return fail(c, LBM_EINVAL, "adjoint_steps: only %lld steps remain", (long long)c->t_adj);
   }

@@ -71,7 +71,7 @@ class LbmConfig(ctypes.Structure):
         ("checkpoint_interval", ctypes.c_int64),
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("inlet", ctypes.c_int32),
-        ("reserved1", ctypes.c_int32),
+        ("n_avg", ctypes.c_int32),
         ("rho_in", ctypes.c_double),
         ("u_cap", ctypes.c_double),
         ("c_mix", ctypes.c_double),
@@ -97,7 +97,7 @@ MODEL_DEFAULTS = dict(
     switch_fn="power", switch_param=3.0, c_dp=1.0, c_hf=0.0, c_var=0.0,
     inlet="velocity", rho_in=1.0, u_cap=0.0, c_mix=0.0,
     collision="bgk", mrt_rates=(1.19, 1.4, 1.2, 1.4, 1.98), tau_s_solid=0.0,
-    plate_x0=0, plate_x1=0, s_plate=1.0,
+    plate_x0=0, plate_x1=0, s_plate=1.0, n_avg=1,
 )
 
 
@@ -121,7 +121,7 @@ def make_config(params: dict, nsteps: int, precision: str = "fp32", checkpoint_i
         switch_fn=fn, reserved0=0, switch_param=float(p["switch_param"]), c_dp=float(p["c_dp"]),
         c_hf=float(p["c_hf"]), c_var=float(p["c_var"]), nsteps=int(nsteps),
         checkpoint_interval=int(checkpoint_interval), hbm_budget_bytes=int(hbm_budget_bytes), inlet=im,
-        reserved1=0, rho_in=float(p["rho_in"]), u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]), collision=co,
+        n_avg=int(p["n_avg"]), rho_in=float(p["rho_in"]), u_cap=float(p["u_cap"]), c_mix=float(p["c_mix"]), collision=co,
         reserved2=0, mrt_rates=(ctypes.c_double * 5)(*[float(v) for v in p["mrt_rates"]]),
         tau_s_solid=float(p["tau_s_solid"]), inplace=1 if inplace else 0, reserved3=0,
         plate_x0=int(p["plate_x0"]), plate_x1=int(p["plate_x1"]), s_plate=float(p["s_plate"]))

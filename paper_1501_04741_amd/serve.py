@@ -19,7 +19,12 @@ Requests of different lattice sizes arrive over time.  The scheduler:
   class advances by the number of steps that takes about that much device
   time, so small requests are not held to the pace of large ones;
 * finishes requests whose adjoint reached t = 0 (objective and gradient are
-  read back after a stream event), frees their memory and admits more.
+  read back after a stream event), frees their memory and admits more;
+* cancels a request on demand: a queued one leaves the queue, an admitted one
+  (in its primal, adjoint or read-back phase) is closed at the next tick and
+  its memory returns to the budget.  Every request's launches go to one
+  stream, so work still queued for a cancelled request runs before any later
+  request's work that reuses its memory.
 
 Requests that arrive while others run join at the next tick: their steps
 share launches with the running ones.  Each request's arithmetic is the same
@@ -38,7 +43,8 @@ from typing import Any, Callable, Dict, List, Optional
 
 import numpy as np
 
-QUEUED, PRIMAL, ADJOINT, FINISHING, DONE, FAILED = "queued", "primal", "adjoint", "finishing", "done", "failed"
+QUEUED, PRIMAL, ADJOINT, FINISHING, DONE, FAILED, CANCELLED = (
+    "queued", "primal", "adjoint", "finishing", "done", "failed", "cancelled")
 
 
 class DeferAdmission(Exception):
@@ -64,6 +70,7 @@ class Job:
     token: Any = None
     admitted: float = math.nan
     finished: float = math.nan
+    cancel_requested: bool = False
     J: float = math.nan
     grad: Any = None
     error: str = ""
@@ -191,6 +198,40 @@ class Server:
             self.active.append(job)
             self.stats["admitted"] += 1
 
+    def cancel(self, rid: int) -> bool:
+        """Cancel request rid: dropped from the queue now, or closed at the next
+        tick if admitted.  Returns False if no such request is queued or active."""
+        for j in list(self.queue):
+            if j.rid == rid:
+                self.queue.remove(j)
+                j.state = CANCELLED
+                j.finished = self.now()
+                self.finished.append(j)
+                self.stats["cancelled"] += 1
+                return True
+        for j in self.active:
+            if j.rid == rid:
+                j.cancel_requested = True
+                return True
+        return False
+
+    def _reap_cancelled(self):
+        still = []
+        for j in self.active:
+            if j.cancel_requested:
+                self.ex.close(j.handle)
+                j.handle = None
+                j.token = None
+                self.used -= j.footprint
+                self.active_state -= j.step_bytes
+                j.state = CANCELLED
+                j.finished = self.now()
+                self.finished.append(j)
+                self.stats["cancelled"] += 1
+            else:
+                still.append(j)
+        self.active = still
+
     # ----------------------------------------------------------------- tick
     def _groups(self, state):
         groups: Dict[Any, List[Job]] = collections.OrderedDict()
@@ -212,6 +253,7 @@ class Server:
 
     def tick(self) -> bool:
         """One scheduling round; returns True if any device work was issued."""
+        self._reap_cancelled()
         self._poll()
         self._admit()
         issued = False

@@ -208,3 +208,34 @@ def test_inplace_requests_served_equal_alone_bitwise():
         J, g = _alone(j.params, j.design, j.steps, j.precision, interval=j.steps)
         assert j.J == J, (j.rid, j.J, J)
         assert np.array_equal(j.grad, g), j.rid
+
+
+def test_cancelled_requests_free_their_memory_and_leave_the_rest_exact():
+    """Cancel one request while queued and two mid-flight (primal and adjoint
+    phase, one of them streamed in place); the others still equal their runs
+    alone bitwise and the arena is whole again."""
+    from paper_1501_04741_amd.serve import ADJOINT, CANCELLED, PRIMAL
+    jobs = _jobs(n_each=2, steps=40)
+    ex = GpuExecutor(arena_bytes=2 << 30, inplace_min_state_bytes=19 * 40 * 12 * 10 * 4)
+    srv = Server(ex, hbm_budget_bytes=2 << 30, quantum=10, policy="fifo")
+    for j in jobs:
+        srv.submit(j)
+    srv.tick()
+    queued = next(j for j in jobs if j.state == "queued") if any(j.state == "queued" for j in jobs) else None
+    for _ in range(4):
+        srv.tick()
+    in_adj = next(j for j in jobs if j.state == ADJOINT)
+    in_primal = next((j for j in jobs if j.state == PRIMAL), None)
+    victims = [in_adj] + ([in_primal] if in_primal else []) + ([queued] if queued and queued.state == "queued" else [])
+    for v in victims:
+        assert srv.cancel(v.rid)
+    srv.drain()
+    for v in victims:
+        assert v.state == CANCELLED
+    assert ex.arena.free_bytes() == ex.arena.size and srv.used == 0
+    for j in jobs:
+        if j in victims:
+            continue
+        assert j.state == DONE, (j.rid, j.state, j.error)
+        J, g = _alone(j.params, j.design, j.steps, j.precision, interval=j.steps)
+        assert j.J == J and np.array_equal(j.grad, g), j.rid

@@ -273,3 +273,31 @@ def test_arena_first_fit_and_coalescing():
         a.release(offs[i], 256)
     assert a.free == [(0, 2560)] and a.free_bytes() == 2560
     assert a.buf.dtype == torch.uint8
+
+
+def test_cancel_queued_and_mid_flight_requests():
+    """A queued request leaves the queue; admitted ones are closed at the next tick
+    whether in their primal or adjoint phase; memory and handles return, and the
+    other requests still get their own results."""
+    from paper_1501_04741_amd.serve import ADJOINT, CANCELLED, PRIMAL
+    ex = FakeExecutor(_oracle_eval)
+    jobs = [_job(i, 16, 8, steps=20) for i in range(4)]
+    srv = Server(ex, hbm_budget_bytes=2 * ex.footprint(jobs[0]), quantum=5, policy="fifo")
+    for j in jobs:
+        srv.submit(j)
+    srv.tick()                        # jobs 0 and 1 admitted (budget holds two), 2 and 3 queued
+    assert [j.state for j in jobs] == [PRIMAL, PRIMAL, "queued", "queued"]
+    assert srv.cancel(3) and jobs[3].state == CANCELLED
+    for _ in range(5):                # job 0 reaches its adjoint
+        srv.tick()
+    assert jobs[0].state == ADJOINT
+    assert srv.cancel(0)              # mid-adjoint
+    assert srv.cancel(99) is False
+    srv.drain()
+    assert jobs[0].state == CANCELLED and jobs[3].state == CANCELLED
+    assert jobs[1].state == DONE and jobs[2].state == DONE
+    for j in (jobs[1], jobs[2]):
+        J, g = _oracle_eval(j)
+        assert j.J == J and np.array_equal(j.grad, g)
+    assert ex.open_handles == 0 and srv.used == 0 and srv.active_state == 0
+    assert srv.stats["cancelled"] == 2
