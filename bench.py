@@ -36,18 +36,12 @@ METRIC = "primal/adjoint MLUPS + HBM roofline frac; served gradients/s, p50/p99 
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE, each scaled by what the
-# counter reads for a 1 GiB device copy in the same run.  The figures hold for the kernel sources
-# and compile flags whose SHA-256 prefix is given (kernels.hpp, lattice.hpp, build.py in that
-# order) and are reported only while those files still match.
+# counter reads for a 1 GiB device copy in the same run, per workload and kernel.  The figures hold
+# for the kernel sources, host dispatch and compile flags whose SHA-256 prefix is given and are
+# reported only while those files still match.
 COUNTER_TRAFFIC = {
-    "sources_sha256_16": "1bf889fd1dddf94e",
-    "workload": "d3q19_channel_256x128x128",
-    "k_primal": None,
-    "k_adjoint": None,
-    "k_adjoint_inplace": 752214692,
-    "k_oneshot": None,
-    "k_oneshot_inplace": 1328265213,
-    "k_primal_inplace": 719794530,
+    "sources_sha256_16": None,
+    "bytes_per_launch": {},
 }
 _COUNTER_SOURCES = ("paper_1501_04741_amd/csrc/kernels.hpp", "paper_1501_04741_amd/csrc/lattice.hpp",
                     "paper_1501_04741_amd/csrc/lbm_adj.hip", "paper_1501_04741_amd/build.py")
@@ -71,9 +65,9 @@ def sources_sha():
 
 
 def _measured_traffic(workload, kernel):
-    if sources_sha() != COUNTER_TRAFFIC["sources_sha256_16"] or workload != COUNTER_TRAFFIC["workload"]:
+    if sources_sha() != COUNTER_TRAFFIC["sources_sha256_16"]:
         return None
-    return COUNTER_TRAFFIC.get(kernel)
+    return COUNTER_TRAFFIC["bytes_per_launch"].get(workload, {}).get(kernel)
 
 
 def _class_counts(p):
@@ -187,17 +181,19 @@ def mixer_leg(dev, steps=4000, os_iters=400):
     osi_us = ei[0].elapsed_time(ei[1]) * 1e3 / os_iters
     pi_us = ei[2].elapsed_time(ei[3]) * 1e3 / steps
     pb, ob = primal_bytes(p, "fp32", recorded=False), oneshot_bytes(p, "fp32")
-    roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
-    return {"workload": "d3q19_d3q7_mixer_empty_450x50x50", "nodes": nodes,
+    wk = "d3q19_d3q7_mixer_empty_450x50x50"
+    roof = lambda b, us, k: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b,
+                             "avg_launch_us": us, "traffic": _measured_traffic(wk, k)}
+    return {"workload": wk, "nodes": nodes,
             "primal": {"kernel": "k_primal<19,7,float>", "steps_timed": steps, "mlups": nodes / prim_us,
-                       "roofline": roof(pb, prim_us)},
+                       "roofline": roof(pb, prim_us, "k_primal")},
             "oneshot": {"kernel": "k_oneshot_inplace<19,7,float>", "iterations_timed": os_iters,
-                        "mlups": nodes / osi_us, "roofline": roof(ob, osi_us)},
+                        "mlups": nodes / osi_us, "roofline": roof(ob, osi_us, "k_oneshot_inplace")},
             "primal_inplace": {"kernel": "k_primal_inplace<19,7,float>", "steps_timed": steps, "mlups": nodes / pi_us,
-                               "roofline": roof(pb, pi_us)},
+                               "roofline": roof(pb, pi_us, "k_primal_inplace")},
             "oneshot_ping_pong": {"kernel": "k_oneshot<19,7,float>", "iterations_timed": os_iters,
-                                  "mlups": nodes / os_us, "roofline": roof(ob, os_us)},
+                                  "mlups": nodes / os_us, "roofline": roof(ob, os_us, "k_oneshot")},
             "note": "two primal states (234 MB) fit the 256 MB last-level cache; the ping-pong one-shot's four "
                     "do not, the in-place one-shot's two do"}
 
@@ -375,10 +371,13 @@ def batched_leg(dev, n_ctx=8, steps=100):
     single_us = ev[4].elapsed_time(ev[5]) * 1e3 / (steps * n_ctx)
     roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
+    key = "d3q19_batch_%dx128x96x96" % n_ctx
     return {"workload": "%d x D3Q19 128x96x96 FP32 channels, %d recorded steps, every step's moments held" % (
                 n_ctx, steps),
-            "primal": {"kernel": "k_primal_batch<19,0,float>", "roofline": roof(n_ctx * pb, prim_us)},
-            "adjoint": {"kernel": "k_adjoint_batch<19,0,float>", "roofline": roof(n_ctx * ab, adj_us)},
+            "primal": {"kernel": "k_primal_batch<19,0,float>",
+                       "roofline": dict(roof(n_ctx * pb, prim_us), traffic=_measured_traffic(key, "k_primal_batch"))},
+            "adjoint": {"kernel": "k_adjoint_batch<19,0,float>",
+                        "roofline": dict(roof(n_ctx * ab, adj_us), traffic=_measured_traffic(key, "k_adjoint_batch"))},
             "primal_single_context": {"kernel": "k_primal<19,0,float>", "roofline": roof(pb, single_us)}}
 
 
@@ -562,6 +561,38 @@ def serve_main(args):
     return 0
 
 
+def legs_main(names, copy_probe_mb=0):
+    """Runs only the named legs (no headline evaluation) and prints their results;
+    copy_probe_mb > 0 adds one device copy of that size (counter calibration)."""
+    import torch
+    dev = torch.device("cuda:0")
+    legs = {
+        "mixer": lambda: mixer_leg(dev),
+        "mrt": lambda: mrt_leg(dev),
+        "inplace": lambda: inplace_leg(dev),
+        "ping_pong": lambda: mrt_leg(dev, collision="bgk", inplace=False),
+        "fp64": lambda: mrt_leg(dev, collision="bgk", inplace=True, prec="fp64"),
+        "batched": lambda: batched_leg(dev),
+        "recompute": lambda: recompute_leg(dev, inplace=True),
+        "recompute_ping_pong": lambda: recompute_leg(dev, inplace=False),
+    }
+    unknown = [n for n in names if n not in legs]
+    if unknown:
+        print("unknown legs: %s" % ", ".join(unknown), file=sys.stderr)
+        return 2
+    torch.cuda.set_device(dev)
+    out = {}
+    for n in names:
+        print("[bench] %s leg" % n, file=sys.stderr, flush=True)
+        out[n] = legs[n]()
+    if copy_probe_mb:
+        a = torch.empty(copy_probe_mb * 2**20 // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -573,6 +604,9 @@ def main(argv=None):
     ap.add_argument("--no-mixer", action="store_true", help="skip the mixing-duct, MRT, in-place, ping-pong and FP64 legs")
     ap.add_argument("--ping-pong", action="store_true", help="run the main evaluation with ping-pong buffers")
     ap.add_argument("--no-recompute", action="store_true", help="skip the checkpoint + recompute leg")
+    ap.add_argument("--only", default="", metavar="LEGS",
+                    help="run only these comma-separated legs (mixer, mrt, inplace, ping_pong, fp64, batched, "
+                         "recompute, recompute_ping_pong) and print them as one JSON object (for profiling)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MB",
                     help="also run one device copy of MB megabytes (counter calibration for profiles)")
@@ -606,6 +640,8 @@ def main(argv=None):
     if args.steps < 1 or args.warmup < 0:
         print("need --steps >= 1 and --warmup >= 0", file=sys.stderr)
         return 2
+    if args.only:
+        return legs_main(args.only.split(","), args.copy_probe)
 
     import numpy as np
     import torch

@@ -18,9 +18,11 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_counter_traffic_keyed_to_sources():
-    w = bench.COUNTER_TRAFFIC["workload"]
-    if bench.sources_sha() == bench.COUNTER_TRAFFIC["sources_sha256_16"]:
-        assert bench._measured_traffic(w, "k_adjoint_inplace") == bench.COUNTER_TRAFFIC["k_adjoint_inplace"]
+    table = bench.COUNTER_TRAFFIC["bytes_per_launch"]
+    for w, kernels in table.items():
+        for k, v in kernels.items():
+            expect = v if bench.sources_sha() == bench.COUNTER_TRAFFIC["sources_sha256_16"] else None
+            assert bench._measured_traffic(w, k) == expect
     assert bench._measured_traffic("another_workload", "k_adjoint_inplace") is None
 
 
