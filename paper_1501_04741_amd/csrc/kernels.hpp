@@ -17,10 +17,13 @@
 // as is.  The primal buffers hold POST-collision states h^k; the pre-collision
 // state of step k+1 is pulled, f^{k+1}_j(x) = h^k_j(x - e_j) (Section 2.1).
 //
-// Launch geometry (all node kernels): block = BX threads along x, grid =
-// (ceil(nx/BX), ny, nz).  y and z are block-uniform, so wall rows are decided
-// per block and every x-shift in the pull stays inside the row the block
-// owns: each fetched cache line of a source row is consumed by one block.
+// Launch geometry (node kernels): block = BX threads along x, grid =
+// (ceil(nx/BX), ny, nz).  The hot kernels (primal, adjoint, one-shot) may also
+// stack R rows in a block (blockDim.y = R) when a row is narrower than the
+// block they aim for; a wave never straddles two rows.  y and z are
+// wave-uniform, so wall rows are decided per wave and every x-shift in the pull
+// stays inside the row the wave's block owns: each fetched cache line of a
+// source row is consumed by one block.
 //
 // Each node is owned by exactly one thread; there are no atomics, and every
 // reduction runs in a fixed order, so results are bitwise reproducible.
@@ -124,6 +127,19 @@ __device__ __forceinline__ int push_addr(const Nbr& b, int j, int ex, int ey, in
 template <int QT>
 __device__ __forceinline__ int own_addr(const Nbr& b, int j) {
   return ((b.Yr[1] + b.Zr[1]) * QT + j) * b.pitch + b.X[1];
+}
+
+// Position of the calling thread in the hot kernels' launch geometry: blocks
+// of blockDim.x = 64k threads along x (a multiple of the wave) and blockDim.y
+// rows, grid (ceil(nx / blockDim.x), ceil(ny / blockDim.y), nz).  A wave never
+// straddles two rows, so y is wave-uniform and is kept in a scalar register.
+// Returns false for the padding lanes and rows.
+template <typename P>
+__device__ __forceinline__ bool hot_pos(const P& p, int& x, int& y, int& z) {
+  x = blockIdx.x * blockDim.x + threadIdx.x;
+  y = __builtin_amdgcn_readfirstlane((int)(blockIdx.y * blockDim.y + threadIdx.y));
+  z = blockIdx.z;
+  return x < p.nx && y < p.ny;
 }
 
 // Streaming stores: non-temporal when the state is too large to be re-read
@@ -779,7 +795,9 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* s
       Real m[Mom<Q, QS, V>::N];
       node_moments<Q, QS, Real, V>(p, cls, y, z, f, g, m);
 #pragma unroll
-      for (int k = 0; k < Mom<Q, QS, V>::N; ++k) put<NT>(mom + (size_t)k * p.Np + n, m[k]);
+      // streaming stores whatever the state size: a moment set is read once, by the
+      // adjoint, after the rest of the run has passed through the cache
+      for (int k = 0; k < Mom<Q, QS, V>::N; ++k) put<true>(mom + (size_t)k * p.Np + n, m[k]);
     }
   }
   if (cls == INTERIOR) {
@@ -798,18 +816,18 @@ template <int Q, int QS, typename Real, bool NT, bool MOM, int V>
 __global__ __launch_bounds__(256) void k_primal(Params<Real> p, const Real* __restrict__ src,
                                                 Real* __restrict__ dst, const Real* __restrict__ w,
                                                 Real* __restrict__ mom) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= p.nx) return;
-  primal_node<Q, QS, Real, NT, MOM, V>(p, src, dst, w, mom, x, blockIdx.y, blockIdx.z);
+  int x, y, z;
+  if (!hot_pos(p, x, y, z)) return;
+  primal_node<Q, QS, Real, NT, MOM, V>(p, src, dst, w, mom, x, y, z);
 }
 
 // One in-place step (even or odd phase); with MOM it also records the moments.
 template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC, bool NTE = false>
 __global__ __launch_bounds__(256) void k_primal_inplace(Params<Real> p, Real* a, const Real* __restrict__ w,
                                                         Real* __restrict__ mom) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= p.nx) return;
-  primal_node<Q, QS, Real, NT, MOM, V, ACC, NTE>(p, a, a, w, mom, x, blockIdx.y, blockIdx.z);
+  int x, y, z;
+  if (!hot_pos(p, x, y, z)) return;
+  primal_node<Q, QS, Real, NT, MOM, V, ACC, NTE>(p, a, a, w, mom, x, y, z);
 }
 
 // ------------------------------------------------------------ objective
@@ -1376,7 +1394,9 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
   for (int k = 0; k < Mom<Q, QS, V>::N; ++k) m[k] = Real(0);
   if (has_moments(p, cls)) {
 #pragma unroll
-    for (int k = 0; k < Mom<Q, QS, V>::N; ++k) m[k] = get<NT>(mom + (size_t)k * p.Np + n);  // read once
+    // read once: streaming hint whatever the state size, so that the moments do not
+    // evict a cotangent state the last-level cache could hold between steps
+    for (int k = 0; k < Mom<Q, QS, V>::N; ++k) m[k] = get<true>(mom + (size_t)k * p.Np + n);
   }
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
   adjoint_vjp<Q, QS, Real, V>(p, cls, x, y, m, wn, mu, nu, lf, lg, gw);
@@ -1388,18 +1408,18 @@ template <int Q, int QS, typename Real, bool NT, int V>
 __global__ __launch_bounds__(256) void k_adjoint(Params<Real> p, const Real* __restrict__ mom,
                                                  const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
                                                  const Real* __restrict__ w, Real* __restrict__ grad) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= p.nx) return;
-  adjoint_node<Q, QS, Real, NT, V>(p, mom, lam_in, lam_out, w, grad, x, blockIdx.y, blockIdx.z);
+  int x, y, z;
+  if (!hot_pos(p, x, y, z)) return;
+  adjoint_node<Q, QS, Real, NT, V>(p, mom, lam_in, lam_out, w, grad, x, y, z);
 }
 
 // One in-place adjoint step (even or odd pattern of the cotangent buffer l).
 template <int Q, int QS, typename Real, bool NT, int V, int ACC, bool NTE = false>
 __global__ __launch_bounds__(256) void k_adjoint_inplace(Params<Real> p, const Real* __restrict__ mom, Real* l,
                                                          const Real* __restrict__ w, Real* __restrict__ grad) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= p.nx) return;
-  adjoint_node<Q, QS, Real, NT, V, ACC, NTE>(p, mom, l, l, w, grad, x, blockIdx.y, blockIdx.z);
+  int x, y, z;
+  if (!hot_pos(p, x, y, z)) return;
+  adjoint_node<Q, QS, Real, NT, V, ACC, NTE>(p, mom, l, l, w, grad, x, y, z);
 }
 
 
@@ -1632,10 +1652,10 @@ __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __r
                                                  Real* __restrict__ lam_out, Real* __restrict__ w,
                                                  Real* __restrict__ grad, const double* __restrict__ glob, Real zeta,
                                                  Real c_pen) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= p.nx) return;
-  oneshot_node<Q, QS, Real, NT, V, ACC_PP>(p, prim_in, prim_out, lam_in, lam_out, w, grad, glob, zeta, c_pen, x,
-                                           blockIdx.y, blockIdx.z);
+  int x, y, z;
+  if (!hot_pos(p, x, y, z)) return;
+  oneshot_node<Q, QS, Real, NT, V, ACC_PP>(p, prim_in, prim_out, lam_in, lam_out, w, grad, glob, zeta, c_pen, x, y,
+                                           z);
 }
 
 // One in-place one-shot iteration (even or odd phase): a is the primal buffer,
@@ -1644,17 +1664,18 @@ template <int Q, int QS, typename Real, bool NT, int V, int ACC>
 __global__ __launch_bounds__(256) void k_oneshot_inplace(Params<Real> p, Real* a, Real* l, Real* __restrict__ w,
                                                          Real* __restrict__ grad, const double* __restrict__ glob,
                                                          Real zeta, Real c_pen) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= p.nx) return;
-  oneshot_node<Q, QS, Real, NT, V, ACC>(p, a, a, l, l, w, grad, glob, zeta, c_pen, x, blockIdx.y, blockIdx.z);
+  int x, y, z;
+  if (!hot_pos(p, x, y, z)) return;
+  oneshot_node<Q, QS, Real, NT, V, ACC>(p, a, a, l, l, w, grad, glob, zeta, c_pen, x, y, z);
 }
 
 // --------------------------------------------------------- batched launches
 // One launch advances many contexts of the same (Q, QS, Real) by one step.
-// Blocks cover kw consecutive waves (64 x-nodes each) of one row, kw chosen per
+// A row part is kw consecutive waves (64 x-nodes each) of one row, kw chosen per
 // launch as the widest of 4, 3, 2, 1 waves that divides every context's waves
-// per row (so no block straddles two rows and none holds more idle lanes than
-// the row's padding to whole waves); block b belongs to the context k with
+// per row (so no part straddles two rows and none holds more idle lanes than
+// the row's padding to whole waves); a block holds rpb parts (several rows only
+// when every row is one part); block b belongs to the context k with
 // start[k] <= b < start[k+1].  The per-node code is the same device function
 // as in the single-context kernels, so results are bitwise identical to them.
 constexpr int kBatchMax = 32;
@@ -1664,30 +1685,58 @@ constexpr int kWave = 64;
 template <typename Real>
 struct BatchStatic {
   Params<Real> p;
-  const Real* w;
-  Real* grad;
   int waves;  // waves per row: ceil(nx / 64)
-  int nt;  // non-temporal stores
 };
 
 // Per-launch arguments, passed by value (about 1.2 KB for kBatchMax = 32).
 template <typename Real>
 struct BatchArgs {
   int n;
-  int kw;  // waves per block (blockDim.x = 64 kw), dividing every context's waves per row
+  int kw;   // waves per row part (64 kw threads), dividing every context's waves per row
+  int rpb;  // row parts per block (blockDim.x = 64 kw rpb); > 1 only when every row is one part
+  int nt;  // streaming stores and hints: the states the launch touches exceed the last-level cache
   int start[kBatchMax + 1];
   const BatchStatic<Real>* st[kBatchMax];
   const Real* a[kBatchMax];  // primal: source state; adjoint: moments of f^n
   const Real* b[kBatchMax];  // adjoint: lambda^{n+1}
   Real* c[kBatchMax];        // primal: destination; adjoint: lambda^n
-  Real* m[kBatchMax];        // primal: where to record moments (null: do not record)
+  Real* m[kBatchMax];        // primal: where to record moments (all set or all null)
+  const Real* w[kBatchMax];  // design field
+  Real* g[kBatchMax];        // adjoint: gradient accumulator
 };
+
+static_assert(sizeof(BatchArgs<double>) <= 4096, "batched launch arguments exceed the kernel-argument limit");
+
+
 
 // Stores a context's batch descriptor (passed by value, so the upload is a
 // stream-ordered launch with no host-side staging).
 template <typename Real>
 __global__ void k_write_desc(BatchStatic<Real> h, BatchStatic<Real>* __restrict__ d) {
   if (blockIdx.x == 0 && threadIdx.x == 0) *d = h;
+}
+
+// Node of the calling thread in local block lb of its context: with one row
+// part per block (rpb = 1) block lb covers waves [kw bx, kw bx + kw) of row
+// lb / (waves / kw); with rpb > 1 (every member's row is one block part) it
+// covers rows rpb lb ... rpb lb + rpb - 1, one row per kw waves.
+template <typename Real>
+__device__ __forceinline__ bool batch_pos(const BatchArgs<Real>& A, const Params<Real>& p, int waves, int lb, int& x,
+                                          int& y, int& z) {
+  const int tw = kWave * A.kw;  // threads per row part
+  int bx, row;
+  if (A.rpb == 1) {
+    const int gx = waves / A.kw;  // blocks per row
+    bx = lb % gx;
+    row = lb / gx;
+  } else {
+    bx = 0;
+    row = __builtin_amdgcn_readfirstlane((int)(lb * A.rpb + threadIdx.x / tw));
+  }
+  x = bx * tw + (int)(threadIdx.x % tw);
+  y = row % p.ny;
+  z = row / p.ny;
+  return x < p.nx && z < p.nz;
 }
 
 template <typename Real>
@@ -1697,45 +1746,33 @@ __device__ __forceinline__ int batch_find(const BatchArgs<Real>& A, int blk) {
   return k;
 }
 
-template <int Q, int QS, typename Real, int V>
+// NT (streaming stores and hints) and MOM (record the moments) are uniform over
+// a launch, so they are template arguments: one code path per kernel keeps the
+// register count of the single-context kernels.
+template <int Q, int QS, typename Real, int V, bool NT, bool MOM>
 __global__ __launch_bounds__(256) void k_primal_batch(BatchArgs<Real> A) {
   const int blk = blockIdx.x;
   const int k = batch_find(A, blk);
-  const BatchStatic<Real>& S = *A.st[k];
-  const int lb = blk - A.start[k];
-  const int gx = S.waves / A.kw;  // blocks per row
-  const int bx = lb % gx, row = lb / gx;
-  const int x = bx * (kWave * A.kw) + threadIdx.x;
-  if (x >= S.p.nx) return;
-  const int y = row % S.p.ny, z = row / S.p.ny;
-  if (S.nt) {
-    if (A.m[k])
-      primal_node<Q, QS, Real, true, true, V>(S.p, A.a[k], A.c[k], S.w, A.m[k], x, y, z);
-    else
-      primal_node<Q, QS, Real, true, false, V>(S.p, A.a[k], A.c[k], S.w, nullptr, x, y, z);
-  } else {
-    if (A.m[k])
-      primal_node<Q, QS, Real, false, true, V>(S.p, A.a[k], A.c[k], S.w, A.m[k], x, y, z);
-    else
-      primal_node<Q, QS, Real, false, false, V>(S.p, A.a[k], A.c[k], S.w, nullptr, x, y, z);
-  }
+  // local copy taken before any store: scalar loads, kept in registers (read
+  // through the pointer they were reloaded after every store)
+  const Params<Real> p = A.st[k]->p;
+  const int waves = A.st[k]->waves;
+  int x, y, z;
+  if (!batch_pos(A, p, waves, blk - A.start[k], x, y, z)) return;
+  primal_node<Q, QS, Real, NT, MOM, V>(p, A.a[k], A.c[k], A.w[k], MOM ? A.m[k] : nullptr, x, y, z);
 }
 
-template <int Q, int QS, typename Real, int V>
+template <int Q, int QS, typename Real, int V, bool NT>
 __global__ __launch_bounds__(256) void k_adjoint_batch(BatchArgs<Real> A) {
   const int blk = blockIdx.x;
   const int k = batch_find(A, blk);
-  const BatchStatic<Real>& S = *A.st[k];
-  const int lb = blk - A.start[k];
-  const int gx = S.waves / A.kw;  // blocks per row
-  const int bx = lb % gx, row = lb / gx;
-  const int x = bx * (kWave * A.kw) + threadIdx.x;
-  if (x >= S.p.nx) return;
-  const int y = row % S.p.ny, z = row / S.p.ny;
-  if (S.nt)
-    adjoint_node<Q, QS, Real, true, V>(S.p, A.a[k], A.b[k], A.c[k], S.w, S.grad, x, y, z);
-  else
-    adjoint_node<Q, QS, Real, false, V>(S.p, A.a[k], A.b[k], A.c[k], S.w, S.grad, x, y, z);
+  // local copy taken before any store: scalar loads, kept in registers (read
+  // through the pointer they were reloaded after every store)
+  const Params<Real> p = A.st[k]->p;
+  const int waves = A.st[k]->waves;
+  int x, y, z;
+  if (!batch_pos(A, p, waves, blk - A.start[k], x, y, z)) return;
+  adjoint_node<Q, QS, Real, NT, V>(p, A.a[k], A.b[k], A.c[k], A.w[k], A.g[k], x, y, z);
 }
 
 // ------------------------------------------------------- small helpers

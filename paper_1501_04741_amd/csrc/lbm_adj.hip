@@ -349,6 +349,28 @@ Geo node_geometry(const lbm_config& c) {
   return g;
 }
 
+// Waves per block the hot kernels (primal, adjoint, one-shot) and batched
+// launches aim for when a row is narrower (their kernels are bounded to 256
+// threads).  Measured on D3Q19 FP32: 96x48x48 recorded in place 0.43 -> 0.48 of
+// HBM peak (one 128-thread row per block against two rows per block); no change
+// at 128x192x192, 192x96x96 or 256x128x128.
+constexpr int kHotWaves = 4;
+
+// Launch geometry of the hot kernels: as node_geometry, and when a row is a
+// single block part (nx <= 256), R consecutive rows share a block (blockDim.y =
+// R) so that it holds about the target number of waves.
+Geo hot_geometry(const lbm_config& c) {
+  Geo g = node_geometry(c);
+  const int waves = (c.nx + 63) / 64;
+  const int k = (int)g.block.x / 64;
+  if (k == waves) {
+    const int R = std::max(1, kHotWaves / k);
+    g.block = dim3(64 * k, R, 1);
+    g.grid = dim3(1, (c.ny + R - 1) / R, c.nz);
+  }
+  return g;
+}
+
 dim3 flat_grid(size_t n) {
   size_t b = (n + 255) / 256;
   return dim3((unsigned)std::min<size_t>(std::max<size_t>(b, 1), 65536), 1, 1);
@@ -375,6 +397,24 @@ int batch_block_waves(lbm_ctx* const* cs, int n) {
   return 1;
 }
 
+// Row parts per block of a batched launch: several rows per block only when
+// every member's row is a single part of kw waves.
+int batch_rows_per_block(lbm_ctx* const* cs, int n, int kw) {
+  for (int k = 0; k < n; ++k)
+    if (batch_waves(cs[k]) != kw) return 1;
+  return std::max(1, kHotWaves / kw);
+}
+
+// Streaming stores and hints in a batched ping-pong launch: decided on the
+// states the launch touches together (a source and a destination per member),
+// not per member: eight 90 MB states are far beyond the cache although each
+// member's pair alone fits.
+int batch_nt(lbm_ctx* const* cs, int n) {
+  uint64_t bytes = 0;
+  for (int k = 0; k < n; ++k) bytes += 2 * cs[k]->plan.state_bytes;
+  return bytes > kLastLevelCacheBytes ? 1 : 0;
+}
+
 // Window of the time-averaged objective: slot s holds state f^{N-W+1+s}.
 double* win_glob(lbm_ctx* c, int64_t s) { return (double*)c->win + s * (kNG + 1); }
 void* win_cols(lbm_ctx* c, int64_t s) {
@@ -387,12 +427,25 @@ struct Ops {
   using RealT = Real;
   static constexpr int kQ = Q, kQS = QS;
   static Params<Real> P(lbm_ctx* c) { return make_params<Real>(c->cfg, c->plan.N); }
-  static int batch_blocks(lbm_ctx* c, int kw) { return batch_waves(c) / kw * c->cfg.ny * c->cfg.nz; }
+  static int batch_blocks(lbm_ctx* c, int kw, int rpb) {
+    const int rows = c->cfg.ny * c->cfg.nz;
+    return rpb == 1 ? batch_waves(c) / kw * rows : (rows + rpb - 1) / rpb;
+  }
   static void primal_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks) {
-    hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V>), dim3(blocks), dim3(kWave * A.kw), 0, st, A);
+    const dim3 g(blocks), b(kWave * A.kw * A.rpb);
+    const bool mom = A.m[0] != nullptr;  // every member records, or none
+    if (A.nt) {
+      if (mom) hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, true, true>), g, b, 0, st, A);
+      else hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, true, false>), g, b, 0, st, A);
+    } else {
+      if (mom) hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, false, true>), g, b, 0, st, A);
+      else hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, false, false>), g, b, 0, st, A);
+    }
   }
   static void adjoint_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks) {
-    hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V>), dim3(blocks), dim3(kWave * A.kw), 0, st, A);
+    const dim3 g(blocks), b(kWave * A.kw * A.rpb);
+    if (A.nt) hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V, true>), g, b, 0, st, A);
+    else hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V, false>), g, b, 0, st, A);
   }
 
   // streaming stores (and cotangent loads) when the state buffers a launch touches exceed the
@@ -409,7 +462,7 @@ struct Ops {
   // loads in both phases (0.662 -> 0.750 at 512x256x128, 0.668 -> 0.815 at
   // 512x128x128; ping-pong 0.753 and 0.766).
   static void primal_inplace(lbm_ctx* c, void* buf, int64_t t, void* mom) {
-    Geo g = node_geometry(c->cfg);
+    Geo g = hot_geometry(c->cfg);
     Real* a = (Real*)buf;
     const Real* w = (const Real*)c->w;
     Real* m = (Real*)mom;
@@ -439,7 +492,7 @@ struct Ops {
 #undef LBM_PI
   }
   static void oneshot_inplace(lbm_ctx* c, double zeta, double pen) {
-    Geo g = node_geometry(c->cfg);
+    Geo g = hot_geometry(c->cfg);
     Real* a = (Real*)c->cur;
     Real* l = (Real*)c->lam[0];
     Real* w = (Real*)c->w;
@@ -462,10 +515,7 @@ struct Ops {
     static_assert(sizeof(BatchStatic<Real>) <= kDescBytes, "descriptor region too small");
     BatchStatic<Real> h;
     h.p = P(c);
-    h.w = (const Real*)c->w;
-    h.grad = (Real*)c->grad;
     h.waves = batch_waves(c);
-    h.nt = nt(c, 2) ? 1 : 0;
     hipLaunchKernelGGL((k_write_desc<Real>), dim3(1), dim3(64), 0, c->stream, h, (BatchStatic<Real>*)c->desc);
     return launch_check(c, "descriptor upload");
   }
@@ -473,7 +523,7 @@ struct Ops {
                 "moment count mismatch");
   // One primal step; records the moments of the pulled state when mom != null.
   static void primal(lbm_ctx* c, const void* src, void* dst, void* mom = nullptr) {
-    Geo g = node_geometry(c->cfg);
+    Geo g = hot_geometry(c->cfg);
     const Real* s = (const Real*)src;
     Real* d = (Real*)dst;
     const Real* w = (const Real*)c->w;
@@ -520,7 +570,7 @@ struct Ops {
   // One in-place adjoint step: the cotangent buffer is in the odd-pattern layout
   // after an even number of adjoint steps (the seed writes that layout).
   static void adjoint_inplace(lbm_ctx* c, const void* mom, int64_t steps_done) {
-    Geo g = node_geometry(c->cfg);
+    Geo g = hot_geometry(c->cfg);
     const Real* m = (const Real*)mom;
     Real* l = (Real*)c->lam[0];
     const Real* w = (const Real*)c->w;
@@ -541,7 +591,7 @@ struct Ops {
 #undef LBM_AI
   }
   static void adjoint(lbm_ctx* c, const void* mom, const void* lin, void* lout) {
-    Geo g = node_geometry(c->cfg);
+    Geo g = hot_geometry(c->cfg);
     if (nt(c, 2))
       hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true, V>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
                          (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
@@ -551,7 +601,7 @@ struct Ops {
   }
   static void oneshot(lbm_ctx* c, const void* src, void* dst, const void* lin, void* lout, double zeta,
                       double pen) {
-    Geo g = node_geometry(c->cfg);
+    Geo g = hot_geometry(c->cfg);
     if (nt(c, 4))
       hipLaunchKernelGGL((k_oneshot<Q, QS, Real, true, V>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
                          (Real*)dst, (const Real*)lin, (Real*)lout, (Real*)c->w, (Real*)c->grad,
@@ -910,6 +960,8 @@ struct RunPrimalBatch {
     std::memset(&A, 0, sizeof A);
     A.n = n;
     A.kw = batch_block_waves(cs, n);
+    A.rpb = batch_rows_per_block(cs, n, A.kw);
+    A.nt = batch_nt(cs, n);
     for (int64_t i = 0; i < nsteps; ++i) {
       int total = 0;
       for (int k = 0; k < n; ++k) {
@@ -917,11 +969,13 @@ struct RunPrimalBatch {
         void* dst = record ? rec_dst(c, c->t) : other_pp(c, c->cur);
         A.start[k] = total;
         A.st[k] = (const BatchStatic<Real>*)c->desc;
+        A.w[k] = (const Real*)c->w;
+        A.g[k] = (Real*)c->grad;
         A.a[k] = (const Real*)c->cur;
         A.b[k] = nullptr;
         A.c[k] = (Real*)dst;
         A.m[k] = record ? (Real*)mom_slot(c, c->t) : nullptr;
-        total += O::batch_blocks(c, A.kw);
+        total += O::batch_blocks(c, A.kw, A.rpb);
         c->cur = dst;
         ++c->t;
       }
@@ -969,6 +1023,8 @@ struct RunAdjointBatch {
         for (int q = 0; q < nn; ++q)
           if (first[q] + r <= last[q]) mem[nm++] = need[q];
         A.kw = batch_block_waves(mem, nm);
+        A.rpb = batch_rows_per_block(mem, nm, A.kw);
+        A.nt = batch_nt(mem, nm);
         int m = 0, total = 0;
         for (int q = 0; q < nn; ++q) {
           const int64_t kk = first[q] + r;
@@ -977,11 +1033,13 @@ struct RunAdjointBatch {
           void* dst = other_pp(c, src[q]);
           A.start[m] = total;
           A.st[m] = (const BatchStatic<Real>*)c->desc;
+          A.w[m] = (const Real*)c->w;
+          A.g[m] = (Real*)c->grad;
           A.a[m] = (const Real*)src[q];
           A.b[m] = nullptr;
           A.c[m] = (Real*)dst;
           A.m[m] = (Real*)mom_slot(c, kk);
-          total += O::batch_blocks(c, A.kw);
+          total += O::batch_blocks(c, A.kw, A.rpb);
           src[q] = dst;
           ++m;
         }
@@ -994,16 +1052,20 @@ struct RunAdjointBatch {
       int total = 0;
       A.n = n;
       A.kw = batch_block_waves(cs, n);
+      A.rpb = batch_rows_per_block(cs, n, A.kw);
+      A.nt = batch_nt(cs, n);
       for (int k = 0; k < n; ++k) {
         lbm_ctx* c = cs[k];
         const int64_t nstep = c->t_adj - 1;
         A.start[k] = total;
         A.st[k] = (const BatchStatic<Real>*)c->desc;
+        A.w[k] = (const Real*)c->w;
+        A.g[k] = (Real*)c->grad;
         A.a[k] = (const Real*)mom_slot(c, nstep);
         A.m[k] = nullptr;
         A.b[k] = (const Real*)c->lam[c->lam_cur];
         A.c[k] = (Real*)c->lam[1 - c->lam_cur];
-        total += O::batch_blocks(c, A.kw);
+        total += O::batch_blocks(c, A.kw, A.rpb);
         c->lam_cur ^= 1;
         --c->t_adj;
       }
