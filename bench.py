@@ -326,8 +326,9 @@ def recompute_leg(dev, workload="d3q19_channel_256x128x128", inplace=True):
 
 def batched_leg(dev, n_ctx=8, steps=100):
     """Batched launches at HBM scale: n_ctx D3Q19 FP32 channels of 128x96x96 (90 MB
-    state each, 1.4 GB per ping-pong step over eight of them), every step's moments
-    held, advanced by one k_primal_batch / k_adjoint_batch launch per step; the
+    state each, 0.7 GB per in-place step over eight of them), every step's
+    moments held, advanced by one k_primal_batch / k_adjoint_batch launch per
+    step, streamed in place (the serving form) and with ping-pong buffers; the
     same contexts one at a time with the single-context kernels for comparison."""
     import numpy as np
     import torch
@@ -340,45 +341,57 @@ def batched_leg(dev, n_ctx=8, steps=100):
     p.pop("filter")
     p.update(c_dp=1.0, c_hf=0.0, c_var=0.0)
     ws = [torch.from_numpy(inputs.porosity(128, 96, 96, 100 + k, 5, np.float32)).to(dev) for k in range(n_ctx)]
-    ctxs = [Lbm(p, nsteps=steps, precision="fp32", checkpoint_interval=steps, device=dev) for _ in range(n_ctx)]
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
-    h = [c.ctx for c in ctxs]
-    for rep_ in range(2):  # the second pass is timed
-        for c, w in zip(ctxs, ws):
-            c.set_design(w)
-            c.reset()
-        ev[0].record()
-        L.lbm_primal_steps_batch(h, steps, record=True)
-        ev[1].record()
-        L.lbm_adjoint_steps_batch(h, 1)
-        ev[2].record()
-        L.lbm_adjoint_steps_batch(h, steps - 1)
-        ev[3].record()
-    # the same work one context at a time (single-context kernels)
-    for c, w in zip(ctxs, ws):
-        c.set_design(w)
-        c.reset()
-    ev[4].record()
-    for c in ctxs:
-        c.primal_steps(steps, record=True)
-    ev[5].record()
-    torch.cuda.synchronize()
-    for c in ctxs:
-        c.close()
     pb, ab = algorithmic_bytes(p, "fp32")
-    prim_us = ev[0].elapsed_time(ev[1]) * 1e3 / steps
-    adj_us = ev[2].elapsed_time(ev[3]) * 1e3 / (steps - 1)
-    single_us = ev[4].elapsed_time(ev[5]) * 1e3 / (steps * n_ctx)
     roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
     key = "d3q19_batch_%dx128x96x96" % n_ctx
-    return {"workload": "%d x D3Q19 128x96x96 FP32 channels, %d recorded steps, every step's moments held" % (
-                n_ctx, steps),
-            "primal": {"kernel": "k_primal_batch<19,0,float>",
-                       "roofline": dict(roof(n_ctx * pb, prim_us), traffic=_measured_traffic(key, "k_primal_batch"))},
-            "adjoint": {"kernel": "k_adjoint_batch<19,0,float>",
-                        "roofline": dict(roof(n_ctx * ab, adj_us), traffic=_measured_traffic(key, "k_adjoint_batch"))},
-            "primal_single_context": {"kernel": "k_primal<19,0,float>", "roofline": roof(pb, single_us)}}
+    out = {"workload": "%d x D3Q19 128x96x96 FP32 channels, %d recorded steps, every step's moments held" % (
+        n_ctx, steps)}
+    for inplace in (True, False):
+        ctxs = [Lbm(p, nsteps=steps, precision="fp32", checkpoint_interval=steps, device=dev, inplace=inplace)
+                for _ in range(n_ctx)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        h = [c.ctx for c in ctxs]
+        for rep_ in range(2):  # the second pass is timed
+            for c, w in zip(ctxs, ws):
+                c.set_design(w)
+                c.reset()
+            ev[0].record()
+            L.lbm_primal_steps_batch(h, steps, record=True)
+            ev[1].record()
+            L.lbm_adjoint_steps_batch(h, 1)
+            ev[2].record()
+            L.lbm_adjoint_steps_batch(h, steps - 1)
+            ev[3].record()
+        # the same work one context at a time (single-context kernels)
+        for c, w in zip(ctxs, ws):
+            c.set_design(w)
+            c.reset()
+        ev[4].record()
+        for c in ctxs:
+            c.primal_steps(steps, record=True)
+        ev[5].record()
+        torch.cuda.synchronize()
+        for c in ctxs:
+            c.close()
+        prim_us = ev[0].elapsed_time(ev[1]) * 1e3 / steps
+        adj_us = ev[2].elapsed_time(ev[3]) * 1e3 / (steps - 1)
+        single_us = ev[4].elapsed_time(ev[5]) * 1e3 / (steps * n_ctx)
+        sub = "inplace" if inplace else "ping_pong"
+        kern = "<19,0,float,%s>" % ("in place" if inplace else "ping-pong")
+        r = {"primal": {"kernel": "k_primal_batch" + kern,
+                        "roofline": dict(roof(n_ctx * pb, prim_us),
+                                         traffic=_measured_traffic(key, "k_primal_batch_" + sub))},
+             "adjoint": {"kernel": "k_adjoint_batch" + kern,
+                         "roofline": dict(roof(n_ctx * ab, adj_us),
+                                          traffic=_measured_traffic(key, "k_adjoint_batch_" + sub))},
+             "primal_single_context": {"kernel": ("k_primal_inplace" if inplace else "k_primal") + "<19,0,float>",
+                                       "roofline": roof(pb, single_us)}}
+        if inplace:
+            out.update(r)
+        else:
+            out["ping_pong"] = r
+    return out
 
 
 def inplace_leg(dev, steps=200):
@@ -617,8 +630,7 @@ def main(argv=None):
     ap.add_argument("--serve-steps", type=int, default=2000, help="primal (= adjoint) steps per request")
     ap.add_argument("--budget-gb", type=float, default=240.0, help="HBM budget for admitted requests")
     ap.add_argument("--inplace-min-mb", type=float, default=32.0,
-                    help="served requests whose state is at least this large stream in place with single-context "
-                         "launches (negative: never)")
+                    help="served requests whose state is at least this large stream in place (negative: never)")
     ap.add_argument("--request-cap-gb", type=float, default=64.0,
                     help="workspace cap per served request: every step's moments are held (no recompute) "
                          "when they fit, else the largest checkpoint interval that does")

@@ -149,8 +149,8 @@ typedef struct lbm_config {
                           * and the adjoint recomputes each segment in      *
                           * place inside its checkpoint.  With nsteps = 0   *
                           * only unrecorded runs and the one-shot iteration *
-                          * are available.  In-place contexts do not join   *
-                          * batched launches (LBM_EINVAL)                   */
+                          * are available.  In-place contexts batch only    *
+                          * with in-place contexts (LBM_EINVAL otherwise)   */
   int32_t reserved3;     /* must be 0                                        */
   int32_t plate_x0, plate_x1; /* heating plate of the heat exchanger (Section *
                           * 4): the bottom-wall (y = 0) nodes with           *
@@ -302,11 +302,16 @@ lbm_status lbm_plan(const lbm_ctx* ctx, int64_t* interval, int64_t* n_checkpoint
 
 /* Batched forms for many contexts with the same (flow, scalar, precision):
  * one kernel launch per step covers every context in ctxs (a descriptor
- * table in each context's workspace maps blocks to contexts).  Every context
- * must be in a state where the single-context call would be valid; the call
- * validates all first and runs none on error.  All contexts must share one
- * stream (that of ctxs[0]).  Results are bitwise identical to the
- * single-context calls. */
+ * table in each context's workspace maps blocks to contexts).  A batch is
+ * all ping-pong or all in place (inplace = 1); in place, members whose
+ * phase differs go in a second launch of the same step, checkpoint copies
+ * and recomputed segments run per member.  Every context must be in a state
+ * where the single-context call would be valid; the call validates all
+ * first and runs none on error.  All contexts must share one stream (that
+ * of ctxs[0]).  Results are bitwise identical to the single-context calls.
+ * Errors: LBM_EINVAL (n outside 1..32, a context twice, different lattices,
+ * precisions or streams, in-place and ping-pong contexts mixed, a
+ * time-averaged objective), LBM_ESTATE as the single-context calls. */
 lbm_status lbm_primal_steps_batch(lbm_ctx* const* ctxs, int32_t n, int64_t nsteps, int32_t record);
 lbm_status lbm_adjoint_steps_batch(lbm_ctx* const* ctxs, int32_t n, int64_t nsteps);
 

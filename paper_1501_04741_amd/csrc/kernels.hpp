@@ -1694,12 +1694,13 @@ struct BatchArgs {
   int n;
   int kw;   // waves per row part (64 kw threads), dividing every context's waves per row
   int rpb;  // row parts per block (blockDim.x = 64 kw rpb); > 1 only when every row is one part
-  int nt;  // streaming stores and hints: the states the launch touches exceed the last-level cache
+  int nt;   // streaming stores and hints: the states the launch touches exceed the last-level cache
+  int nte;  // in place: the even phase's loads take the hint too (states far beyond the cache)
   int start[kBatchMax + 1];
   const BatchStatic<Real>* st[kBatchMax];
   const Real* a[kBatchMax];  // primal: source state; adjoint: moments of f^n
-  const Real* b[kBatchMax];  // adjoint: lambda^{n+1}
-  Real* c[kBatchMax];        // primal: destination; adjoint: lambda^n
+  const Real* b[kBatchMax];  // adjoint: lambda^{n+1} (in place: the cotangent buffer)
+  Real* c[kBatchMax];        // primal: destination (in place: = a); adjoint: lambda^n (in place: = b)
   Real* m[kBatchMax];        // primal: where to record moments (all set or all null)
   const Real* w[kBatchMax];  // design field
   Real* g[kBatchMax];        // adjoint: gradient accumulator
@@ -1749,7 +1750,9 @@ __device__ __forceinline__ int batch_find(const BatchArgs<Real>& A, int blk) {
 // NT (streaming stores and hints) and MOM (record the moments) are uniform over
 // a launch, so they are template arguments: one code path per kernel keeps the
 // register count of the single-context kernels.
-template <int Q, int QS, typename Real, int V, bool NT, bool MOM>
+// ACC: ping-pong (a = source, c = destination) or one in-place phase (a = c =
+// the member's working buffer; members of other phases go in another launch).
+template <int Q, int QS, typename Real, int V, bool NT, bool MOM, int ACC, bool NTE = false>
 __global__ __launch_bounds__(256) void k_primal_batch(BatchArgs<Real> A) {
   const int blk = blockIdx.x;
   const int k = batch_find(A, blk);
@@ -1759,10 +1762,11 @@ __global__ __launch_bounds__(256) void k_primal_batch(BatchArgs<Real> A) {
   const int waves = A.st[k]->waves;
   int x, y, z;
   if (!batch_pos(A, p, waves, blk - A.start[k], x, y, z)) return;
-  primal_node<Q, QS, Real, NT, MOM, V>(p, A.a[k], A.c[k], A.w[k], MOM ? A.m[k] : nullptr, x, y, z);
+  primal_node<Q, QS, Real, NT, MOM, V, ACC, NTE>(p, A.a[k], A.c[k], A.w[k], MOM ? A.m[k] : nullptr, x, y, z);
 }
 
-template <int Q, int QS, typename Real, int V, bool NT>
+// ACC: ping-pong (b = lambda^{n+1}, c = lambda^n) or one in-place pattern (b = c).
+template <int Q, int QS, typename Real, int V, bool NT, int ACC, bool NTE = false>
 __global__ __launch_bounds__(256) void k_adjoint_batch(BatchArgs<Real> A) {
   const int blk = blockIdx.x;
   const int k = batch_find(A, blk);
@@ -1772,7 +1776,7 @@ __global__ __launch_bounds__(256) void k_adjoint_batch(BatchArgs<Real> A) {
   const int waves = A.st[k]->waves;
   int x, y, z;
   if (!batch_pos(A, p, waves, blk - A.start[k], x, y, z)) return;
-  adjoint_node<Q, QS, Real, NT, V>(p, A.a[k], A.b[k], A.c[k], A.w[k], A.g[k], x, y, z);
+  adjoint_node<Q, QS, Real, NT, V, ACC, NTE>(p, A.a[k], A.b[k], A.c[k], A.w[k], A.g[k], x, y, z);
 }
 
 // ------------------------------------------------------- small helpers

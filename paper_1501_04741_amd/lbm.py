@@ -334,8 +334,9 @@ class Lbm:
         inplace: stream in place (one primal and one adjoint buffer, each read and
         rewritten by every step).  With nsteps = 0 the context runs unrecorded steps
         and the one-shot iteration; with nsteps > 0 a recorded run keeps the moments
-        of every step (no checkpoints, no recompute: checkpoint_interval must be 0
-        or >= nsteps) and its adjoint streams in place too."""
+        of every step unless checkpoint_interval (1 <= C < nsteps) or the budget asks
+        for checkpoints, whose segments the adjoint then recomputes in place; the
+        adjoint streams in place too."""
         library()
         self.device = torch.device(device if device is not None else "cuda")
         self.params = dict(params)

@@ -129,15 +129,15 @@ def test_inplace_set_state_round_trip():
         _same_state(a, b)
 
 
-def test_inplace_refuses_recording_adjoint_and_batches():
+def test_inplace_refuses_recording_adjoint_and_mixed_batches():
     p = CASES[0][1]
     a, b = _pair(p, "fp32")
     with pytest.raises(LbmError):
         b.primal_steps(1, record=True)
     with pytest.raises(LbmError):
         b.adjoint_steps(1)
-    with pytest.raises(LbmError):
-        L.lbm_primal_steps_batch([b.ctx], 1, record=False)
+    with pytest.raises(LbmError):  # a batch is all in place or all ping-pong
+        L.lbm_primal_steps_batch([b.ctx, a.ctx], 1, record=False)
     b.primal_steps(2)                    # still usable
     a.primal_steps(2)
     _same_state(a, b)

@@ -84,6 +84,76 @@ def test_batched_block_widths_bitwise_equal_single(widths):
         assert np.array_equal(c.gradient().cpu().numpy(), g)
 
 
+def _alone_inplace(p, w, steps, prec, interval=0):
+    ctx = Lbm(p, nsteps=steps, precision=prec, checkpoint_interval=interval, inplace=True)
+    J, g = ctx.value_and_grad(torch.from_numpy(w))
+    out = (J, g.cpu().numpy())
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("kind", ["d2q9", "d3q19_d3q7"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_inplace_batched_bitwise_equals_single_inplace(kind, prec):
+    """In-place members (store-all and checkpointed plans, whose segments are
+    recomputed in place) batched together, with members one step apart so that
+    every batched step and every batched adjoint step runs two launches (one
+    per phase): J and the gradient equal the single-context in-place run
+    bitwise, which in turn equals the ping-pong run."""
+    if kind == "d2q9":
+        ps = [_p(9, 0, 40, 12, 1), _p(9, 0, 70, 9, 1), _p(9, 0, 300, 6, 1), _p(9, 0, 128, 17, 1)]
+    else:
+        ps = [_p(19, 7, 18, 8, 7), _p(19, 7, 33, 6, 5), _p(19, 7, 64, 9, 6)]
+    steps = 31
+    intervals = [0, 5, 9, 4][: len(ps)]
+    dt = np.float32 if prec == "fp32" else np.float64
+    ws = [inputs.porosity(p["nx"], p["ny"], p["nz"], 20 + i, 3, dt) for i, p in enumerate(ps)]
+    ref = [_alone_inplace(p, w, steps, prec, c) for p, w, c in zip(ps, ws, intervals)]
+    pp = _alone(ps[1], ws[1], steps, prec, intervals[1])
+    assert pp[0] == ref[1][0] and np.array_equal(pp[1], ref[1][1])
+    ctxs = [Lbm(p, nsteps=steps, precision=prec, checkpoint_interval=c, inplace=True) for p, c in zip(ps, intervals)]
+    for c, w in zip(ctxs, ws):
+        c.set_design(torch.from_numpy(w))
+        c.reset()
+    handles = [c.ctx for c in ctxs]
+    ctxs[0].primal_steps(1, record=True)  # member 0 runs one step ahead: mixed phases
+    for k in (6, 13):
+        L.lbm_primal_steps_batch(handles, k, record=True)
+    ctxs[0].primal_steps(steps - 20, record=True)
+    L.lbm_primal_steps_batch(handles[1:], steps - 19, record=True)
+    Js = [c.objective()[0] for c in ctxs]
+    ctxs[-1].adjoint_steps(1)  # the last member one adjoint step ahead: mixed patterns
+    for k in (4, 12):
+        L.lbm_adjoint_steps_batch(handles, k)
+    ctxs[-1].adjoint_steps(steps - 17)
+    L.lbm_adjoint_steps_batch(handles[:-1], steps - 16)
+    for c, (J, g), Jb in zip(ctxs, ref, Js):
+        assert Jb == J
+        assert np.array_equal(c.gradient().cpu().numpy(), g)
+
+
+def test_inplace_batched_unrecorded_steps_bitwise_equal_single():
+    ps = [_p(19, 7, 18, 8, 7), _p(19, 7, 33, 6, 5), _p(19, 7, 128, 9, 6)]
+    ws = [inputs.porosity(p["nx"], p["ny"], p["nz"], 30 + i, 3, np.float64) for i, p in enumerate(ps)]
+    single = [Lbm(p, nsteps=0, precision="fp64", inplace=True) for p in ps]
+    batch = [Lbm(p, nsteps=0, precision="fp64", inplace=True) for p in ps]
+    for a, b, w in zip(single, batch, ws):
+        a.set_design(torch.from_numpy(w))
+        b.set_design(torch.from_numpy(w))
+        a.reset()
+        b.reset()
+    batch[1].primal_steps(1)  # one step ahead: mixed phases
+    L.lbm_primal_steps_batch([b.ctx for b in batch], 24, record=False)
+    L.lbm_primal_steps_batch([batch[0].ctx, batch[2].ctx], 1, record=False)
+    for a in single:
+        a.primal_steps(25)
+    for a, b in zip(single, batch):
+        fa, ga = a.get_state()
+        fb, gb = b.get_state()
+        assert torch.equal(fa, fb) and torch.equal(ga, gb)
+        assert a.objective()[0] == b.objective()[0]
+
+
 def test_batched_abi_rejects_mixed_kinds_and_bad_state():
     a = Lbm(_p(9, 0, 20, 8, 1), nsteps=4, precision="fp32")
     b = Lbm(_p(19, 0, 8, 6, 5), nsteps=4, precision="fp32")
@@ -133,7 +203,8 @@ def test_served_results_equal_alone_bitwise():
     srv.drain()
     assert all(j.state == DONE for j in jobs), [(j.rid, j.state, j.error) for j in jobs]
     for j in jobs:
-        ctx = Lbm(j.params, nsteps=j.steps, precision=j.precision, hbm_budget_bytes=ex._plan_bytes(j))
+        ctx = Lbm(j.params, nsteps=j.steps, precision=j.precision, hbm_budget_bytes=ex._plan_bytes(j),
+                  inplace=j._inplace)
         J, g = ctx.value_and_grad(torch.from_numpy(j.design))
         assert j.J == J, (j.rid, j.J, J)
         assert np.array_equal(j.grad, g.cpu().numpy()), j.rid
@@ -165,7 +236,8 @@ def test_serving_failure_isolation():
         if j is bad:
             continue
         assert j.state == DONE
-        ctx = Lbm(j.params, nsteps=j.steps, precision=j.precision, hbm_budget_bytes=ex._plan_bytes(j))
+        ctx = Lbm(j.params, nsteps=j.steps, precision=j.precision, hbm_budget_bytes=ex._plan_bytes(j),
+                  inplace=j._inplace)
         J, g = ctx.value_and_grad(torch.from_numpy(j.design))
         assert j.J == J and np.array_equal(j.grad, g.cpu().numpy())
         ctx.close()
@@ -180,7 +252,8 @@ def test_arena_backed_server_results_equal_alone():
     assert all(j.state == DONE for j in jobs), [(j.rid, j.state, j.error) for j in jobs]
     assert ex.arena.free_bytes() == ex.arena.size
     for j in jobs:
-        ctx = Lbm(j.params, nsteps=j.steps, precision=j.precision, hbm_budget_bytes=ex._plan_bytes(j))
+        ctx = Lbm(j.params, nsteps=j.steps, precision=j.precision, hbm_budget_bytes=ex._plan_bytes(j),
+                  inplace=j._inplace)
         J, g = ctx.value_and_grad(torch.from_numpy(j.design))
         assert j.J == J and np.array_equal(j.grad, g.cpu().numpy()), j.rid
         ctx.close()
@@ -188,7 +261,7 @@ def test_arena_backed_server_results_equal_alone():
 
 def test_inplace_requests_served_equal_alone_bitwise():
     """Requests above the in-place threshold (here every request of the 40x12x10 size)
-    stream in place with single-context launches beside the batched ping-pong ones;
+    stream in place, batched among themselves beside the batched ping-pong ones;
     every result equals the request run alone (ping-pong, every step's moments held)."""
     jobs = _jobs(n_each=2, steps=33)
     big = 19 * 40 * 12 * 10 * 4
