@@ -40,8 +40,33 @@ HBM_PEAK_GBS = 8000.0
 # for the kernel sources, host dispatch and compile flags whose SHA-256 prefix is given and are
 # reported only while those files still match.
 COUNTER_TRAFFIC = {
-    "sources_sha256_16": None,
-    "bytes_per_launch": {},
+    "sources_sha256_16": "08336e4a57632a75",
+    "bytes_per_launch": {
+        "d3q19_batch_8x128x96x96": {
+            "k_adjoint_batch<19,0,float,in place>": 1689961895,
+            "k_adjoint_batch<19,0,float,ping-pong>": 1687915183,
+            "k_primal_batch<19,0,float,in place,recorded>": 1616575054,
+            "k_primal_batch<19,0,float,ping-pong,recorded>": 1615537699
+        },
+        "d3q19_channel_256x128x128": {
+            "k_adjoint<19,0,float>": 751441878,
+            "k_adjoint_inplace<19,0,double>": 1504100242,
+            "k_adjoint_inplace<19,0,float,MRT>": 751841007,
+            "k_adjoint_inplace<19,0,float>": 752388933,
+            "k_oneshot_inplace<19,0,float>": 1328551016,
+            "k_primal<19,0,float,recorded>": 718935411,
+            "k_primal_inplace<19,0,double,recorded>": 1441254092,
+            "k_primal_inplace<19,0,float,MRT,recorded>": 719383240,
+            "k_primal_inplace<19,0,float,recorded>": 719897301,
+            "k_primal_inplace<19,0,float,unrecorded>": 656420133
+        },
+        "d3q19_d3q7_mixer_empty_450x50x50": {
+            "k_oneshot<19,7,float>": 515536335,
+            "k_oneshot_inplace<19,7,float>": 512715591,
+            "k_primal<19,7,float,unrecorded>": 255636339,
+            "k_primal_inplace<19,7,float,unrecorded>": 253474559
+        }
+    }
 }
 _COUNTER_SOURCES = ("paper_1501_04741_amd/csrc/kernels.hpp", "paper_1501_04741_amd/csrc/lattice.hpp",
                     "paper_1501_04741_amd/csrc/lbm_adj.hip", "paper_1501_04741_amd/build.py")
@@ -68,6 +93,21 @@ def _measured_traffic(workload, kernel):
     if sources_sha() != COUNTER_TRAFFIC["sources_sha256_16"]:
         return None
     return COUNTER_TRAFFIC["bytes_per_launch"].get(workload, {}).get(kernel)
+
+
+def klabel(family, p, prec, mode=""):
+    """Label of a kernel variant in the bench line, and the key of its counter
+    traffic: the kernel family with lattice, precision, collision and mode
+    ("recorded" / "unrecorded" for the primal kernels, "in place" / "ping-pong"
+    for the batched ones), e.g. k_primal_inplace<19,0,float,recorded>."""
+    parts = [str(p["flow"]), str(p.get("scalar", 0)), "float" if prec == "fp32" else "double"]
+    if p.get("collision") == "mrt":
+        parts.append("MRT")
+    if p.get("tau_s_solid"):
+        parts.append("VD")
+    if mode:
+        parts.append(mode)
+    return "%s<%s>" % (family, ",".join(parts))
 
 
 def _class_counts(p):
@@ -185,15 +225,18 @@ def mixer_leg(dev, steps=4000, os_iters=400):
     roof = lambda b, us, k: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b,
                              "avg_launch_us": us, "traffic": _measured_traffic(wk, k)}
+    kp = klabel("k_primal", p, "fp32", "unrecorded")
+    kpi = klabel("k_primal_inplace", p, "fp32", "unrecorded")
+    ko = klabel("k_oneshot", p, "fp32")
+    koi = klabel("k_oneshot_inplace", p, "fp32")
     return {"workload": wk, "nodes": nodes,
-            "primal": {"kernel": "k_primal<19,7,float>", "steps_timed": steps, "mlups": nodes / prim_us,
-                       "roofline": roof(pb, prim_us, "k_primal")},
-            "oneshot": {"kernel": "k_oneshot_inplace<19,7,float>", "iterations_timed": os_iters,
-                        "mlups": nodes / osi_us, "roofline": roof(ob, osi_us, "k_oneshot_inplace")},
-            "primal_inplace": {"kernel": "k_primal_inplace<19,7,float>", "steps_timed": steps, "mlups": nodes / pi_us,
-                               "roofline": roof(pb, pi_us, "k_primal_inplace")},
-            "oneshot_ping_pong": {"kernel": "k_oneshot<19,7,float>", "iterations_timed": os_iters,
-                                  "mlups": nodes / os_us, "roofline": roof(ob, os_us, "k_oneshot")},
+            "primal": {"kernel": kp, "steps_timed": steps, "mlups": nodes / prim_us, "roofline": roof(pb, prim_us, kp)},
+            "oneshot": {"kernel": koi, "iterations_timed": os_iters,
+                        "mlups": nodes / osi_us, "roofline": roof(ob, osi_us, koi)},
+            "primal_inplace": {"kernel": kpi, "steps_timed": steps, "mlups": nodes / pi_us,
+                               "roofline": roof(pb, pi_us, kpi)},
+            "oneshot_ping_pong": {"kernel": ko, "iterations_timed": os_iters,
+                                  "mlups": nodes / os_us, "roofline": roof(ob, os_us, ko)},
             "note": "two primal states (234 MB) fit the 256 MB last-level cache; the ping-pong one-shot's four "
                     "do not, the in-place one-shot's two do"}
 
@@ -236,15 +279,16 @@ def mrt_leg(dev, steps=200, collision="mrt", inplace=True, prec="fp32"):
     roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
     sfx = "_inplace" if inplace else ""
-    tag = ",MRT" if collision == "mrt" else ""
-    real = "float" if prec == "fp32" else "double"
-    return {"workload": "d3q19_channel_256x128x128, %s collision, %s, %s" % (
-                collision.upper(), "in place" if inplace else "ping-pong", prec.upper()),
+    wk = "d3q19_channel_256x128x128"
+    kp = klabel("k_primal" + sfx, p, prec, "recorded")
+    ka = klabel("k_adjoint" + sfx, p, prec)
+    return {"workload": "%s, %s collision, %s, %s" % (
+                wk, collision.upper(), "in place" if inplace else "ping-pong", prec.upper()),
             "steps_timed": steps,
-            "primal": {"kernel": "k_primal%s<19,0,%s%s>" % (sfx, real, tag), "mlups": nodes / prim_us,
-                       "roofline": roof(pb, prim_us)},
-            "adjoint": {"kernel": "k_adjoint%s<19,0,%s%s>" % (sfx, real, tag), "mlups": nodes / adj_us,
-                        "roofline": roof(ab, adj_us)}}
+            "primal": {"kernel": kp, "mlups": nodes / prim_us,
+                       "roofline": dict(roof(pb, prim_us), traffic=_measured_traffic(wk, kp))},
+            "adjoint": {"kernel": ka, "mlups": nodes / adj_us,
+                        "roofline": dict(roof(ab, adj_us), traffic=_measured_traffic(wk, ka))}}
 
 
 def recompute_leg(dev, workload="d3q19_channel_256x128x128", inplace=True):
@@ -301,8 +345,9 @@ def recompute_leg(dev, workload="d3q19_channel_256x128x128", inplace=True):
     bwd_bytes = N * ab + recomputed * pb
     roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
-    real = "float" if prec == "fp32" else "double"
     sfx = "_inplace" if inplace else ""
+    kp = klabel("k_primal" + sfx, p, prec, "recorded")
+    ka = klabel("k_adjoint" + sfx, p, prec)
     return {"workload": "%s, checkpoint every %d steps (%d checkpoints, %d moment sets), %s" % (
                 workload, C, plan["checkpoints"], plan["moment_sets"], "in place" if inplace else "ping-pong"),
             "lbm_steps": N, "checkpoint_interval": C, "workspace_gb": round(ws / 1e9, 3),
@@ -316,12 +361,10 @@ def recompute_leg(dev, workload="d3q19_channel_256x128x128", inplace=True):
                                   "frac": bwd_bytes / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                   "bytes": bwd_bytes,
                                   "note": "N adjoint launches + the recorded primal launches of the recompute"},
-            "primal": {"kernel": "k_primal%s<19,0,%s>" % (sfx, real), "mlups": nodes / prim_us,
-                       "roofline": dict(roof(pb, prim_us),
-                                        traffic=_measured_traffic(workload, "k_primal" + sfx))},
-            "adjoint": {"kernel": "k_adjoint%s<19,0,%s>" % (sfx, real), "mlups": nodes / adj_us,
-                        "roofline": dict(roof(ab, adj_us),
-                                         traffic=_measured_traffic(workload, "k_adjoint" + sfx))}}
+            "primal": {"kernel": kp, "mlups": nodes / prim_us,
+                       "roofline": dict(roof(pb, prim_us), traffic=_measured_traffic(workload, kp))},
+            "adjoint": {"kernel": ka, "mlups": nodes / adj_us,
+                        "roofline": dict(roof(ab, adj_us), traffic=_measured_traffic(workload, ka))}}
 
 
 def batched_leg(dev, n_ctx=8, steps=100):
@@ -377,16 +420,14 @@ def batched_leg(dev, n_ctx=8, steps=100):
         prim_us = ev[0].elapsed_time(ev[1]) * 1e3 / steps
         adj_us = ev[2].elapsed_time(ev[3]) * 1e3 / (steps - 1)
         single_us = ev[4].elapsed_time(ev[5]) * 1e3 / (steps * n_ctx)
-        sub = "inplace" if inplace else "ping_pong"
-        kern = "<19,0,float,%s>" % ("in place" if inplace else "ping-pong")
-        r = {"primal": {"kernel": "k_primal_batch" + kern,
-                        "roofline": dict(roof(n_ctx * pb, prim_us),
-                                         traffic=_measured_traffic(key, "k_primal_batch_" + sub))},
-             "adjoint": {"kernel": "k_adjoint_batch" + kern,
-                         "roofline": dict(roof(n_ctx * ab, adj_us),
-                                          traffic=_measured_traffic(key, "k_adjoint_batch_" + sub))},
-             "primal_single_context": {"kernel": ("k_primal_inplace" if inplace else "k_primal") + "<19,0,float>",
-                                       "roofline": roof(pb, single_us)}}
+        mode = "in place" if inplace else "ping-pong"
+        kp = klabel("k_primal_batch", p, "fp32", mode + ",recorded")
+        ka = klabel("k_adjoint_batch", p, "fp32", mode)
+        r = {"primal": {"kernel": kp, "roofline": dict(roof(n_ctx * pb, prim_us), traffic=_measured_traffic(key, kp))},
+             "adjoint": {"kernel": ka, "roofline": dict(roof(n_ctx * ab, adj_us), traffic=_measured_traffic(key, ka))},
+             "primal_single_context": {
+                 "kernel": klabel("k_primal_inplace" if inplace else "k_primal", p, "fp32", "recorded"),
+                 "roofline": roof(pb, single_us)}}
         if inplace:
             out.update(r)
         else:
@@ -429,9 +470,14 @@ def inplace_leg(dev, steps=200):
     nodes = p["nx"] * p["ny"] * p["nz"]
     roof = lambda b, us: {"bound": "hbm", "achieved": b / (us * 1e-6) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                           "frac": b / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, "bytes_per_launch": b, "avg_launch_us": us}
-    return {"workload": "d3q19_channel_256x128x128 streamed in place", "steps_timed": steps,
-            "primal": {"kernel": "k_primal_inplace<19,0,float>", "mlups": nodes / prim_us, "roofline": roof(pb, prim_us)},
-            "oneshot": {"kernel": "k_oneshot_inplace<19,0,float>", "mlups": nodes / os_us, "roofline": roof(ob, os_us)},
+    wk = "d3q19_channel_256x128x128"
+    kp = klabel("k_primal_inplace", p, "fp32", "unrecorded")
+    ko = klabel("k_oneshot_inplace", p, "fp32")
+    return {"workload": wk + " streamed in place", "steps_timed": steps,
+            "primal": {"kernel": kp, "mlups": nodes / prim_us,
+                       "roofline": dict(roof(pb, prim_us), traffic=_measured_traffic(wk, kp))},
+            "oneshot": {"kernel": ko, "mlups": nodes / os_us,
+                        "roofline": dict(roof(ob, os_us), traffic=_measured_traffic(wk, ko))},
             "workspace_gb": {"inplace": round(ws_inplace / 1e9, 3), "ping_pong": round(ws_pp / 1e9, 3)}}
 
 
@@ -750,8 +796,9 @@ def main(argv=None):
 
     nodes = L.N
     pb, ab = algorithmic_bytes(p, prec)
-    kname = lambda k: "%s%s<%d,%d,%s>" % (k, "_inplace" if inplace else "", p["flow"], p.get("scalar", 0),
-                                           "float" if prec == "fp32" else "double")
+    sfx = "_inplace" if inplace else ""
+    kp, ka, ko = (klabel("k_primal" + sfx, p, prec, "recorded"), klabel("k_adjoint" + sfx, p, prec),
+                  klabel("k_oneshot" + sfx, p, prec))
     ob = oneshot_bytes(p, prec)
     os_gbs = ob / (os_launch_ms * 1e-3) / 1e9
     prim_gbs = pb / (primal_launch_ms * 1e-3) / 1e9
@@ -788,21 +835,21 @@ def main(argv=None):
         "forward_ms": fwd_ms,
         "backward_ms": bwd_ms,
         "roofline": None,  # the dominant kernel's, filled in below
-        "roofline_primal": {"bound": "hbm", "kernel": kname("k_primal"), "achieved": prim_gbs,
+        "roofline_primal": {"bound": "hbm", "kernel": kp, "achieved": prim_gbs,
                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": prim_gbs / HBM_PEAK_GBS,
-                            "traffic": _measured_traffic(args.workload, kname("k_primal").split("<")[0]),
+                            "traffic": _measured_traffic(args.workload, kp),
                             "bytes_per_launch": pb, "avg_launch_us": primal_launch_ms * 1e3},
-        "roofline_adjoint": {"bound": "hbm", "kernel": kname("k_adjoint"), "achieved": adj_gbs,
+        "roofline_adjoint": {"bound": "hbm", "kernel": ka, "achieved": adj_gbs,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": (adj_gbs / HBM_PEAK_GBS) if adj_gbs else None,
-                             "traffic": _measured_traffic(args.workload, kname("k_adjoint").split("<")[0]),
+                             "traffic": _measured_traffic(args.workload, ka),
                              "bytes_per_launch": ab,
                              "avg_launch_us": adjoint_launch_ms * 1e3 if k_last > 1 else None},
-        "oneshot": {"kernel": kname("k_oneshot"), "iterations_timed": os_iters,
+        "oneshot": {"kernel": ko, "iterations_timed": os_iters,
                     "mlups": nodes / (os_launch_ms * 1e-3) / 1e6,
                     "roofline": {"bound": "hbm", "achieved": os_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                  "frac": os_gbs / HBM_PEAK_GBS,
-                                 "traffic": _measured_traffic(args.workload, kname("k_oneshot").split("<")[0]),
+                                 "traffic": _measured_traffic(args.workload, ko),
                                  "bytes_per_launch": ob,
                                  "avg_launch_us": os_launch_ms * 1e3}},
     }
