@@ -409,6 +409,213 @@ __device__ __forceinline__ void store_cot(Real* a, const Nbr& b, const Real (&lf
   }
 }
 
+// ------------------------------------------------ x-shifts through LDS
+// When a block spans whole rows (nx at most its width), the populations whose
+// access is shifted along x (e_x != 0) are read and written line-aligned: for
+// a load every thread reads the value at its own x of the source run into LDS
+// and, after a barrier, takes the one at x - e_x (the shift wraps inside the
+// row, as the periodic pull does); for a store it writes its result at x + e_x
+// of the LDS run and, after a barrier, stores the value at its own x.  Every
+// global access is then a whole-wave, line-aligned run and no cache line is
+// shared between waves.  lds holds bt values per shifted population (one run
+// per block row: the calling thread's row starts at seg, its position in the
+// row is its x); act is false for padding lanes and rows, which skip every
+// global access but take part in every barrier.
+template <int Q, int QS>
+struct Shifted {
+  __host__ __device__ static constexpr int flow_slot(int j) {
+    int n = 0;
+    for (int k = 0; k < j; ++k) n += Lat<Q>::ex(k) != 0;
+    return n;
+  }
+  __host__ __device__ static constexpr int scalar_slot(int i) {
+    int n = flow_slot(Q);
+    for (int k = 0; k < i; ++k) n += SLat<QS>::ex(k) != 0;
+    return n;
+  }
+  __host__ __device__ static constexpr int count() { return scalar_slot(QS); }
+};
+
+// Staging layout of the single-context hot kernels (blockDim.y rows of
+// blockDim.x threads): the calling thread's row segment and the run stride.
+__device__ __forceinline__ int lx_seg() { return threadIdx.y * blockDim.x; }
+__device__ __forceinline__ int lx_span() { return blockDim.x * blockDim.y; }
+
+// Row r(dy, dz) = Yr[1 + dy] + Zr[1 + dz]; address of slot jj's run in it.
+template <int QT>
+__device__ __forceinline__ int run_addr(const Nbr& b, int jj, int dy, int dz) {
+  return ((b.Yr[1 + dy] + b.Zr[1 + dz]) * QT + jj) * b.pitch;
+}
+
+// Loads of a pulled (ping-pong, odd in-place phase) state with the x-shifted
+// populations staged through LDS; the others as load_state.
+// NTS: streaming hint on the staged (now aligned) loads.  It pays for the
+// ping-pong pull (256x128x128 D3Q19 FP32: 0.732 -> 0.752 of HBM peak) but not
+// in place, where the last-level cache keeps part of the state between the
+// two phases (0.89 plain against 0.78 hinted), unless the state is far beyond
+// the cache (NTE, as for the even phase's loads, see load_state).
+template <int Q, int QS, typename Real, int ACC, bool NT, bool NTS>
+__device__ __forceinline__ void load_state_lx(const Real* a, const Nbr& b, Real (&f)[Q], Real (&g)[QS > 0 ? QS : 1],
+                                              Real* lds, int seg, int bt, bool act) {
+  static_assert(ACC != ACC_EVEN, "the even phase has no shifted access");
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  using H = Shifted<Q, QS>;
+  constexpr int QT = Q + QS;
+  constexpr bool odd = (ACC == ACC_ODD);
+#pragma unroll
+  for (int j = 0; j < Q; ++j)
+    if (L::ex(j) == 0)
+      f[j] = act ? get<NT>(a + pull_addr<QT>(b, odd ? L::opp(j) : j, L::ex(j), L::ey(j), L::ez(j))) : Real(0);
+#pragma unroll
+  for (int i = 0; i < QS; ++i)
+    if (S::ex(i) == 0)
+      g[i] = act ? get<NT>(a + pull_addr<QT>(b, Q + (odd ? S::opp(i) : i), S::ex(i), S::ey(i), S::ez(i))) : Real(0);
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) != 0)
+        lds[H::flow_slot(j) * bt + seg + b.X[1]] =
+            get<NTS>(a + run_addr<QT>(b, odd ? L::opp(j) : j, -L::ey(j), -L::ez(j)) + b.X[1]);
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (S::ex(i) != 0)
+        lds[H::scalar_slot(i) * bt + seg + b.X[1]] =
+            get<NTS>(a + run_addr<QT>(b, Q + (odd ? S::opp(i) : i), -S::ey(i), -S::ez(i)) + b.X[1]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < Q; ++j)
+    if (L::ex(j) != 0) f[j] = act ? lds[H::flow_slot(j) * bt + seg + b.X[1 - L::ex(j)]] : Real(0);
+#pragma unroll
+  for (int i = 0; i < QS; ++i)
+    if (S::ex(i) != 0) g[i] = act ? lds[H::scalar_slot(i) * bt + seg + b.X[1 - S::ex(i)]] : Real(0);
+}
+
+// Stores of the odd in-place phase (pushed to x + e_j) with the x-shifted
+// populations staged through LDS.  The first barrier keeps the staging of the
+// loads intact until every thread has read it.
+// NTS: streaming stores for the staged populations.
+template <int Q, int QS, typename Real, bool NT, bool NTS>
+__device__ __forceinline__ void store_state_lx(Real* a, const Nbr& b, const Real (&f)[Q],
+                                               const Real (&g)[QS > 0 ? QS : 1], Real* lds, int seg, int bt,
+    bool act) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  using H = Shifted<Q, QS>;
+  constexpr int QT = Q + QS;
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) != 0) lds[H::flow_slot(j) * bt + seg + b.X[1 + L::ex(j)]] = f[j];
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (S::ex(i) != 0) lds[H::scalar_slot(i) * bt + seg + b.X[1 + S::ex(i)]] = g[i];
+  }
+  __syncthreads();
+  if (!act) return;
+  Nbr bb = b;  // addresses recomputed (see store_state)
+#pragma unroll
+  for (int k = 0; k < 3; ++k) asm volatile("" : "+v"(bb.X[k]));
+#pragma unroll
+  for (int j = 0; j < Q; ++j)
+    if (L::ex(j) == 0) put<NT>(a + push_addr<QT>(bb, j, L::ex(j), L::ey(j), L::ez(j)), f[j]);
+#pragma unroll
+  for (int i = 0; i < QS; ++i)
+    if (S::ex(i) == 0) put<NT>(a + push_addr<QT>(bb, Q + i, S::ex(i), S::ey(i), S::ez(i)), g[i]);
+#pragma unroll
+  for (int j = 0; j < Q; ++j)
+    if (L::ex(j) != 0)
+      put<NTS>(a + run_addr<QT>(bb, j, L::ey(j), L::ez(j)) + bb.X[1], lds[H::flow_slot(j) * bt + seg + bb.X[1]]);
+#pragma unroll
+  for (int i = 0; i < QS; ++i)
+    if (S::ex(i) != 0)
+      put<NTS>(a + run_addr<QT>(bb, Q + i, S::ey(i), S::ez(i)) + bb.X[1], lds[H::scalar_slot(i) * bt + seg + bb.X[1]]);
+}
+
+// Cotangent loads (mu_j(x) = lambda_j(x + e_j): ping-pong, or the odd in-place
+// pattern) with the x-shifted populations staged through LDS; the others as
+// load_cot.  NTS as for load_state_lx.
+template <int Q, int QS, typename Real, int ACC, bool NT, bool NTS>
+__device__ __forceinline__ void load_cot_lx(const Real* a, const Nbr& b, Real (&mu)[Q], Real (&nu)[QS > 0 ? QS : 1],
+                                            Real* lds, int seg, int bt, bool act) {
+  static_assert(ACC != ACC_EVEN, "the even pattern has no shifted access");
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  using H = Shifted<Q, QS>;
+  constexpr int QT = Q + QS;
+  constexpr bool odd = (ACC == ACC_ODD);
+#pragma unroll
+  for (int j = 0; j < Q; ++j)
+    if (L::ex(j) == 0)
+      mu[j] = act ? get<NT>(a + push_addr<QT>(b, odd ? L::opp(j) : j, L::ex(j), L::ey(j), L::ez(j))) : Real(0);
+#pragma unroll
+  for (int i = 0; i < QS; ++i)
+    if (S::ex(i) == 0)
+      nu[i] = act ? get<NT>(a + push_addr<QT>(b, Q + (odd ? S::opp(i) : i), S::ex(i), S::ey(i), S::ez(i))) : Real(0);
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) != 0)
+        lds[H::flow_slot(j) * bt + seg + b.X[1]] =
+            get<NTS>(a + run_addr<QT>(b, odd ? L::opp(j) : j, L::ey(j), L::ez(j)) + b.X[1]);
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (S::ex(i) != 0)
+        lds[H::scalar_slot(i) * bt + seg + b.X[1]] =
+            get<NTS>(a + run_addr<QT>(b, Q + (odd ? S::opp(i) : i), S::ey(i), S::ez(i)) + b.X[1]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < Q; ++j)
+    if (L::ex(j) != 0) mu[j] = act ? lds[H::flow_slot(j) * bt + seg + b.X[1 + L::ex(j)]] : Real(0);
+#pragma unroll
+  for (int i = 0; i < QS; ++i)
+    if (S::ex(i) != 0) nu[i] = act ? lds[H::scalar_slot(i) * bt + seg + b.X[1 + S::ex(i)]] : Real(0);
+}
+
+// Cotangent stores of the odd in-place pattern (lambda_j(x) to slot j of
+// x - e_j) with the x-shifted populations staged through LDS.
+template <int Q, int QS, typename Real, bool NT, bool NTS>
+__device__ __forceinline__ void store_cot_lx(Real* a, const Nbr& b, const Real (&lf)[Q],
+                                             const Real (&lg)[QS > 0 ? QS : 1], Real* lds, int seg, int bt,
+    bool act) {
+  using L = Lat<Q>;
+  using S = SLat<QS>;
+  using H = Shifted<Q, QS>;
+  constexpr int QT = Q + QS;
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j)
+      if (L::ex(j) != 0) lds[H::flow_slot(j) * bt + seg + b.X[1 - L::ex(j)]] = lf[j];
+#pragma unroll
+    for (int i = 0; i < QS; ++i)
+      if (S::ex(i) != 0) lds[H::scalar_slot(i) * bt + seg + b.X[1 - S::ex(i)]] = lg[i];
+  }
+  __syncthreads();
+  if (!act) return;
+  Nbr bb = b;  // addresses recomputed (see store_state)
+#pragma unroll
+  for (int k = 0; k < 3; ++k) asm volatile("" : "+v"(bb.X[k]));
+#pragma unroll
+  for (int j = 0; j < Q; ++j)
+    if (L::ex(j) == 0) put<NT>(a + pull_addr<QT>(bb, j, L::ex(j), L::ey(j), L::ez(j)), lf[j]);
+#pragma unroll
+  for (int i = 0; i < QS; ++i)
+    if (S::ex(i) == 0) put<NT>(a + pull_addr<QT>(bb, Q + i, S::ex(i), S::ey(i), S::ez(i)), lg[i]);
+#pragma unroll
+  for (int j = 0; j < Q; ++j)
+    if (L::ex(j) != 0)
+      put<NTS>(a + run_addr<QT>(bb, j, -L::ey(j), -L::ez(j)) + bb.X[1], lds[H::flow_slot(j) * bt + seg + bb.X[1]]);
+#pragma unroll
+  for (int i = 0; i < QS; ++i)
+    if (S::ex(i) != 0)
+      put<NTS>(a + run_addr<QT>(bb, Q + i, -S::ey(i), -S::ez(i)) + bb.X[1],
+               lds[H::scalar_slot(i) * bt + seg + bb.X[1]]);
+}
+
 // Pre-collision state of a node for the inspection and objective kernels: the
 // access pattern of the buffer is a run-time argument there.
 template <int Q, int QS, typename Real>
@@ -780,23 +987,27 @@ __device__ __forceinline__ void node_moments(const Params<Real>& p, int cls, int
 // restrict qualifier here (the ping-pong kernels declare theirs).
 // NTE: streaming hint on the even phase's loads as well (states far beyond the
 // last-level cache; see load_state)
-template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC = ACC_PP, bool NTE = false>
+template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC = ACC_PP, bool NTE = false, bool LX = false>
 __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* src, Real* dst,
                                             const Real* __restrict__ w, Real* __restrict__ mom, int x, int y,
-                                            int z) {
+                                            int z, Real* lds = nullptr, int seg = 0, int bt = 0, bool act = true) {
   constexpr bool is3d = (Q == 19);
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_inode(b);  // workspace node arrays
   Real f[Q], g[QS > 0 ? QS : 1];
-  load_state<Q, QS, Real, ACC, NT && (ACC != ACC_EVEN || NTE)>(src, b, f, g);
-  const int cls = node_class(p, x, y, z, is3d);
+  if constexpr (LX)
+    load_state_lx<Q, QS, Real, ACC, NT, NT && (ACC == ACC_PP || NTE)>(src, b, f, g, lds, seg, bt, act);
+  else
+    load_state<Q, QS, Real, ACC, NT && (ACC != ACC_EVEN || NTE)>(src, b, f, g);
+  // padding lanes (LX only) take the wall operator: a permutation, no memory access
+  const int cls = act ? node_class(p, x, y, z, is3d) : WALL;
   if constexpr (MOM) {
     if (has_moments(p, cls)) {  // the only classes whose transposes read them
       Real m[Mom<Q, QS, V>::N];
       node_moments<Q, QS, Real, V>(p, cls, y, z, f, g, m);
-#pragma unroll
       // streaming stores whatever the state size: a moment set is read once, by the
       // adjoint, after the rest of the run has passed through the cache
+#pragma unroll
       for (int k = 0; k < Mom<Q, QS, V>::N; ++k) put<true>(mom + (size_t)k * p.Np + n, m[k]);
     }
   }
@@ -809,25 +1020,43 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* s
   } else {
     collide_outlet<Q, QS, Real>(p, f, g);
   }
-  store_state<Q, QS, Real, NT, ACC>(dst, b, f, g);
+  if constexpr (LX && ACC == ACC_ODD)
+    store_state_lx<Q, QS, Real, NT, NT && NTE>(dst, b, f, g, lds, seg, bt, act);
+  else if (act)
+    store_state<Q, QS, Real, NT, ACC>(dst, b, f, g);
 }
 
-template <int Q, int QS, typename Real, bool NT, bool MOM, int V>
+// LX: the block spans whole rows and the x-shifted populations go through LDS
+// (see load_state_lx); no thread leaves before the barriers.
+template <int Q, int QS, typename Real, bool NT, bool MOM, int V, bool LX = false>
 __global__ __launch_bounds__(256) void k_primal(Params<Real> p, const Real* __restrict__ src,
                                                 Real* __restrict__ dst, const Real* __restrict__ w,
                                                 Real* __restrict__ mom) {
   int x, y, z;
-  if (!hot_pos(p, x, y, z)) return;
-  primal_node<Q, QS, Real, NT, MOM, V>(p, src, dst, w, mom, x, y, z);
+  const bool act = hot_pos(p, x, y, z);
+  if constexpr (LX) {
+    __shared__ Real lds[Shifted<Q, QS>::count() * 256];
+    primal_node<Q, QS, Real, NT, MOM, V, ACC_PP, false, true>(p, src, dst, w, mom, x, y, z, lds, lx_seg(), lx_span(), act);
+  } else {
+    if (!act) return;
+    primal_node<Q, QS, Real, NT, MOM, V>(p, src, dst, w, mom, x, y, z);
+  }
 }
 
 // One in-place step (even or odd phase); with MOM it also records the moments.
-template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC, bool NTE = false>
+template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC, bool NTE = false, bool LX = false>
 __global__ __launch_bounds__(256) void k_primal_inplace(Params<Real> p, Real* a, const Real* __restrict__ w,
                                                         Real* __restrict__ mom) {
   int x, y, z;
-  if (!hot_pos(p, x, y, z)) return;
-  primal_node<Q, QS, Real, NT, MOM, V, ACC, NTE>(p, a, a, w, mom, x, y, z);
+  const bool act = hot_pos(p, x, y, z);
+  if constexpr (LX) {
+    static_assert(ACC == ACC_ODD, "only the odd phase has shifted access");
+    __shared__ Real lds[Shifted<Q, QS>::count() * 256];
+    primal_node<Q, QS, Real, NT, MOM, V, ACC, NTE, true>(p, a, a, w, mom, x, y, z, lds, lx_seg(), lx_span(), act);
+  } else {
+    if (!act) return;
+    primal_node<Q, QS, Real, NT, MOM, V, ACC, NTE>(p, a, a, w, mom, x, y, z);
+  }
 }
 
 // ------------------------------------------------------------ objective
@@ -1378,17 +1607,22 @@ __device__ __forceinline__ void adjoint_vjp(const Params<Real>& p, int cls, int 
 // recorded steps, in-place adjoint at 256x128x128: 0.829 with it, 0.847
 // without, the 2000-step evaluation unchanged; at 512x128x128: 0.813 with it,
 // 0.660 without).
-template <int Q, int QS, typename Real, bool NT, int V, int ACC = ACC_PP, bool NTE = false>
+template <int Q, int QS, typename Real, bool NT, int V, int ACC = ACC_PP, bool NTE = false, bool LX = false>
 __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* __restrict__ mom,
                                              const Real* lam_in, Real* lam_out, const Real* __restrict__ w,
-                                             Real* __restrict__ grad, int x, int y, int z) {
+                                             Real* __restrict__ grad, int x, int y, int z, Real* lds = nullptr,
+                                             int seg = 0, int bt = 0, bool act = true) {
   constexpr bool is3d = (Q == 19);
   constexpr int QSA = QS > 0 ? QS : 1;
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_inode(b);  // workspace node arrays
   Real mu[Q], nu[QSA];
-  load_cot<Q, QS, Real, ACC, NT && (ACC != ACC_EVEN || NTE)>(lam_in, b, mu, nu);
-  const int cls = node_class(p, x, y, z, is3d);
+  if constexpr (LX)
+    load_cot_lx<Q, QS, Real, ACC, NT, NT && (ACC == ACC_PP || NTE)>(lam_in, b, mu, nu, lds, seg, bt, act);
+  else
+    load_cot<Q, QS, Real, ACC, NT && (ACC != ACC_EVEN || NTE)>(lam_in, b, mu, nu);
+  // padding lanes (LX only) take the wall transpose: a permutation, no memory access
+  const int cls = act ? node_class(p, x, y, z, is3d) : WALL;
   Real m[Mom<Q, QS, V>::N], lf[Q], lg[QSA], gw;
 #pragma unroll
   for (int k = 0; k < Mom<Q, QS, V>::N; ++k) m[k] = Real(0);
@@ -1401,25 +1635,42 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
   adjoint_vjp<Q, QS, Real, V>(p, cls, x, y, m, wn, mu, nu, lf, lg, gw);
   if (cls == INTERIOR) grad[n] += gw;
-  store_cot<Q, QS, Real, NT, ACC>(lam_out, b, lf, lg);
+  if constexpr (LX && ACC == ACC_ODD)
+    store_cot_lx<Q, QS, Real, NT, NT && NTE>(lam_out, b, lf, lg, lds, seg, bt, act);
+  else if (act)
+    store_cot<Q, QS, Real, NT, ACC>(lam_out, b, lf, lg);
 }
 
-template <int Q, int QS, typename Real, bool NT, int V>
+// LX as for k_primal.
+template <int Q, int QS, typename Real, bool NT, int V, bool LX = false>
 __global__ __launch_bounds__(256) void k_adjoint(Params<Real> p, const Real* __restrict__ mom,
                                                  const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
                                                  const Real* __restrict__ w, Real* __restrict__ grad) {
   int x, y, z;
-  if (!hot_pos(p, x, y, z)) return;
-  adjoint_node<Q, QS, Real, NT, V>(p, mom, lam_in, lam_out, w, grad, x, y, z);
+  const bool act = hot_pos(p, x, y, z);
+  if constexpr (LX) {
+    __shared__ Real lds[Shifted<Q, QS>::count() * 256];
+    adjoint_node<Q, QS, Real, NT, V, ACC_PP, false, true>(p, mom, lam_in, lam_out, w, grad, x, y, z, lds, lx_seg(), lx_span(), act);
+  } else {
+    if (!act) return;
+    adjoint_node<Q, QS, Real, NT, V>(p, mom, lam_in, lam_out, w, grad, x, y, z);
+  }
 }
 
 // One in-place adjoint step (even or odd pattern of the cotangent buffer l).
-template <int Q, int QS, typename Real, bool NT, int V, int ACC, bool NTE = false>
+template <int Q, int QS, typename Real, bool NT, int V, int ACC, bool NTE = false, bool LX = false>
 __global__ __launch_bounds__(256) void k_adjoint_inplace(Params<Real> p, const Real* __restrict__ mom, Real* l,
                                                          const Real* __restrict__ w, Real* __restrict__ grad) {
   int x, y, z;
-  if (!hot_pos(p, x, y, z)) return;
-  adjoint_node<Q, QS, Real, NT, V, ACC, NTE>(p, mom, l, l, w, grad, x, y, z);
+  const bool act = hot_pos(p, x, y, z);
+  if constexpr (LX) {
+    static_assert(ACC == ACC_ODD, "only the odd pattern has shifted access");
+    __shared__ Real lds[Shifted<Q, QS>::count() * 256];
+    adjoint_node<Q, QS, Real, NT, V, ACC, NTE, true>(p, mom, l, l, w, grad, x, y, z, lds, lx_seg(), lx_span(), act);
+  } else {
+    if (!act) return;
+    adjoint_node<Q, QS, Real, NT, V, ACC, NTE>(p, mom, l, l, w, grad, x, y, z);
+  }
 }
 
 
@@ -1603,19 +1854,29 @@ __global__ __launch_bounds__(256) void k_get_adjoint(Params<Real> p, const Real*
 // update races with nothing.
 // prim_in/prim_out and lam_in/lam_out are the same buffers in place, hence no
 // restrict on them here (the ping-pong kernel declares it).
-template <int Q, int QS, typename Real, bool NT, int V, int ACC>
+// LX: x-shifted populations of both states through LDS (lds holds the
+// primal's staging runs, then the cotangent's).
+template <int Q, int QS, typename Real, bool NT, int V, int ACC, bool LX = false>
 __device__ __forceinline__ void oneshot_node(const Params<Real>& p, const Real* prim_in, Real* prim_out,
                                              const Real* lam_in, Real* lam_out, Real* __restrict__ w,
                                              Real* __restrict__ grad, const double* __restrict__ glob, Real zeta,
-                                             Real c_pen, int x, int y, int z) {
+                                             Real c_pen, int x, int y, int z, Real* lds = nullptr,
+                                             int seg = 0, int bt = 0, bool act = true) {
   constexpr bool is3d = (Q == 19);
   constexpr int QSA = QS > 0 ? QS : 1;
+  constexpr int kRuns = Shifted<Q, QS>::count() * 256;
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_inode(b);  // workspace node arrays
-  const int cls = node_class(p, x, y, z, is3d);
+  // padding lanes (LX only) take the wall operators: permutations, no memory access
+  const int cls = act ? node_class(p, x, y, z, is3d) : WALL;
   Real f[Q], g[QSA], mu[Q], nu[QSA];
-  load_state<Q, QS, Real, ACC, NT>(prim_in, b, f, g);
-  load_cot<Q, QS, Real, ACC, NT>(lam_in, b, mu, nu);
+  if constexpr (LX) {
+    load_state_lx<Q, QS, Real, ACC, NT, NT && ACC == ACC_PP>(prim_in, b, f, g, lds, seg, bt, act);
+    load_cot_lx<Q, QS, Real, ACC, NT, NT && ACC == ACC_PP>(lam_in, b, mu, nu, lds + kRuns, seg, bt, act);
+  } else {
+    load_state<Q, QS, Real, ACC, NT>(prim_in, b, f, g);
+    load_cot<Q, QS, Real, ACC, NT>(lam_in, b, mu, nu);
+  }
   const Real wn = (cls == INTERIOR) ? w[n] : Real(1);
   Real m[Mom<Q, QS, V>::N], lf[Q], lg[QSA], gw;
   node_moments<Q, QS, Real, V>(p, cls, y, z, f, g, m);
@@ -1637,8 +1898,14 @@ __device__ __forceinline__ void oneshot_node(const Params<Real>& p, const Real* 
   } else {
     collide_outlet<Q, QS, Real>(p, f, g);
   }
-  store_state<Q, QS, Real, NT, ACC>(prim_out, b, f, g);
-  store_cot<Q, QS, Real, NT, ACC>(lam_out, b, lf, lg);
+  if constexpr (LX && ACC == ACC_ODD) {
+    store_state_lx<Q, QS, Real, NT, false>(prim_out, b, f, g, lds, seg, bt, act);
+    store_cot_lx<Q, QS, Real, NT, false>(lam_out, b, lf, lg, lds + kRuns, seg, bt, act);
+  } else if (act) {
+    store_state<Q, QS, Real, NT, ACC>(prim_out, b, f, g);
+    store_cot<Q, QS, Real, NT, ACC>(lam_out, b, lf, lg);
+  }
+  if (!act) return;
   grad[n] = gw;
   if (cls == INTERIOR) {
     const Real v = wn + zeta * (gw + c_pen * (Real(1) - Real(2) * wn));
@@ -1646,27 +1913,41 @@ __device__ __forceinline__ void oneshot_node(const Params<Real>& p, const Real* 
   }
 }
 
-template <int Q, int QS, typename Real, bool NT, int V>
+template <int Q, int QS, typename Real, bool NT, int V, bool LX = false>
 __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __restrict__ prim_in,
                                                  Real* __restrict__ prim_out, const Real* __restrict__ lam_in,
                                                  Real* __restrict__ lam_out, Real* __restrict__ w,
                                                  Real* __restrict__ grad, const double* __restrict__ glob, Real zeta,
                                                  Real c_pen) {
   int x, y, z;
-  if (!hot_pos(p, x, y, z)) return;
-  oneshot_node<Q, QS, Real, NT, V, ACC_PP>(p, prim_in, prim_out, lam_in, lam_out, w, grad, glob, zeta, c_pen, x, y,
-                                           z);
+  const bool act = hot_pos(p, x, y, z);
+  if constexpr (LX) {
+    __shared__ Real lds[2 * Shifted<Q, QS>::count() * 256];
+    oneshot_node<Q, QS, Real, NT, V, ACC_PP, true>(p, prim_in, prim_out, lam_in, lam_out, w, grad, glob, zeta, c_pen,
+                                                   x, y, z, lds, lx_seg(), lx_span(), act);
+  } else {
+    if (!act) return;
+    oneshot_node<Q, QS, Real, NT, V, ACC_PP>(p, prim_in, prim_out, lam_in, lam_out, w, grad, glob, zeta, c_pen, x,
+                                             y, z);
+  }
 }
 
 // One in-place one-shot iteration (even or odd phase): a is the primal buffer,
 // l the adjoint buffer, each read and rewritten in place.
-template <int Q, int QS, typename Real, bool NT, int V, int ACC>
+template <int Q, int QS, typename Real, bool NT, int V, int ACC, bool LX = false>
 __global__ __launch_bounds__(256) void k_oneshot_inplace(Params<Real> p, Real* a, Real* l, Real* __restrict__ w,
                                                          Real* __restrict__ grad, const double* __restrict__ glob,
                                                          Real zeta, Real c_pen) {
   int x, y, z;
-  if (!hot_pos(p, x, y, z)) return;
-  oneshot_node<Q, QS, Real, NT, V, ACC>(p, a, a, l, l, w, grad, glob, zeta, c_pen, x, y, z);
+  const bool act = hot_pos(p, x, y, z);
+  if constexpr (LX) {
+    static_assert(ACC == ACC_ODD, "only the odd phase has shifted access");
+    __shared__ Real lds[2 * Shifted<Q, QS>::count() * 256];
+    oneshot_node<Q, QS, Real, NT, V, ACC, true>(p, a, a, l, l, w, grad, glob, zeta, c_pen, x, y, z, lds, lx_seg(), lx_span(), act);
+  } else {
+    if (!act) return;
+    oneshot_node<Q, QS, Real, NT, V, ACC>(p, a, a, l, l, w, grad, glob, zeta, c_pen, x, y, z);
+  }
 }
 
 // --------------------------------------------------------- batched launches
@@ -1696,6 +1977,7 @@ struct BatchArgs {
   int rpb;  // row parts per block (blockDim.x = 64 kw rpb); > 1 only when every row is one part
   int nt;   // streaming stores and hints: the states the launch touches exceed the last-level cache
   int nte;  // in place: the even phase's loads take the hint too (states far beyond the cache)
+  int lx;   // every member's row is one row part: x-shifted populations through LDS
   int start[kBatchMax + 1];
   const BatchStatic<Real>* st[kBatchMax];
   const Real* a[kBatchMax];  // primal: source state; adjoint: moments of f^n
@@ -1752,7 +2034,9 @@ __device__ __forceinline__ int batch_find(const BatchArgs<Real>& A, int blk) {
 // register count of the single-context kernels.
 // ACC: ping-pong (a = source, c = destination) or one in-place phase (a = c =
 // the member's working buffer; members of other phases go in another launch).
-template <int Q, int QS, typename Real, int V, bool NT, bool MOM, int ACC, bool NTE = false>
+// LX: every member's row is one block part; x-shifted populations through LDS
+// (one run per row part of kw waves), no thread leaves before the barriers.
+template <int Q, int QS, typename Real, int V, bool NT, bool MOM, int ACC, bool NTE = false, bool LX = false>
 __global__ __launch_bounds__(256) void k_primal_batch(BatchArgs<Real> A) {
   const int blk = blockIdx.x;
   const int k = batch_find(A, blk);
@@ -1761,12 +2045,20 @@ __global__ __launch_bounds__(256) void k_primal_batch(BatchArgs<Real> A) {
   const Params<Real> p = A.st[k]->p;
   const int waves = A.st[k]->waves;
   int x, y, z;
-  if (!batch_pos(A, p, waves, blk - A.start[k], x, y, z)) return;
-  primal_node<Q, QS, Real, NT, MOM, V, ACC, NTE>(p, A.a[k], A.c[k], A.w[k], MOM ? A.m[k] : nullptr, x, y, z);
+  const bool act = batch_pos(A, p, waves, blk - A.start[k], x, y, z);
+  if constexpr (LX) {
+    __shared__ Real lds[Shifted<Q, QS>::count() * 256];
+    const int tw = kWave * A.kw;
+    primal_node<Q, QS, Real, NT, MOM, V, ACC, NTE, true>(p, A.a[k], A.c[k], A.w[k], MOM ? A.m[k] : nullptr, x, y, z,
+                                                         lds, (int)(threadIdx.x / tw) * tw, (int)blockDim.x, act);
+  } else {
+    if (!act) return;
+    primal_node<Q, QS, Real, NT, MOM, V, ACC, NTE>(p, A.a[k], A.c[k], A.w[k], MOM ? A.m[k] : nullptr, x, y, z);
+  }
 }
 
 // ACC: ping-pong (b = lambda^{n+1}, c = lambda^n) or one in-place pattern (b = c).
-template <int Q, int QS, typename Real, int V, bool NT, int ACC, bool NTE = false>
+template <int Q, int QS, typename Real, int V, bool NT, int ACC, bool NTE = false, bool LX = false>
 __global__ __launch_bounds__(256) void k_adjoint_batch(BatchArgs<Real> A) {
   const int blk = blockIdx.x;
   const int k = batch_find(A, blk);
@@ -1775,8 +2067,16 @@ __global__ __launch_bounds__(256) void k_adjoint_batch(BatchArgs<Real> A) {
   const Params<Real> p = A.st[k]->p;
   const int waves = A.st[k]->waves;
   int x, y, z;
-  if (!batch_pos(A, p, waves, blk - A.start[k], x, y, z)) return;
-  adjoint_node<Q, QS, Real, NT, V, ACC, NTE>(p, A.a[k], A.b[k], A.c[k], A.w[k], A.g[k], x, y, z);
+  const bool act = batch_pos(A, p, waves, blk - A.start[k], x, y, z);
+  if constexpr (LX) {
+    __shared__ Real lds[Shifted<Q, QS>::count() * 256];
+    const int tw = kWave * A.kw;
+    adjoint_node<Q, QS, Real, NT, V, ACC, NTE, true>(p, A.a[k], A.b[k], A.c[k], A.w[k], A.g[k], x, y, z, lds,
+                                                     (int)(threadIdx.x / tw) * tw, (int)blockDim.x, act);
+  } else {
+    if (!act) return;
+    adjoint_node<Q, QS, Real, NT, V, ACC, NTE>(p, A.a[k], A.b[k], A.c[k], A.w[k], A.g[k], x, y, z);
+  }
 }
 
 // ------------------------------------------------------- small helpers

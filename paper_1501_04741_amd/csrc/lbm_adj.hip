@@ -356,6 +356,16 @@ Geo node_geometry(const lbm_config& c) {
 // at 128x192x192, 192x96x96 or 256x128x128.
 constexpr int kHotWaves = 4;
 
+// x-shifted populations through LDS (kernels' LX variants): when one block
+// part spans a whole row, i.e. nx <= 256.  Measured on the 256x128x128 D3Q19
+// FP32 channel (fraction of HBM peak): recorded in-place primal 0.839 -> 0.892,
+// in-place adjoint 0.846 -> 0.903, ping-pong primal 0.732 -> 0.752, ping-pong
+// adjoint 0.798 -> 0.807; FP64 and the one-shot unchanged.  The MRT adjoint
+// (90 registers, five waves per SIMD) loses at its barriers (0.80 -> 0.75) and
+// keeps the plain access.
+bool lx_rows(const lbm_config& c) { return c.nx <= 256; }
+bool lx_adjoint(const lbm_config& c) { return lx_rows(c) && c.collision != LBM_COLL_MRT; }
+
 // Launch geometry of the hot kernels: as node_geometry, and when a row is a
 // single block part (nx <= 256), R consecutive rows share a block (blockDim.y =
 // R) so that it holds about the target number of waves.
@@ -405,6 +415,14 @@ int batch_rows_per_block(lbm_ctx* const* cs, int n, int kw) {
   return std::max(1, kHotWaves / kw);
 }
 
+// x-shifted populations through LDS in a batched launch: when every member's
+// row is a single row part (as lx_rows for one context).
+int batch_lx(lbm_ctx* const* cs, int n, int kw) {
+  for (int k = 0; k < n; ++k)
+    if (batch_waves(cs[k]) != kw) return 0;
+  return 1;
+}
+
 // Streaming stores and hints in a batched ping-pong launch: decided on the
 // states the launch touches together (a source and a destination per member),
 // not per member: eight 90 MB states are far beyond the cache although each
@@ -451,7 +469,12 @@ struct Ops {
     if (acc == ACC_EVEN && NTV && A.nte)
       hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_EVEN, true>), g, b, 0, st, A);
     else if (acc == ACC_EVEN) hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_EVEN>), g, b, 0, st, A);
+    else if (acc == ACC_ODD && A.lx && A.nte)
+      hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_ODD, true, true>), g, b, 0, st, A);
+    else if (acc == ACC_ODD && A.lx)
+      hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_ODD, false, true>), g, b, 0, st, A);
     else if (acc == ACC_ODD) hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_ODD>), g, b, 0, st, A);
+    else if (A.lx) hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_PP, false, true>), g, b, 0, st, A);
     else hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_PP>), g, b, 0, st, A);
   }
   static void primal_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks, int acc = ACC_PP) {
@@ -467,10 +490,16 @@ struct Ops {
   }
   template <bool NTV>
   static void adjoint_batch_acc(hipStream_t st, const BatchArgs<Real>& A, dim3 g, dim3 b, int acc) {
+    constexpr bool kLx = !(V & kVarMRT);  // the MRT adjoint keeps the plain access (see lx_adjoint)
     if (acc == ACC_EVEN && NTV && A.nte)
       hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V, NTV, ACC_EVEN, true>), g, b, 0, st, A);
     else if (acc == ACC_EVEN) hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V, NTV, ACC_EVEN>), g, b, 0, st, A);
+    else if (acc == ACC_ODD && A.lx && A.nte)
+      hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V, NTV, ACC_ODD, true, kLx>), g, b, 0, st, A);
+    else if (acc == ACC_ODD && A.lx)
+      hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V, NTV, ACC_ODD, false, kLx>), g, b, 0, st, A);
     else if (acc == ACC_ODD) hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V, NTV, ACC_ODD>), g, b, 0, st, A);
+    else if (A.lx) hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V, NTV, ACC_PP, false, kLx>), g, b, 0, st, A);
     else hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V, NTV, ACC_PP>), g, b, 0, st, A);
   }
   static void adjoint_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks, int acc = ACC_PP) {
@@ -498,8 +527,20 @@ struct Ops {
     const Real* w = (const Real*)c->w;
     Real* m = (Real*)mom;
     const bool even = (t % 2 == 0);
-#define LBM_PI(NTV, MOMV, ACCV) \
-  hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), a, w, m)
+    const bool lx = lx_rows(c->cfg);
+    const bool far = c->plan.state_bytes > 2 * kLastLevelCacheBytes;  // streaming hints on the staged accesses
+#define LBM_PI(NTV, MOMV, ACCV)                                                                                    \
+  do {                                                                                                             \
+    if (ACCV == ACC_ODD && lx && far)                                                                              \
+      hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACC_ODD, true, true>), g.grid, g.block, 0,   \
+                         c->stream, P(c), a, w, m);                                                                \
+    else if (ACCV == ACC_ODD && lx)                                                                                \
+      hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACC_ODD, false, true>), g.grid, g.block, 0,  \
+                         c->stream, P(c), a, w, m);                                                                \
+    else                                                                                                           \
+      hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), \
+                         a, w, m);                                                                                 \
+  } while (0)
     if (m && nt(c, 1)) {
       // the even phase's loads take the streaming hint too once the state is far beyond the cache
       if (even && c->plan.state_bytes > 2 * kLastLevelCacheBytes)
@@ -530,9 +571,16 @@ struct Ops {
     Real* gr = (Real*)c->grad;
     const double* gl = (const double*)c->glob;
     const bool even = (c->t % 2 == 0);
-#define LBM_OS_INPLACE(NTV, ACCV)                                                                         \
-  hipLaunchKernelGGL((k_oneshot_inplace<Q, QS, Real, NTV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), a, l, w, gr, \
-                     gl, (Real)zeta, (Real)pen)
+    const bool lx = lx_rows(c->cfg);
+#define LBM_OS_INPLACE(NTV, ACCV)                                                                                 \
+  do {                                                                                                            \
+    if (ACCV == ACC_ODD && lx)                                                                                    \
+      hipLaunchKernelGGL((k_oneshot_inplace<Q, QS, Real, NTV, V, ACC_ODD, true>), g.grid, g.block, 0, c->stream,   \
+                         P(c), a, l, w, gr, gl, (Real)zeta, (Real)pen);                                           \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_oneshot_inplace<Q, QS, Real, NTV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), a, l, \
+                         w, gr, gl, (Real)zeta, (Real)pen);                                                       \
+  } while (0)
     if (nt(c, 2)) {
       if (even) LBM_OS_INPLACE(true, ACC_EVEN);
       else LBM_OS_INPLACE(true, ACC_ODD);
@@ -559,17 +607,22 @@ struct Ops {
     Real* d = (Real*)dst;
     const Real* w = (const Real*)c->w;
     Real* m = (Real*)mom;
+#define LBM_PP(NTV, MOMV)                                                                                     \
+  do {                                                                                                        \
+    if (lx_rows(c->cfg))                                                                                      \
+      hipLaunchKernelGGL((k_primal<Q, QS, Real, NTV, MOMV, V, true>), g.grid, g.block, 0, c->stream, P(c), s, d, w, \
+                         m);                                                                                  \
+    else                                                                                                      \
+      hipLaunchKernelGGL((k_primal<Q, QS, Real, NTV, MOMV, V>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m); \
+  } while (0)
     if (nt(c, 2)) {
-      if (m)
-        hipLaunchKernelGGL((k_primal<Q, QS, Real, true, true, V>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
-      else
-        hipLaunchKernelGGL((k_primal<Q, QS, Real, true, false, V>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+      if (m) LBM_PP(true, true);
+      else LBM_PP(true, false);
     } else {
-      if (m)
-        hipLaunchKernelGGL((k_primal<Q, QS, Real, false, true, V>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
-      else
-        hipLaunchKernelGGL((k_primal<Q, QS, Real, false, false, V>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m);
+      if (m) LBM_PP(false, true);
+      else LBM_PP(false, false);
     }
+#undef LBM_PP
   }
   static void objective(lbm_ctx* c, const void* src, double* out) {
     double* part = c->glob + kGlobSlots;
@@ -607,8 +660,20 @@ struct Ops {
     const Real* w = (const Real*)c->w;
     Real* gr = (Real*)c->grad;
     const bool odd = (steps_done % 2 == 0);
-#define LBM_AI(NTV, ACCV) \
-  hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, NTV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), m, l, w, gr)
+    const bool lx = lx_adjoint(c->cfg);
+    const bool far = c->plan.state_bytes > 2 * kLastLevelCacheBytes;  // streaming hints on the staged accesses
+#define LBM_AI(NTV, ACCV)                                                                                         \
+  do {                                                                                                            \
+    if (ACCV == ACC_ODD && lx && far)                                                                             \
+      hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, NTV, V, ACC_ODD, true, true>), g.grid, g.block, 0,       \
+                         c->stream, P(c), m, l, w, gr);                                                           \
+    else if (ACCV == ACC_ODD && lx)                                                                               \
+      hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, NTV, V, ACC_ODD, false, true>), g.grid, g.block, 0,      \
+                         c->stream, P(c), m, l, w, gr);                                                           \
+    else                                                                                                          \
+      hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, NTV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), m, l, \
+                         w, gr);                                                                                  \
+  } while (0)
     if (nt(c, 1)) {
       if (odd) LBM_AI(true, ACC_ODD);
       else if (c->plan.state_bytes > 2 * kLastLevelCacheBytes)  // even-phase hint far beyond the cache
@@ -623,24 +688,37 @@ struct Ops {
   }
   static void adjoint(lbm_ctx* c, const void* mom, const void* lin, void* lout) {
     Geo g = hot_geometry(c->cfg);
-    if (nt(c, 2))
-      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true, V>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
-                         (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
+    const Real *m = (const Real*)mom, *li = (const Real*)lin, *w = (const Real*)c->w;
+    Real *lo = (Real*)lout, *gr = (Real*)c->grad;
+    const bool lx = lx_adjoint(c->cfg);
+    if (nt(c, 2) && lx)
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true, V, true>), g.grid, g.block, 0, c->stream, P(c), m, li, lo, w, gr);
+    else if (nt(c, 2))
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true, V>), g.grid, g.block, 0, c->stream, P(c), m, li, lo, w, gr);
+    else if (lx)
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false, V, true>), g.grid, g.block, 0, c->stream, P(c), m, li, lo, w,
+                         gr);
     else
-      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false, V>), g.grid, g.block, 0, c->stream, P(c), (const Real*)mom,
-                         (const Real*)lin, (Real*)lout, (const Real*)c->w, (Real*)c->grad);
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false, V>), g.grid, g.block, 0, c->stream, P(c), m, li, lo, w, gr);
   }
   static void oneshot(lbm_ctx* c, const void* src, void* dst, const void* lin, void* lout, double zeta,
                       double pen) {
     Geo g = hot_geometry(c->cfg);
-    if (nt(c, 4))
-      hipLaunchKernelGGL((k_oneshot<Q, QS, Real, true, V>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
-                         (Real*)dst, (const Real*)lin, (Real*)lout, (Real*)c->w, (Real*)c->grad,
-                         (const double*)c->glob, (Real)zeta, (Real)pen);
-    else
-      hipLaunchKernelGGL((k_oneshot<Q, QS, Real, false, V>), g.grid, g.block, 0, c->stream, P(c), (const Real*)src,
-                         (Real*)dst, (const Real*)lin, (Real*)lout, (Real*)c->w, (Real*)c->grad,
-                         (const double*)c->glob, (Real)zeta, (Real)pen);
+    const Real *s = (const Real*)src, *li = (const Real*)lin;
+    Real *d = (Real*)dst, *lo = (Real*)lout, *w = (Real*)c->w, *gr = (Real*)c->grad;
+    const double* gl = (const double*)c->glob;
+    const bool lx = lx_rows(c->cfg);
+#define LBM_OS(NTV, LXV)                                                                                   \
+  hipLaunchKernelGGL((k_oneshot<Q, QS, Real, NTV, V, LXV>), g.grid, g.block, 0, c->stream, P(c), s, d, li, lo, w, gr, \
+                     gl, (Real)zeta, (Real)pen)
+    if (nt(c, 4)) {
+      if (lx) LBM_OS(true, true);
+      else LBM_OS(true, false);
+    } else {
+      if (lx) LBM_OS(false, true);
+      else LBM_OS(false, false);
+    }
+#undef LBM_OS
   }
   static void get_adjoint(lbm_ctx* c, const void* lam, double* lf, double* lg, int pattern) {
     Geo g = node_geometry(c->cfg);
@@ -1008,6 +1086,7 @@ struct RunPrimalBatch {
         A.n = nm;
         A.kw = batch_block_waves(mem, nm);
         A.rpb = batch_rows_per_block(mem, nm, A.kw);
+        A.lx = batch_lx(mem, nm, A.kw);
         batch_nt_inplace(mem, nm, !record, &A.nt, &A.nte);
         int total = 0;
         for (int k = 0; k < nm; ++k) {
@@ -1038,6 +1117,7 @@ struct RunPrimalBatch {
     A.n = n;
     A.kw = batch_block_waves(cs, n);
     A.rpb = batch_rows_per_block(cs, n, A.kw);
+    A.lx = batch_lx(cs, n, A.kw);
     A.nt = batch_nt(cs, n);
     for (int64_t i = 0; i < nsteps; ++i) {
       int total = 0;
@@ -1090,6 +1170,7 @@ struct RunAdjointBatch {
         A.n = nm;
         A.kw = batch_block_waves(mem, nm);
         A.rpb = batch_rows_per_block(mem, nm, A.kw);
+        A.lx = batch_lx(mem, nm, A.kw);
         batch_nt_inplace(mem, nm, false, &A.nt, &A.nte);
         int total = 0;
         for (int k = 0; k < nm; ++k) {
@@ -1146,6 +1227,7 @@ struct RunAdjointBatch {
           if (first[q] + r <= last[q]) mem[nm++] = need[q];
         A.kw = batch_block_waves(mem, nm);
         A.rpb = batch_rows_per_block(mem, nm, A.kw);
+        A.lx = batch_lx(mem, nm, A.kw);
         A.nt = batch_nt(mem, nm);
         int m = 0, total = 0;
         for (int q = 0; q < nn; ++q) {
@@ -1175,6 +1257,7 @@ struct RunAdjointBatch {
       A.n = n;
       A.kw = batch_block_waves(cs, n);
       A.rpb = batch_rows_per_block(cs, n, A.kw);
+      A.lx = batch_lx(cs, n, A.kw);
       A.nt = batch_nt(cs, n);
       for (int k = 0; k < n; ++k) {
         lbm_ctx* c = cs[k];
