@@ -452,8 +452,9 @@ __device__ __forceinline__ int run_addr(const Nbr& b, int jj, int dy, int dz) {
 // NTS: streaming hint on the staged (now aligned) loads.  It pays for the
 // ping-pong pull (256x128x128 D3Q19 FP32: 0.732 -> 0.752 of HBM peak) but not
 // in place, where the last-level cache keeps part of the state between the
-// two phases (0.89 plain against 0.78 hinted), unless the state is far beyond
-// the cache (NTE, as for the even phase's loads, see load_state).
+// two phases (0.89 plain against 0.78 hinted); for states far beyond the cache
+// the in-place adjoint takes it (8 x 128x96x96 batched: 0.79 -> 0.81) and the
+// in-place primal does not (FP64 256x128x128: 0.768 -> 0.738 with it).
 template <int Q, int QS, typename Real, int ACC, bool NT, bool NTS>
 __device__ __forceinline__ void load_state_lx(const Real* a, const Nbr& b, Real (&f)[Q], Real (&g)[QS > 0 ? QS : 1],
                                               Real* lds, int seg, int bt, bool act) {
@@ -996,7 +997,7 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* s
   const int n = own_inode(b);  // workspace node arrays
   Real f[Q], g[QS > 0 ? QS : 1];
   if constexpr (LX)
-    load_state_lx<Q, QS, Real, ACC, NT, NT && (ACC == ACC_PP || NTE)>(src, b, f, g, lds, seg, bt, act);
+    load_state_lx<Q, QS, Real, ACC, NT, NT && ACC == ACC_PP>(src, b, f, g, lds, seg, bt, act);
   else
     load_state<Q, QS, Real, ACC, NT && (ACC != ACC_EVEN || NTE)>(src, b, f, g);
   // padding lanes (LX only) take the wall operator: a permutation, no memory access
@@ -1021,7 +1022,7 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* s
     collide_outlet<Q, QS, Real>(p, f, g);
   }
   if constexpr (LX && ACC == ACC_ODD)
-    store_state_lx<Q, QS, Real, NT, NT && NTE>(dst, b, f, g, lds, seg, bt, act);
+    store_state_lx<Q, QS, Real, NT, false>(dst, b, f, g, lds, seg, bt, act);
   else if (act)
     store_state<Q, QS, Real, NT, ACC>(dst, b, f, g);
 }

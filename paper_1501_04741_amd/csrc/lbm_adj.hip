@@ -360,11 +360,10 @@ constexpr int kHotWaves = 4;
 // part spans a whole row, i.e. nx <= 256.  Measured on the 256x128x128 D3Q19
 // FP32 channel (fraction of HBM peak): recorded in-place primal 0.839 -> 0.892,
 // in-place adjoint 0.846 -> 0.903, ping-pong primal 0.732 -> 0.752, ping-pong
-// adjoint 0.798 -> 0.807; FP64 and the one-shot unchanged.  The MRT adjoint
-// (90 registers, five waves per SIMD) loses at its barriers (0.80 -> 0.75) and
-// keeps the plain access.
-bool lx_rows(const lbm_config& c) { return c.nx <= 256; }
-bool lx_adjoint(const lbm_config& c) { return lx_rows(c) && c.collision != LBM_COLL_MRT; }
+// adjoint 0.798 -> 0.807; FP64 and the one-shot unchanged.  The MRT kernels
+// (87-90 registers, five waves per SIMD) lose at the barriers (adjoint 0.80 ->
+// 0.75, primal 0.79 -> 0.77) and keep the plain access.
+bool lx_rows(const lbm_config& c) { return c.nx <= 256 && c.collision != LBM_COLL_MRT; }
 
 // Launch geometry of the hot kernels: as node_geometry, and when a row is a
 // single block part (nx <= 256), R consecutive rows share a block (blockDim.y =
@@ -466,15 +465,14 @@ struct Ops {
   // batched steps in access pattern acc (ping-pong, or one in-place phase)
   template <bool NTV, bool MOMV>
   static void primal_batch_acc(hipStream_t st, const BatchArgs<Real>& A, dim3 g, dim3 b, int acc) {
+    constexpr bool kLx = !(V & kVarMRT);  // the MRT kernels keep the plain access (see lx_rows)
     if (acc == ACC_EVEN && NTV && A.nte)
       hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_EVEN, true>), g, b, 0, st, A);
     else if (acc == ACC_EVEN) hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_EVEN>), g, b, 0, st, A);
-    else if (acc == ACC_ODD && A.lx && A.nte)
-      hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_ODD, true, true>), g, b, 0, st, A);
     else if (acc == ACC_ODD && A.lx)
-      hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_ODD, false, true>), g, b, 0, st, A);
+      hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_ODD, false, kLx>), g, b, 0, st, A);
     else if (acc == ACC_ODD) hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_ODD>), g, b, 0, st, A);
-    else if (A.lx) hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_PP, false, true>), g, b, 0, st, A);
+    else if (A.lx) hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_PP, false, kLx>), g, b, 0, st, A);
     else hipLaunchKernelGGL((k_primal_batch<Q, QS, Real, V, NTV, MOMV, ACC_PP>), g, b, 0, st, A);
   }
   static void primal_batch(hipStream_t st, const BatchArgs<Real>& A, int blocks, int acc = ACC_PP) {
@@ -490,7 +488,7 @@ struct Ops {
   }
   template <bool NTV>
   static void adjoint_batch_acc(hipStream_t st, const BatchArgs<Real>& A, dim3 g, dim3 b, int acc) {
-    constexpr bool kLx = !(V & kVarMRT);  // the MRT adjoint keeps the plain access (see lx_adjoint)
+    constexpr bool kLx = !(V & kVarMRT);  // the MRT kernels keep the plain access (see lx_rows)
     if (acc == ACC_EVEN && NTV && A.nte)
       hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V, NTV, ACC_EVEN, true>), g, b, 0, st, A);
     else if (acc == ACC_EVEN) hipLaunchKernelGGL((k_adjoint_batch<Q, QS, Real, V, NTV, ACC_EVEN>), g, b, 0, st, A);
@@ -528,13 +526,9 @@ struct Ops {
     Real* m = (Real*)mom;
     const bool even = (t % 2 == 0);
     const bool lx = lx_rows(c->cfg);
-    const bool far = c->plan.state_bytes > 2 * kLastLevelCacheBytes;  // streaming hints on the staged accesses
 #define LBM_PI(NTV, MOMV, ACCV)                                                                                    \
   do {                                                                                                             \
-    if (ACCV == ACC_ODD && lx && far)                                                                              \
-      hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACC_ODD, true, true>), g.grid, g.block, 0,   \
-                         c->stream, P(c), a, w, m);                                                                \
-    else if (ACCV == ACC_ODD && lx)                                                                                \
+    if (ACCV == ACC_ODD && lx)                                                                                     \
       hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACC_ODD, false, true>), g.grid, g.block, 0,  \
                          c->stream, P(c), a, w, m);                                                                \
     else                                                                                                           \
@@ -660,7 +654,7 @@ struct Ops {
     const Real* w = (const Real*)c->w;
     Real* gr = (Real*)c->grad;
     const bool odd = (steps_done % 2 == 0);
-    const bool lx = lx_adjoint(c->cfg);
+    const bool lx = lx_rows(c->cfg);
     const bool far = c->plan.state_bytes > 2 * kLastLevelCacheBytes;  // streaming hints on the staged accesses
 #define LBM_AI(NTV, ACCV)                                                                                         \
   do {                                                                                                            \
@@ -690,7 +684,7 @@ struct Ops {
     Geo g = hot_geometry(c->cfg);
     const Real *m = (const Real*)mom, *li = (const Real*)lin, *w = (const Real*)c->w;
     Real *lo = (Real*)lout, *gr = (Real*)c->grad;
-    const bool lx = lx_adjoint(c->cfg);
+    const bool lx = lx_rows(c->cfg);
     if (nt(c, 2) && lx)
       hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true, V, true>), g.grid, g.block, 0, c->stream, P(c), m, li, lo, w, gr);
     else if (nt(c, 2))
