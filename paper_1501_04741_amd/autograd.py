@@ -7,6 +7,8 @@ forward(w)   -> J: records N primal steps of the library (full states every C
 backward(gJ) -> gJ * dJ/dw: the hand-written adjoint kernel, run N reverse
                 steps with segment recomputes from the checkpoints
                 (theorem of Section 2.2, unsteady form), then the gradient.
+                By default both stream in place and segments are recomputed
+                inside their checkpoints.
 
 The context (``Lbm``) holds one recorded trajectory at a time.  Each forward
 overwrites it, so the backward of an earlier forward whose trajectory has been
@@ -16,7 +18,7 @@ from __future__ import annotations
 
 import torch
 
-from .lbm import Lbm, lbm_objective_async
+from .lbm import Lbm, lbm_objective_async, lbm_required_bytes, make_config
 
 
 class LbmObjective(torch.autograd.Function):
@@ -52,18 +54,36 @@ class LbmObjective(torch.autograd.Function):
         return grad_w, None, None
 
 
+def smallest_inplace_interval(params: dict, nsteps: int, precision: str) -> int:
+    """Checkpoint interval C whose in-place workspace (ceil(N/C) checkpoint states
+    and C moment sets besides the two working states) is smallest."""
+    best = None
+    for c in range(1, nsteps + 1):
+        b = lbm_required_bytes(make_config(params, nsteps, precision, checkpoint_interval=c, inplace=True))
+        if best is None or b < best[0]:
+            best = (b, c)
+    return best[1]
+
+
 class LbmSolver:
     """Owns one GPU context sized for ``nsteps`` and exposes J(w) as a
     differentiable function: ``J = solver(w); J.backward()``."""
 
     def __init__(self, params: dict, nsteps: int, precision: str = "fp32", checkpoint_interval: int = 0,
-                 hbm_budget_bytes: int = 0, device=None, differentiable: bool = True):
+                 hbm_budget_bytes: int = 0, device=None, differentiable: bool = True, inplace: bool = True):
         """differentiable=False sizes the workspace for unrecorded forwards only
-        (five states instead of the checkpoint plan); such a solver offers value()."""
+        (five states instead of the checkpoint plan); such a solver offers value().
+        inplace (default): one primal and one adjoint buffer streamed in place, the
+        faster kernels; with neither checkpoint_interval nor hbm_budget_bytes given
+        the checkpoint interval is the one with the smallest workspace (about
+        sqrt(N Qt / moments per node) steps), as the ping-pong default is."""
         self.nsteps = int(nsteps)
         self.differentiable = differentiable
-        self.lbm = Lbm(params, nsteps=self.nsteps if differentiable else 0, precision=precision,
-                       checkpoint_interval=checkpoint_interval, hbm_budget_bytes=hbm_budget_bytes, device=device)
+        n = self.nsteps if differentiable else 0
+        if inplace and n > 0 and not checkpoint_interval and not hbm_budget_bytes:
+            checkpoint_interval = smallest_inplace_interval(params, n, precision)
+        self.lbm = Lbm(params, nsteps=n, precision=precision, checkpoint_interval=checkpoint_interval,
+                       hbm_budget_bytes=hbm_budget_bytes, device=device, inplace=inplace)
         self._pending = False  # a recorded trajectory is waiting for its backward
         self._generation = 0   # forwards run so far (a backward must belong to the latest)
 

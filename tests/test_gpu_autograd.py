@@ -120,3 +120,29 @@ def test_channel_256x128x128_fd_on_32_nodes():
     err = np.linalg.norm(g[idx] - fd) / np.linalg.norm(fd)
     print("rel-L2", err)
     assert err <= 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_solver_streams_in_place_by_default_bitwise_equal_ping_pong(prec):
+    """The default solver streams in place with the smallest-workspace checkpoint
+    interval (segments recomputed inside their checkpoints); J and dJ/dw equal
+    those of the ping-pong solver at the same interval bitwise."""
+    p = dict(flow=19, scalar=7, nx=40, ny=12, nz=9, tau=0.8, tau_s=0.6, u_in=0.02, switch_fn="ramp",
+             switch_param=0.01, c_dp=0.1, c_var=1.0, s_in_lo=0.0, s_in_hi=1.0, s_split_axis=1)
+    steps = 90
+    dt = np.float32 if prec == "fp32" else np.float64
+    w0 = torch.from_numpy(inputs.porosity(40, 12, 9, 4, 3, dt)).cuda()
+    a = LbmSolver(p, steps, precision=prec)
+    C = a.lbm.plan()["interval"]
+    assert a.lbm.cfg.inplace == 1 and 1 < C < steps
+    b = LbmSolver(p, steps, precision=prec, checkpoint_interval=C, inplace=False)
+    assert b.lbm.cfg.inplace == 0
+    out = []
+    for s in (a, b):
+        w = w0.clone().requires_grad_(True)
+        J = s(w)
+        J.backward()
+        out.append((float(J.detach()), w.grad.detach().cpu().numpy()))
+        s.close()
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1])
