@@ -436,6 +436,21 @@ struct Shifted {
   __host__ __device__ static constexpr int count() { return scalar_slot(QS); }
 };
 
+// Largest block of the single-context hot kernels: a row of up to four waves
+// (nx <= 256) is one block, so that its x-shifts can be staged in LDS.  Rows
+// of up to eight waves as one 512-thread block (staged as well) measured slower
+// on the 450-wide mixing duct: primal 0.789 -> 0.764, in-place one-shot
+// 0.876 -> 0.832 of HBM peak.
+constexpr int kHotThreads = 256;
+
+// Staging runs of the single-context hot kernels, in dynamic LDS sized by the
+// launch (shifted populations x block threads, twice for the one-shot).
+extern __shared__ __align__(16) unsigned char lx_smem[];
+template <typename Real>
+__device__ __forceinline__ Real* lx_lds() {
+  return reinterpret_cast<Real*>(lx_smem);
+}
+
 // Staging layout of the single-context hot kernels (blockDim.y rows of
 // blockDim.x threads): the calling thread's row segment and the run stride.
 __device__ __forceinline__ int lx_seg() { return threadIdx.y * blockDim.x; }
@@ -1030,14 +1045,15 @@ __device__ __forceinline__ void primal_node(const Params<Real>& p, const Real* s
 // LX: the block spans whole rows and the x-shifted populations go through LDS
 // (see load_state_lx); no thread leaves before the barriers.
 template <int Q, int QS, typename Real, bool NT, bool MOM, int V, bool LX = false>
-__global__ __launch_bounds__(256) void k_primal(Params<Real> p, const Real* __restrict__ src,
+__global__ __launch_bounds__(kHotThreads) void k_primal(Params<Real> p, const Real* __restrict__ src,
                                                 Real* __restrict__ dst, const Real* __restrict__ w,
                                                 Real* __restrict__ mom) {
   int x, y, z;
   const bool act = hot_pos(p, x, y, z);
   if constexpr (LX) {
-    __shared__ Real lds[Shifted<Q, QS>::count() * 256];
-    primal_node<Q, QS, Real, NT, MOM, V, ACC_PP, false, true>(p, src, dst, w, mom, x, y, z, lds, lx_seg(), lx_span(), act);
+    Real* lds = lx_lds<Real>();
+    primal_node<Q, QS, Real, NT, MOM, V, ACC_PP, false, true>(p, src, dst, w, mom, x, y, z, lds, lx_seg(), lx_span(),
+                                                              act);
   } else {
     if (!act) return;
     primal_node<Q, QS, Real, NT, MOM, V>(p, src, dst, w, mom, x, y, z);
@@ -1046,13 +1062,13 @@ __global__ __launch_bounds__(256) void k_primal(Params<Real> p, const Real* __re
 
 // One in-place step (even or odd phase); with MOM it also records the moments.
 template <int Q, int QS, typename Real, bool NT, bool MOM, int V, int ACC, bool NTE = false, bool LX = false>
-__global__ __launch_bounds__(256) void k_primal_inplace(Params<Real> p, Real* a, const Real* __restrict__ w,
+__global__ __launch_bounds__(kHotThreads) void k_primal_inplace(Params<Real> p, Real* a, const Real* __restrict__ w,
                                                         Real* __restrict__ mom) {
   int x, y, z;
   const bool act = hot_pos(p, x, y, z);
   if constexpr (LX) {
     static_assert(ACC == ACC_ODD, "only the odd phase has shifted access");
-    __shared__ Real lds[Shifted<Q, QS>::count() * 256];
+    Real* lds = lx_lds<Real>();
     primal_node<Q, QS, Real, NT, MOM, V, ACC, NTE, true>(p, a, a, w, mom, x, y, z, lds, lx_seg(), lx_span(), act);
   } else {
     if (!act) return;
@@ -1644,14 +1660,15 @@ __device__ __forceinline__ void adjoint_node(const Params<Real>& p, const Real* 
 
 // LX as for k_primal.
 template <int Q, int QS, typename Real, bool NT, int V, bool LX = false>
-__global__ __launch_bounds__(256) void k_adjoint(Params<Real> p, const Real* __restrict__ mom,
+__global__ __launch_bounds__(kHotThreads) void k_adjoint(Params<Real> p, const Real* __restrict__ mom,
                                                  const Real* __restrict__ lam_in, Real* __restrict__ lam_out,
                                                  const Real* __restrict__ w, Real* __restrict__ grad) {
   int x, y, z;
   const bool act = hot_pos(p, x, y, z);
   if constexpr (LX) {
-    __shared__ Real lds[Shifted<Q, QS>::count() * 256];
-    adjoint_node<Q, QS, Real, NT, V, ACC_PP, false, true>(p, mom, lam_in, lam_out, w, grad, x, y, z, lds, lx_seg(), lx_span(), act);
+    Real* lds = lx_lds<Real>();
+    adjoint_node<Q, QS, Real, NT, V, ACC_PP, false, true>(p, mom, lam_in, lam_out, w, grad, x, y, z, lds, lx_seg(),
+                                                          lx_span(), act);
   } else {
     if (!act) return;
     adjoint_node<Q, QS, Real, NT, V>(p, mom, lam_in, lam_out, w, grad, x, y, z);
@@ -1660,13 +1677,13 @@ __global__ __launch_bounds__(256) void k_adjoint(Params<Real> p, const Real* __r
 
 // One in-place adjoint step (even or odd pattern of the cotangent buffer l).
 template <int Q, int QS, typename Real, bool NT, int V, int ACC, bool NTE = false, bool LX = false>
-__global__ __launch_bounds__(256) void k_adjoint_inplace(Params<Real> p, const Real* __restrict__ mom, Real* l,
+__global__ __launch_bounds__(kHotThreads) void k_adjoint_inplace(Params<Real> p, const Real* __restrict__ mom, Real* l,
                                                          const Real* __restrict__ w, Real* __restrict__ grad) {
   int x, y, z;
   const bool act = hot_pos(p, x, y, z);
   if constexpr (LX) {
     static_assert(ACC == ACC_ODD, "only the odd pattern has shifted access");
-    __shared__ Real lds[Shifted<Q, QS>::count() * 256];
+    Real* lds = lx_lds<Real>();
     adjoint_node<Q, QS, Real, NT, V, ACC, NTE, true>(p, mom, l, l, w, grad, x, y, z, lds, lx_seg(), lx_span(), act);
   } else {
     if (!act) return;
@@ -1865,7 +1882,7 @@ __device__ __forceinline__ void oneshot_node(const Params<Real>& p, const Real* 
                                              int seg = 0, int bt = 0, bool act = true) {
   constexpr bool is3d = (Q == 19);
   constexpr int QSA = QS > 0 ? QS : 1;
-  constexpr int kRuns = Shifted<Q, QS>::count() * 256;
+  const int kRuns = Shifted<Q, QS>::count() * bt;  // the cotangent's runs follow the primal's
   const Nbr b = make_nbr(p, x, y, z);
   const int n = own_inode(b);  // workspace node arrays
   // padding lanes (LX only) take the wall operators: permutations, no memory access
@@ -1915,7 +1932,7 @@ __device__ __forceinline__ void oneshot_node(const Params<Real>& p, const Real* 
 }
 
 template <int Q, int QS, typename Real, bool NT, int V, bool LX = false>
-__global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __restrict__ prim_in,
+__global__ __launch_bounds__(kHotThreads) void k_oneshot(Params<Real> p, const Real* __restrict__ prim_in,
                                                  Real* __restrict__ prim_out, const Real* __restrict__ lam_in,
                                                  Real* __restrict__ lam_out, Real* __restrict__ w,
                                                  Real* __restrict__ grad, const double* __restrict__ glob, Real zeta,
@@ -1923,7 +1940,7 @@ __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __r
   int x, y, z;
   const bool act = hot_pos(p, x, y, z);
   if constexpr (LX) {
-    __shared__ Real lds[2 * Shifted<Q, QS>::count() * 256];
+    Real* lds = lx_lds<Real>();
     oneshot_node<Q, QS, Real, NT, V, ACC_PP, true>(p, prim_in, prim_out, lam_in, lam_out, w, grad, glob, zeta, c_pen,
                                                    x, y, z, lds, lx_seg(), lx_span(), act);
   } else {
@@ -1936,15 +1953,16 @@ __global__ __launch_bounds__(256) void k_oneshot(Params<Real> p, const Real* __r
 // One in-place one-shot iteration (even or odd phase): a is the primal buffer,
 // l the adjoint buffer, each read and rewritten in place.
 template <int Q, int QS, typename Real, bool NT, int V, int ACC, bool LX = false>
-__global__ __launch_bounds__(256) void k_oneshot_inplace(Params<Real> p, Real* a, Real* l, Real* __restrict__ w,
+__global__ __launch_bounds__(kHotThreads) void k_oneshot_inplace(Params<Real> p, Real* a, Real* l, Real* __restrict__ w,
                                                          Real* __restrict__ grad, const double* __restrict__ glob,
                                                          Real zeta, Real c_pen) {
   int x, y, z;
   const bool act = hot_pos(p, x, y, z);
   if constexpr (LX) {
     static_assert(ACC == ACC_ODD, "only the odd phase has shifted access");
-    __shared__ Real lds[2 * Shifted<Q, QS>::count() * 256];
-    oneshot_node<Q, QS, Real, NT, V, ACC, true>(p, a, a, l, l, w, grad, glob, zeta, c_pen, x, y, z, lds, lx_seg(), lx_span(), act);
+    Real* lds = lx_lds<Real>();
+    oneshot_node<Q, QS, Real, NT, V, ACC, true>(p, a, a, l, l, w, grad, glob, zeta, c_pen, x, y, z, lds, lx_seg(),
+                                                lx_span(), act);
   } else {
     if (!act) return;
     oneshot_node<Q, QS, Real, NT, V, ACC>(p, a, a, l, l, w, grad, glob, zeta, c_pen, x, y, z);

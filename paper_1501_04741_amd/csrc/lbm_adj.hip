@@ -363,18 +363,19 @@ constexpr int kHotWaves = 4;
 // adjoint 0.798 -> 0.807; FP64 and the one-shot unchanged.  The MRT kernels
 // (87-90 registers, five waves per SIMD) lose at the barriers (adjoint 0.80 ->
 // 0.75, primal 0.79 -> 0.77) and keep the plain access.
-bool lx_rows(const lbm_config& c) { return c.nx <= 256 && c.collision != LBM_COLL_MRT; }
+bool lx_rows(const lbm_config& c) { return c.nx <= kHotThreads && c.collision != LBM_COLL_MRT; }
 
-// Launch geometry of the hot kernels: as node_geometry, and when a row is a
-// single block part (nx <= 256), R consecutive rows share a block (blockDim.y =
-// R) so that it holds about the target number of waves.
+// Launch geometry of the hot kernels: a row of up to kHotThreads / 64 waves
+// (nx <= 256) is one block (its x-shifts are then staged in LDS), and when a
+// row is narrower than kHotWaves waves, R consecutive rows share a block
+// (blockDim.y = R) so that it holds about that many; wider rows as
+// node_geometry.
 Geo hot_geometry(const lbm_config& c) {
   Geo g = node_geometry(c);
   const int waves = (c.nx + 63) / 64;
-  const int k = (int)g.block.x / 64;
-  if (k == waves) {
-    const int R = std::max(1, kHotWaves / k);
-    g.block = dim3(64 * k, R, 1);
+  if (waves * 64 <= kHotThreads) {
+    const int R = std::max(1, kHotWaves / waves);
+    g.block = dim3(64 * waves, R, 1);
     g.grid = dim3(1, (c.ny + R - 1) / R, c.nz);
   }
   return g;
@@ -509,6 +510,16 @@ struct Ops {
   // streaming stores (and cotangent loads) when the state buffers a launch touches exceed the
   // last-level cache: ping-pong primal and adjoint 2, in-place primal 1, one-shot 4 (2 in place)
   static bool nt(lbm_ctx* c, int buffers) { return buffers * c->plan.state_bytes > kLastLevelCacheBytes; }
+  // dynamic LDS of an LX launch: the staging runs of `states` states, one value per thread each
+  static size_t lx_bytes(const Geo& g, int states) {
+    return (size_t)states * Shifted<Q, QS>::count() * g.block.x * g.block.y * sizeof(Real);
+  }
+  // LX variant for this context and launch: rows that fit a block, and staging
+  // within 64 KB of LDS per block (the FP64 one-shot of D3Q19 + D3Q7 on 512-wide
+  // blocks would need 96 KB and keeps the plain access)
+  static bool lx(lbm_ctx* c, const Geo& g, int states) {
+    return lx_rows(c->cfg) && lx_bytes(g, states) <= 65536;
+  }
   // access pattern of the current state buffer: ping-pong, or the in-place phase of step t
   static int acc(lbm_ctx* c) { return c->plan.inplace ? ((c->t % 2 == 0) ? ACC_EVEN : ACC_ODD) : ACC_PP; }
   // One in-place step from the current phase; records the moments when mom != null.
@@ -525,12 +536,12 @@ struct Ops {
     const Real* w = (const Real*)c->w;
     Real* m = (Real*)mom;
     const bool even = (t % 2 == 0);
-    const bool lx = lx_rows(c->cfg);
+    const bool lx = Ops::lx(c, g, 1);
 #define LBM_PI(NTV, MOMV, ACCV)                                                                                    \
   do {                                                                                                             \
     if (ACCV == ACC_ODD && lx)                                                                                     \
-      hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACC_ODD, false, true>), g.grid, g.block, 0,  \
-                         c->stream, P(c), a, w, m);                                                                \
+      hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACC_ODD, false, true>), g.grid, g.block,     \
+                         lx_bytes(g, 1), c->stream, P(c), a, w, m);                                                \
     else                                                                                                           \
       hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, NTV, MOMV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), \
                          a, w, m);                                                                                 \
@@ -565,12 +576,12 @@ struct Ops {
     Real* gr = (Real*)c->grad;
     const double* gl = (const double*)c->glob;
     const bool even = (c->t % 2 == 0);
-    const bool lx = lx_rows(c->cfg);
+    const bool lx = Ops::lx(c, g, 2);
 #define LBM_OS_INPLACE(NTV, ACCV)                                                                                 \
   do {                                                                                                            \
     if (ACCV == ACC_ODD && lx)                                                                                    \
-      hipLaunchKernelGGL((k_oneshot_inplace<Q, QS, Real, NTV, V, ACC_ODD, true>), g.grid, g.block, 0, c->stream,   \
-                         P(c), a, l, w, gr, gl, (Real)zeta, (Real)pen);                                           \
+      hipLaunchKernelGGL((k_oneshot_inplace<Q, QS, Real, NTV, V, ACC_ODD, true>), g.grid, g.block, lx_bytes(g, 2),  \
+                         c->stream, P(c), a, l, w, gr, gl, (Real)zeta, (Real)pen);                                \
     else                                                                                                          \
       hipLaunchKernelGGL((k_oneshot_inplace<Q, QS, Real, NTV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), a, l, \
                          w, gr, gl, (Real)zeta, (Real)pen);                                                       \
@@ -603,9 +614,9 @@ struct Ops {
     Real* m = (Real*)mom;
 #define LBM_PP(NTV, MOMV)                                                                                     \
   do {                                                                                                        \
-    if (lx_rows(c->cfg))                                                                                      \
-      hipLaunchKernelGGL((k_primal<Q, QS, Real, NTV, MOMV, V, true>), g.grid, g.block, 0, c->stream, P(c), s, d, w, \
-                         m);                                                                                  \
+    if (Ops::lx(c, g, 1))                                                                                     \
+      hipLaunchKernelGGL((k_primal<Q, QS, Real, NTV, MOMV, V, true>), g.grid, g.block, lx_bytes(g, 1), c->stream,  \
+                         P(c), s, d, w, m);                                                                   \
     else                                                                                                      \
       hipLaunchKernelGGL((k_primal<Q, QS, Real, NTV, MOMV, V>), g.grid, g.block, 0, c->stream, P(c), s, d, w, m); \
   } while (0)
@@ -654,16 +665,16 @@ struct Ops {
     const Real* w = (const Real*)c->w;
     Real* gr = (Real*)c->grad;
     const bool odd = (steps_done % 2 == 0);
-    const bool lx = lx_rows(c->cfg);
+    const bool lx = Ops::lx(c, g, 1);
     const bool far = c->plan.state_bytes > 2 * kLastLevelCacheBytes;  // streaming hints on the staged accesses
 #define LBM_AI(NTV, ACCV)                                                                                         \
   do {                                                                                                            \
     if (ACCV == ACC_ODD && lx && far)                                                                             \
-      hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, NTV, V, ACC_ODD, true, true>), g.grid, g.block, 0,       \
-                         c->stream, P(c), m, l, w, gr);                                                           \
+      hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, NTV, V, ACC_ODD, true, true>), g.grid, g.block,          \
+                         lx_bytes(g, 1), c->stream, P(c), m, l, w, gr);                                           \
     else if (ACCV == ACC_ODD && lx)                                                                               \
-      hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, NTV, V, ACC_ODD, false, true>), g.grid, g.block, 0,      \
-                         c->stream, P(c), m, l, w, gr);                                                           \
+      hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, NTV, V, ACC_ODD, false, true>), g.grid, g.block,         \
+                         lx_bytes(g, 1), c->stream, P(c), m, l, w, gr);                                           \
     else                                                                                                          \
       hipLaunchKernelGGL((k_adjoint_inplace<Q, QS, Real, NTV, V, ACCV>), g.grid, g.block, 0, c->stream, P(c), m, l, \
                          w, gr);                                                                                  \
@@ -684,14 +695,15 @@ struct Ops {
     Geo g = hot_geometry(c->cfg);
     const Real *m = (const Real*)mom, *li = (const Real*)lin, *w = (const Real*)c->w;
     Real *lo = (Real*)lout, *gr = (Real*)c->grad;
-    const bool lx = lx_rows(c->cfg);
+    const bool lx = Ops::lx(c, g, 1);
     if (nt(c, 2) && lx)
-      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true, V, true>), g.grid, g.block, 0, c->stream, P(c), m, li, lo, w, gr);
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true, V, true>), g.grid, g.block, lx_bytes(g, 1), c->stream, P(c), m,
+                         li, lo, w, gr);
     else if (nt(c, 2))
       hipLaunchKernelGGL((k_adjoint<Q, QS, Real, true, V>), g.grid, g.block, 0, c->stream, P(c), m, li, lo, w, gr);
     else if (lx)
-      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false, V, true>), g.grid, g.block, 0, c->stream, P(c), m, li, lo, w,
-                         gr);
+      hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false, V, true>), g.grid, g.block, lx_bytes(g, 1), c->stream, P(c), m,
+                         li, lo, w, gr);
     else
       hipLaunchKernelGGL((k_adjoint<Q, QS, Real, false, V>), g.grid, g.block, 0, c->stream, P(c), m, li, lo, w, gr);
   }
@@ -701,10 +713,10 @@ struct Ops {
     const Real *s = (const Real*)src, *li = (const Real*)lin;
     Real *d = (Real*)dst, *lo = (Real*)lout, *w = (Real*)c->w, *gr = (Real*)c->grad;
     const double* gl = (const double*)c->glob;
-    const bool lx = lx_rows(c->cfg);
+    const bool lx = Ops::lx(c, g, 2);
 #define LBM_OS(NTV, LXV)                                                                                   \
-  hipLaunchKernelGGL((k_oneshot<Q, QS, Real, NTV, V, LXV>), g.grid, g.block, 0, c->stream, P(c), s, d, li, lo, w, gr, \
-                     gl, (Real)zeta, (Real)pen)
+  hipLaunchKernelGGL((k_oneshot<Q, QS, Real, NTV, V, LXV>), g.grid, g.block, LXV ? lx_bytes(g, 2) : 0, c->stream, \
+                     P(c), s, d, li, lo, w, gr, gl, (Real)zeta, (Real)pen)
     if (nt(c, 4)) {
       if (lx) LBM_OS(true, true);
       else LBM_OS(true, false);
