@@ -14,8 +14,16 @@ design field, rounded to FP32 as the GPU run receives it.
              spare): J, the gradient at 8192 interior nodes drawn with
              PCG64(0), and the L2 norm of the full gradient
 
-Usage: python tests/golden/make_oracle_goldens.py {exchanger|mixer|channel} [threads]
-Run time on 8 host cores: about 50 min, 2-3 h and 35 min.
+With "fields" before the case, it stores instead the oracle's macroscopic
+fields after the workload's full forward horizon (no adjoint; for the channel
+the whole 2000 steps): the velocity and the scalar at 16384 nodes drawn with
+PCG64(1) from all nodes, their largest magnitudes over the whole lattice, and
+J.  These pin the FP32 velocity over the full horizon (relative to the largest
+velocity, bar 1e-4).
+
+Usage: python tests/golden/make_oracle_goldens.py [fields] {exchanger|mixer|channel} [threads]
+Run time on 8 host cores: about 50 min, 2-3 h and 35 min; fields about 10,
+15 and 30 min.
 """
 from __future__ import annotations
 
@@ -42,6 +50,33 @@ CASES = {
 
 def golden_path(case: str) -> str:
     return os.path.join(HERE, "oracle_%s.npz" % CASES[case]["workload"])
+
+
+def fields_path(case: str) -> str:
+    return os.path.join(HERE, "oracle_fields_%s.npz" % CASES[case]["workload"])
+
+
+def make_fields(case: str) -> str:
+    """Macroscopic fields of the oracle's forward run over the workload's horizon."""
+    spec = CASES[case]
+    wl = inputs.workload(spec["workload"])
+    p = inputs.model_params(wl)
+    steps = int(wl["steps"])
+    w = inputs.design_for(wl).astype(np.float64)
+    t0 = time.time()
+    r = oracle.primal(p, w, steps)
+    secs = time.time() - t0
+    rho, u, T = oracle.fields(p, r["f"], r["g"])
+    n = rho.size
+    idx = np.sort(np.random.Generator(np.random.PCG64(1)).choice(n, size=16384, replace=False)).astype(np.int64)
+    out = dict(workload=np.array(spec["workload"]), steps=np.int64(steps), J=np.float64(r["J"]), idx=idx,
+               u=u[:, idx], T=T[idx], rho=rho[idx], u_max=np.float64(np.abs(u).max()),
+               T_max=np.float64(np.abs(T).max()), seconds=np.float64(secs), threads=np.int64(oracle.threads()))
+    path = fields_path(case)
+    np.savez_compressed(path, **out)
+    print("fields %s: %s, %d steps, J = %.12g, max|u| = %.6g, %.0f s on %d threads" % (
+        case, spec["workload"], steps, r["J"], out["u_max"], secs, out["threads"]), flush=True)
+    return path
 
 
 def sample_nodes(params: dict, count: int) -> np.ndarray:
@@ -77,7 +112,10 @@ def make(case: str) -> str:
 
 
 if __name__ == "__main__":
-    which = sys.argv[1]
-    if len(sys.argv) > 2:
-        oracle.threads(int(sys.argv[2]))
-    make(which)
+    args = sys.argv[1:]
+    fields = bool(args) and args[0] == "fields"
+    if fields:
+        args = args[1:]
+    if len(args) > 1:
+        oracle.threads(int(args[1]))
+    (make_fields if fields else make)(args[0])

@@ -11,7 +11,11 @@ stored in tests/golden/ by make_oracle_goldens.py, which calls only the oracle:
              checkpointed plan with recompute: J, the gradient at 8192 seeded
              interior nodes and the norm of the full gradient
 
-Bars: |J - J_ref| <= 1e-4 |J_ref|, ||g - g_ref||_2 <= 1e-3 ||g_ref||_2."""
+and, from the oracle's forward over each workload's whole horizon (the
+channel's 2000 steps included), the velocity and scalar at 16384 seeded nodes.
+
+Bars: |J - J_ref| <= 1e-4 |J_ref|, ||g - g_ref||_2 <= 1e-3 ||g_ref||_2,
+max|u - u_ref| <= 1e-4 max|u_ref| (the scalar likewise)."""
 import os
 
 import numpy as np
@@ -83,3 +87,38 @@ def test_channel_256x128x128_fp32_matches_oracle_golden(plan):
     assert abs(J - float(ref["J"])) <= 1e-4 * abs(float(ref["J"]))
     assert err <= 1e-3
     assert norm_err <= 1e-3
+
+
+@pytest.mark.parametrize("name", ["d2q9_d2q5_exchanger_512x256", "d3q19_d3q7_mixer_128x64x64",
+                                  "d3q19_channel_256x128x128"])
+def test_full_horizon_fp32_fields_match_oracle_golden(name):
+    """The FP32 forward over each workload's whole horizon (the channel's full
+    2000 steps), streamed in place as the benchmark streams it, against the
+    oracle's fields at 16384 seeded nodes: velocity and scalar within 1e-4 of
+    their largest magnitude, J within 1e-4."""
+    path = os.path.join(GOLDEN, "oracle_fields_%s.npz" % name)
+    if not os.path.exists(path):
+        pytest.skip("oracle golden %s not generated (tests/golden/make_oracle_goldens.py fields)" %
+                    os.path.basename(path))
+    ref = np.load(path, allow_pickle=False)
+    wl = inputs.workload(name)
+    p = inputs.model_params(wl)
+    N = int(wl["steps"])
+    assert int(ref["steps"]) == N
+    ctx = Lbm(p, nsteps=0, precision="fp32", inplace=True)
+    ctx.set_design(torch.from_numpy(inputs.design_for(wl)))
+    ctx.reset()
+    ctx.primal_steps(N)
+    J, _ = ctx.objective()
+    _, u, s = ctx.fields()
+    idx = torch.from_numpy(ref["idx"]).to(u.device)
+    u_err = float(np.abs(u[:, idx].cpu().numpy() - ref["u"]).max()) / float(ref["u_max"])
+    msg = "%s: J %.10g oracle %.10g, max velocity error %.2e of max|u|" % (name, J, float(ref["J"]), u_err)
+    if p.get("scalar"):
+        T_err = float(np.abs(s[idx].cpu().numpy() - ref["T"]).max()) / float(ref["T_max"])
+        msg += ", scalar %.2e of max|T|" % T_err
+        assert T_err <= 1e-4
+    print(msg)
+    ctx.close()
+    assert u_err <= 1e-4
+    assert abs(J - float(ref["J"])) <= 1e-4 * abs(float(ref["J"]))
