@@ -21,7 +21,10 @@ PCG64(1) from all nodes, their largest magnitudes over the whole lattice, and
 J.  These pin the FP32 velocity over the full horizon (relative to the largest
 velocity, bar 1e-4).
 
-Usage: python tests/golden/make_oracle_goldens.py [fields] {exchanger|mixer|channel} [threads]
+With "serving" it stores J and the gradient (its norm and 4096 sampled interior
+nodes) of the first request of each size in the benchmark's serving trace.
+
+Usage: python tests/golden/make_oracle_goldens.py [fields] {exchanger|mixer|channel|serving} [threads]
 Run time on 8 host cores: about 50 min, 2-3 h and 35 min; fields about 10,
 15 and 30 min.
 """
@@ -79,6 +82,49 @@ def make_fields(case: str) -> str:
     return path
 
 
+def serving_path() -> str:
+    return os.path.join(HERE, "oracle_serving_requests.npz")
+
+
+# Horizon of the serving golden per request size: the trace's 2000 steps, but
+# 200 for D3Q19 192x96x96, whose 2000-step oracle adjoint would take hours.
+SERVING_STEPS = (2000, 2000, 2000, 200)
+
+
+def serving_requests():
+    """The first request of each size in the benchmark's 400-request trace
+    (Poisson 20/s, seed 1), with the horizon the golden holds for it."""
+    trace = inputs.poisson_trace(400, 20.0, seed=1)
+    out = []
+    for kind, size in enumerate(inputs.SERVE_SIZES):
+        req = next(r for r in trace if (r.params["flow"], r.params["nx"]) == (size["flow"], size["nx"]))
+        out.append((kind, req, SERVING_STEPS[kind]))
+    return out
+
+
+def make_serving() -> str:
+    """J and dJ/dw of the oracle for one request of each serving size: the
+    gradient's norm and its values at 4096 interior nodes drawn with PCG64(0)."""
+    rows = dict(rid=[], kind=[], steps=[], J=[], grad_norm=[], sample_idx=[], grad_sample=[], seconds=[])
+    for kind, req, steps in serving_requests():
+        p = req.params
+        w = inputs.request_design(req).astype(np.float64)  # the FP32 field the GPU receives
+        t0 = time.time()
+        r = oracle.adjoint(p, w, steps)
+        secs = time.time() - t0
+        idx = sample_nodes(p, 4096)
+        for k, v in (("rid", req.rid), ("kind", kind), ("steps", steps), ("J", r["J"]),
+                     ("grad_norm", np.linalg.norm(r["grad"])), ("sample_idx", idx), ("grad_sample", r["grad"][idx]),
+                     ("seconds", secs)):
+            rows[k].append(v)
+        print("serving request %d (size %d, %s %dx%dx%d): %d steps, J = %.12g, %.0f s" % (
+            req.rid, kind, "D3Q19" if p["flow"] == 19 else "D2Q9", p["nx"], p["ny"], p["nz"], steps, r["J"], secs),
+            flush=True)
+    path = serving_path()
+    np.savez_compressed(path, threads=np.int64(oracle.threads()), **{k: np.array(v) for k, v in rows.items()})
+    return path
+
+
 def sample_nodes(params: dict, count: int) -> np.ndarray:
     """Sorted indices of `count` distinct interior nodes, drawn with PCG64(0)."""
     interior = np.flatnonzero(oracle.mask(params) == 0)
@@ -118,4 +164,7 @@ if __name__ == "__main__":
         args = args[1:]
     if len(args) > 1:
         oracle.threads(int(args[1]))
-    (make_fields if fields else make)(args[0])
+    if args[0] == "serving":
+        make_serving()
+    else:
+        (make_fields if fields else make)(args[0])

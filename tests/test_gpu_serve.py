@@ -312,3 +312,36 @@ def test_cancelled_requests_free_their_memory_and_leave_the_rest_exact():
         assert j.state == DONE, (j.rid, j.state, j.error)
         J, g = _alone(j.params, j.design, j.steps, j.precision, interval=j.steps)
         assert j.J == J and np.array_equal(j.grad, g), j.rid
+
+
+def test_served_requests_at_full_size_match_oracle_golden():
+    """One request of each serving size (the first of its size in the benchmark's
+    400-request trace, seed 1), served together in FP32 at its real size and
+    horizon (2000 + 2000 steps; 200 + 200 for D3Q19 192x96x96), against the
+    oracle's J and gradient stored by tests/golden/make_oracle_goldens.py:
+    J within 1e-4, the gradient at 4096 seeded interior nodes within 1e-3
+    relative L2 and its norm within 1e-3."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_serving_requests.npz")
+    if not os.path.exists(path):
+        pytest.skip("oracle golden oracle_serving_requests.npz not generated")
+    ref = np.load(path, allow_pickle=False)
+    trace = inputs.poisson_trace(400, 20.0, seed=1)
+    jobs = []
+    for i in range(len(ref["rid"])):
+        req = trace[int(ref["rid"][i])]
+        jobs.append(Job(rid=req.rid, params=req.params, steps=int(ref["steps"][i]),
+                        design=inputs.request_design(req), precision="fp32", arrival=0.0))
+    srv = Server(GpuExecutor(), hbm_budget_bytes=200 << 30, quantum=50)
+    srv.replay(jobs, realtime=False)
+    for i, j in enumerate(jobs):
+        assert j.state == DONE, (j.rid, j.state, j.error)
+        Jr = float(ref["J"][i])
+        idx = ref["sample_idx"][i]
+        gs = ref["grad_sample"][i]
+        err = np.linalg.norm(j.grad[idx] - gs) / np.linalg.norm(gs)
+        nerr = abs(np.linalg.norm(j.grad) / float(ref["grad_norm"][i]) - 1)
+        print("request %d (%s): J %.10g oracle %.10g, sampled gradient rel-L2 %.2e, norm %.2e" % (
+            j.rid, "x".join(str(j.params[k]) for k in ("nx", "ny", "nz")), j.J, Jr, err, nerr))
+        assert abs(j.J - Jr) <= 1e-4 * abs(Jr)
+        assert err <= 1e-3 and nerr <= 1e-3
