@@ -24,7 +24,11 @@ velocity, bar 1e-4).
 With "serving" it stores J and the gradient (its norm and 4096 sampled interior
 nodes) of the first request of each size in the benchmark's serving trace.
 
-Usage: python tests/golden/make_oracle_goldens.py [fields] {exchanger|mixer|channel|serving} [threads]
+With "directional" it stores J and the complex-step directional derivative
+dJ/dw . v of the benchmark channel over its full 2000 steps (v: standard normal
+values from PCG64(2)).
+
+Usage: python tests/golden/make_oracle_goldens.py [fields] {exchanger|mixer|channel|serving|directional} [threads]
 Run time on 8 host cores: about 50 min, 2-3 h and 35 min; fields about 10,
 15 and 30 min.
 """
@@ -79,6 +83,35 @@ def make_fields(case: str) -> str:
     np.savez_compressed(path, **out)
     print("fields %s: %s, %d steps, J = %.12g, max|u| = %.6g, %.0f s on %d threads" % (
         case, spec["workload"], steps, r["J"], out["u_max"], secs, out["threads"]), flush=True)
+    return path
+
+
+def directional_path() -> str:
+    return os.path.join(HERE, "oracle_directional_d3q19_channel_256x128x128.npz")
+
+
+def direction(n: int) -> np.ndarray:
+    """The seeded direction of the whole-horizon directional derivative."""
+    return np.random.Generator(np.random.PCG64(2)).standard_normal(n)
+
+
+def make_directional() -> str:
+    """J and dJ/dw . v of the benchmark channel over its full 2000 steps, by complex
+    step through the whole run (exact up to rounding), for the seeded direction v:
+    the gradient's projection at the horizon the adjoint golden cannot reach."""
+    wl = inputs.workload("d3q19_channel_256x128x128")
+    p = inputs.model_params(wl)
+    steps = int(wl["steps"])
+    w = inputs.design_for(wl).astype(np.float64)
+    v = direction(w.size)
+    t0 = time.time()
+    J, dJ = oracle.directional(p, w, v, steps)
+    secs = time.time() - t0
+    path = directional_path()
+    np.savez_compressed(path, workload=np.array("d3q19_channel_256x128x128"), steps=np.int64(steps), J=np.float64(J),
+                        dJ_v=np.float64(dJ), direction_seed=np.int64(2), seconds=np.float64(secs),
+                        threads=np.int64(oracle.threads()))
+    print("directional: %d steps, J = %.12g, dJ.v = %.12g, %.0f s" % (steps, J, dJ, secs), flush=True)
     return path
 
 
@@ -166,5 +199,7 @@ if __name__ == "__main__":
         oracle.threads(int(args[1]))
     if args[0] == "serving":
         make_serving()
+    elif args[0] == "directional":
+        make_directional()
     else:
         (make_fields if fields else make)(args[0])
