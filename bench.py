@@ -681,11 +681,11 @@ def main(argv=None):
                     help="workspace cap per served request: every step's moments are held (no recompute) "
                          "when they fit, else the largest checkpoint interval that does")
     ap.add_argument("--quantum", type=int, default=50, help="steps per request per scheduling tick")
-    ap.add_argument("--quantum-ms", type=float, default=5.0,
+    ap.add_argument("--quantum-ms", type=float, default=10.0,
                     help="device time per cost class per tick (0 = fixed --quantum steps)")
     ap.add_argument("--no-baseline", action="store_true", help="skip the one-at-a-time replay")
     ap.add_argument("--policy", default="sjf", choices=["sjf", "fifo"])
-    ap.add_argument("--max-active-gb", type=float, default=0.4,
+    ap.add_argument("--max-active-gb", type=float, default=0.3,
                     help="cap on the summed state size of admitted requests (0 = none)")
     args = ap.parse_args(argv)
     if args.serve and args.gpus == 1:
