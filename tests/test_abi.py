@@ -145,3 +145,17 @@ def test_inplace_workspace_holds_two_states(lib):
     assert abs(b - (inpl + S * state + best * mom)) < 4 * 2 ** 20
     with pytest.raises(lbm.LbmError):   # not even the smallest plan fits
         lbm.lbm_required_bytes(lbm.make_config(p, 100, hbm_budget_bytes=inpl + mom, inplace=True))
+
+
+def test_solver_default_interval_minimises_the_in_place_workspace(lib):
+    """LbmSolver's default in-place plan: the checkpoint interval with the smallest
+    workspace, which is below the ping-pong default's on the benchmark channel."""
+    from paper_1501_04741_amd import inputs
+    from paper_1501_04741_amd.autograd import smallest_inplace_interval
+    from paper_1501_04741_amd.lbm import lbm_required_bytes, make_config
+    p = inputs.model_params(inputs.workload("d3q19_channel_256x128x128"))
+    C = smallest_inplace_interval(p, 2000, "fp32")
+    size = lambda c: lbm_required_bytes(make_config(p, 2000, "fp32", checkpoint_interval=c, inplace=True))
+    assert 1 < C < 2000
+    assert all(size(C) <= size(c) for c in (1, C // 2, C - 1, C + 1, 2 * C, 2000))
+    assert size(C) < lbm_required_bytes(make_config(p, 2000, "fp32"))

@@ -34,3 +34,24 @@ def test_cpu_baseline_reports_every_sample():
     assert r["kind"] == "oracle" and r["unit"] == "MLUPS" and r["cores"] >= 1
     assert [s["workload"] for s in r["samples"]] == [s[0] for s in samples]
     assert r["value"] == r["samples"][1]["mlups"] > 0
+
+
+def test_kernel_labels_tell_every_profiled_variant_apart():
+    """The counter-traffic keys: one label per kernel variant the bench reports."""
+    base = dict(flow=19, scalar=0)
+    labels = {
+        bench.klabel("k_primal_inplace", base, "fp32", "recorded"),
+        bench.klabel("k_primal_inplace", base, "fp32", "unrecorded"),
+        bench.klabel("k_primal_inplace", dict(base, collision="mrt"), "fp32", "recorded"),
+        bench.klabel("k_primal_inplace", base, "fp64", "recorded"),
+        bench.klabel("k_primal", base, "fp32", "recorded"),
+        bench.klabel("k_primal_batch", base, "fp32", "in place,recorded"),
+        bench.klabel("k_primal_batch", base, "fp32", "ping-pong,recorded"),
+        bench.klabel("k_primal_inplace", dict(flow=19, scalar=7), "fp32", "recorded"),
+    }
+    assert len(labels) == 8
+    assert bench.klabel("k_adjoint_inplace", base, "fp32") == "k_adjoint_inplace<19,0,float>"
+    for wl, kernels in bench.COUNTER_TRAFFIC["bytes_per_launch"].items():
+        for k in kernels:
+            assert k.split("<")[0] in ("k_primal", "k_primal_inplace", "k_adjoint", "k_adjoint_inplace",
+                                       "k_oneshot", "k_oneshot_inplace", "k_primal_batch", "k_adjoint_batch")
