@@ -435,15 +435,17 @@ int batch_nt(lbm_ctx* const* cs, int n) {
 
 // The same for an in-place launch (one buffer per member, read and rewritten),
 // with the single-context rule: recorded and adjoint steps stream once the
-// buffers exceed the cache, unrecorded steps only beyond twice the cache; the
-// even phase's loads take the hint too beyond twice the cache (8 x 128x96x96
-// D3Q19 FP32 recorded, 0.72 GB together: primal 0.64, adjoint 0.66 of HBM peak
-// without it).
-void batch_nt_inplace(lbm_ctx* const* cs, int n, bool unrecorded, int* nt, int* nte) {
+// buffers exceed the cache; unrecorded steps stream in the odd phase only
+// between one and two caches (4 x 128x96x96 D3Q19 FP32, 0.36 GB together: 0.69 ->
+// 0.80 of HBM peak; 5 x: 0.67 -> 0.74) and in both phases beyond; the even
+// phase's loads take the hint too beyond twice the cache (8 x 128x96x96 recorded,
+// 0.72 GB together: primal 0.64, adjoint 0.66 of HBM peak without it).
+void batch_nt_inplace(lbm_ctx* const* cs, int n, bool unrecorded, bool odd, int* nt, int* nte) {
   uint64_t bytes = 0;
   for (int k = 0; k < n; ++k) bytes += cs[k]->plan.state_bytes;
   const bool far = bytes > 2 * kLastLevelCacheBytes;
-  *nt = (unrecorded ? far : bytes > kLastLevelCacheBytes) ? 1 : 0;
+  const bool over = bytes > kLastLevelCacheBytes;
+  *nt = (unrecorded ? far || (odd && over) : over) ? 1 : 0;
   *nte = far ? 1 : 0;
 }
 
@@ -526,10 +528,13 @@ struct Ops {
   // Streaming stores and hints: a recorded step takes them once its state exceeds
   // the last-level cache (plain stores: 0.819 -> 0.748 of peak, D3Q19 FP32
   // 256x128x128), its even phase's loads only beyond twice the cache.  An
-  // unrecorded step stores plainly up to twice the cache (NT stores without load
-  // hints: 0.766 -> 0.741 at 256x128x128) and beyond it takes NT stores and hinted
-  // loads in both phases (0.662 -> 0.750 at 512x256x128, 0.668 -> 0.815 at
-  // 512x128x128; ping-pong 0.753 and 0.766).
+  // unrecorded step stores plainly up to the cache size (NT stores in the odd
+  // phase cost 0.76 -> 0.73 at 128x96x96 and 0.88 -> 0.86 at 192x128x128); between
+  // one and two caches its odd (staged) phase takes NT stores and the even phase
+  // stays plain (0.787 -> 0.860 at 256x128x128; NT stores in both phases 0.741,
+  // with the even-phase load hint 0.839); beyond twice the cache it takes NT
+  // stores and hinted loads in both phases (0.662 -> 0.750 at 512x256x128, 0.668 ->
+  // 0.815 at 512x128x128; a plain even phase there 0.66 and 0.67).
   static void primal_inplace(lbm_ctx* c, void* buf, int64_t t, void* mom) {
     Geo g = hot_geometry(c->cfg);
     Real* a = (Real*)buf;
@@ -561,6 +566,10 @@ struct Ops {
       if (even)
         hipLaunchKernelGGL((k_primal_inplace<Q, QS, Real, true, false, V, ACC_EVEN, true>), g.grid, g.block, 0,
                            c->stream, P(c), a, w, m);
+      else LBM_PI(true, false, ACC_ODD);
+    } else if (nt(c, 1)) {
+      // unrecorded, state between one and two caches: streaming stores in the odd phase only
+      if (even) LBM_PI(false, false, ACC_EVEN);
       else LBM_PI(true, false, ACC_ODD);
     } else {
       if (even) LBM_PI(false, false, ACC_EVEN);
@@ -1087,7 +1096,7 @@ struct RunPrimalBatch {
         A.kw = batch_block_waves(mem, nm);
         A.rpb = batch_rows_per_block(mem, nm, A.kw);
         A.lx = batch_lx(mem, nm, A.kw);
-        batch_nt_inplace(mem, nm, !record, &A.nt, &A.nte);
+        batch_nt_inplace(mem, nm, !record, phase == 1, &A.nt, &A.nte);
         int total = 0;
         for (int k = 0; k < nm; ++k) {
           lbm_ctx* c = mem[k];
@@ -1171,7 +1180,7 @@ struct RunAdjointBatch {
         A.kw = batch_block_waves(mem, nm);
         A.rpb = batch_rows_per_block(mem, nm, A.kw);
         A.lx = batch_lx(mem, nm, A.kw);
-        batch_nt_inplace(mem, nm, false, &A.nt, &A.nte);
+        batch_nt_inplace(mem, nm, false, false, &A.nt, &A.nte);
         A.nt = 1;  // the adjoint streams whatever the state size (see Ops::adjoint_inplace)
         int total = 0;
         for (int k = 0; k < nm; ++k) {
