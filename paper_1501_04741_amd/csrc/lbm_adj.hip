@@ -804,6 +804,8 @@ lbm_status dispatch(lbm_ctx* c, A&&... a) {
 void* ckpt_slot(lbm_ctx* c, int64_t s) { return c->ckpt + (uint64_t)s * c->plan.state_bytes; }
 // Moment set of step k (slot k mod C).
 void* mom_slot(lbm_ctx* c, int64_t k) { return c->mom + (uint64_t)(k % c->plan.C) * c->plan.mom_bytes; }
+// Trajectory segment holding the horizon's last step (0 in a store-all plan).
+int64_t last_segment(lbm_ctx* c) { return c->cfg.nsteps > 0 ? (c->cfg.nsteps - 1) / c->plan.C : 0; }
 void* other_pp(lbm_ctx* c, const void* cur) { return (cur == c->pp[0]) ? c->pp[1] : c->pp[0]; }
 
 // Destination of h^k while recording: a checkpoint slot or a ping-pong buffer.
@@ -833,12 +835,16 @@ bool window_complete(const lbm_ctx* c) {
 template <class O>
 struct RunPrimal {
   static lbm_status run(lbm_ctx* c, int64_t nsteps, int record) {
+    // A recorded run keeps the moments of the horizon's last segment only (all of
+    // them in a store-all plan): the backward recomputes every earlier segment
+    // from its checkpoint before it reads that segment's moments.
+    const int64_t keep_from = last_segment(c) * c->plan.C;
     if (c->plan.inplace) {
       const bool ckpts = record && c->work != ckpt_slot(c, 0);  // checkpointed plan (C < N)
       for (int64_t i = 0; i < nsteps; ++i) {
         if (ckpts && c->t % c->plan.C == 0)  // the state at t = sC, in its phase's layout
           O::copy(c, c->work, ckpt_slot(c, c->t / c->plan.C), (size_t)c->plan.QT * c->plan.Np);
-        O::primal_inplace(c, c->work, c->t, record ? mom_slot(c, c->t) : nullptr);
+        O::primal_inplace(c, c->work, c->t, record && c->t >= keep_from ? mom_slot(c, c->t) : nullptr);
         ++c->t;
         capture_window<O>(c);
       }
@@ -847,7 +853,7 @@ struct RunPrimal {
     for (int64_t i = 0; i < nsteps; ++i) {
       void* src = c->cur;
       void* dst = record ? rec_dst(c, c->t) : other_pp(c, c->cur);
-      O::primal(c, src, dst, record ? mom_slot(c, c->t) : nullptr);
+      O::primal(c, src, dst, record && c->t >= keep_from ? mom_slot(c, c->t) : nullptr);
       c->cur = dst;
       ++c->t;
       capture_window<O>(c);
@@ -909,7 +915,11 @@ void start_adjoint(lbm_ctx* c) {
   O::fill(c, c->grad, (size_t)c->plan.Np);
   c->lam_cur = 0;
   c->t_adj = c->rec_len;
-  c->mom_seg = c->rec_len > 0 ? (c->rec_len - 1) / C : -1;
+  // the recorded run's moments are held when it ended in the horizon's last segment
+  // (a batched run records every step, so this can miss a segment it holds: that
+  // segment is then recomputed, with the same result)
+  const int64_t s = c->rec_len > 0 ? (c->rec_len - 1) / C : -1;
+  c->mom_seg = s == last_segment(c) ? s : -1;
   c->adj_started = true;
 }
 

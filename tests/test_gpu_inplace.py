@@ -296,3 +296,44 @@ def test_inplace_checkpointed_run_bitwise_equal_pingpong(name, p, C):
     if prec == "fp64" and name != "d3q19_d3q7_mrt_pressure_mix":  # its 23-step gradient is ~1e-8: rounding-level
         ref = oracle.adjoint(p, w.numpy(), steps)
         assert np.linalg.norm(g - ref["grad"]) <= 1e-10 * np.linalg.norm(ref["grad"])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("name,p", [CASES[1], CASES[3]], ids=[CASES[1][0], CASES[3][0]])
+def test_checkpointed_run_ending_before_the_last_segment(name, p, prec):
+    """A checkpointed forward keeps the moments of the horizon's last segment only.
+    A recorded run that stops earlier (13 of 23 steps, a checkpoint every 4, so
+    inside segment 3 of 6) therefore holds none: the backward recomputes that
+    segment as well.  J, the adjoint state after each chunk and the gradient
+    bitwise equal to the store-all plan stopped at the same step, ping-pong and
+    in place, and (FP64) within 1e-10 of the oracle's 13-step run."""
+    steps, stop = 23, 13
+    dt = np.float32 if prec == "fp32" else np.float64
+    w = torch.from_numpy(inputs.porosity(p["nx"], p["ny"], p["nz"], 8, 3, dt))
+    xs = [Lbm(p, nsteps=steps, precision=prec, checkpoint_interval=4),
+          Lbm(p, nsteps=steps, precision=prec, checkpoint_interval=4, inplace=True),
+          Lbm(p, nsteps=steps, precision=prec, inplace=True),
+          Lbm(p, nsteps=steps, precision=prec, checkpoint_interval=steps)]
+    assert [x.plan()["interval"] for x in xs] == [4, 4, steps, steps]
+    for x in xs:
+        x.set_design(w)
+        x.reset()
+        x.primal_steps(5, record=True)
+        x.primal_steps(stop - 5, record=True)
+    J = xs[0].objective()
+    assert all(x.objective() == J for x in xs[1:])
+    for k in (2, 6, 5):
+        for x in xs:
+            x.adjoint_steps(k)
+        la = _np(xs[0].get_adjoint()[0])
+        for x in xs[1:]:
+            assert np.array_equal(la, _np(x.get_adjoint()[0]))
+    g = _np(xs[0].gradient())
+    for x in xs[1:]:
+        assert np.array_equal(g, _np(x.gradient()))
+    if prec == "fp64" and name != "d3q19_d3q7_mrt_pressure_mix":
+        ref = oracle.adjoint(p, w.numpy(), stop)
+        assert abs(J[0] - ref["J"]) <= 1e-10 * abs(ref["J"])
+        assert np.linalg.norm(g - ref["grad"]) <= 1e-10 * np.linalg.norm(ref["grad"])
+    for x in xs:
+        x.close()
