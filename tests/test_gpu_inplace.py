@@ -236,6 +236,54 @@ def test_inplace_streaming_hint_variants_bitwise_equal_pingpong_fp64_256x128x128
     b.close()
 
 
+
+def test_unrecorded_inplace_between_one_and_two_caches_bitwise_equal_pingpong():
+    """Unrecorded in-place steps on states between one and two last-level caches
+    take streaming stores in the odd phase only: the benchmark channel in FP32
+    (319 MB) alone, and four 128x96x96 channels (0.36 GB together) in one batched
+    launch per phase, against the ping-pong path and the single-context kernels,
+    bitwise, after chunks ending in both phases."""
+    wl = inputs.workload("d3q19_channel_256x128x128")
+    p = inputs.model_params(wl)
+    w = torch.from_numpy(inputs.design_for(wl, np.float32)).cuda()
+    a = Lbm(p, nsteps=0, precision="fp32")
+    b = Lbm(p, nsteps=0, precision="fp32", inplace=True)
+    assert 256 * 2**20 < b.plan()["state_bytes"] <= 2 * 256 * 2**20
+    for c in (a, b):
+        c.set_design(w)
+        c.reset()
+    for k in (3, 2):
+        a.primal_steps(k)
+        b.primal_steps(k)
+        fa, _ = a.get_state()
+        fb, _ = b.get_state()
+        assert torch.equal(fa, fb)
+        del fa, fb
+    assert a.objective() == b.objective()
+    a.close()
+    b.close()
+    q = dict(p, nx=128, ny=96, nz=96)
+    ws = [torch.from_numpy(inputs.porosity(128, 96, 96, 40 + k, 5, np.float32)).cuda() for k in range(4)]
+    single = [Lbm(q, nsteps=0, precision="fp32", inplace=True) for _ in range(4)]
+    batch = [Lbm(q, nsteps=0, precision="fp32", inplace=True) for _ in range(4)]
+    total = sum(c.plan()["state_bytes"] for c in batch)
+    assert 256 * 2**20 < total <= 2 * 256 * 2**20
+    for x, y, wk in zip(single, batch, ws):
+        for c in (x, y):
+            c.set_design(wk)
+            c.reset()
+    for k in (3, 2):
+        for x in single:
+            x.primal_steps(k)
+        L.lbm_primal_steps_batch([c.ctx for c in batch], k, record=False)
+        for x, y in zip(single, batch):
+            fx, _ = x.get_state()
+            fy, _ = y.get_state()
+            assert torch.equal(fx, fy)
+            del fx, fy
+    for c in single + batch:
+        c.close()
+
 def test_set_design_after_adjoint_refuses_state_reads_until_reset():
     """Once an adjoint has run (and recomputed segments have overwritten the
     primal buffers), a new design invalidates the primal state: calls that read it
